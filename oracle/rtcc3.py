@@ -1,0 +1,581 @@
+"""Oracle: a plain, slow, complex128 CPU implementation of real-time CC3.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module;
+only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+it.  It shares no code with the HIP implementation.
+
+What it computes (arXiv 2407.18947, Sec. 2.1 and Appendix A):
+
+* the perturbed Hamiltonian H(t) = F + U - mu.E(t) (Sec. 2.1, eq. cc3-h-pert;
+  dipole coupling of Sec. 2.2.1), in the canonical orbital basis with
+  (pq|rs) = sum_P B[P,p,q] B[P,r,s];
+* the T1 transformation O = exp(-T1) O exp(T1) (Sec. 2.1, Appendix A);
+* the right-hand sides of the amplitude equations, i dt/dt = <mu|Hbar|0>
+  (eq. cc3-rt-t) and -i dlambda/dt = dL/dt (eq. cc3-rt-l, obtained from the
+  Euler-Lagrange equations of the CC3 Lagrangian in Appendix A):
+    - singles/doubles CCSD parts: closed-shell T1-transformed CCSD (the
+      paper uses the existing CCSD equations and does not print them);
+      the Lambda side is the derivative of the Lagrangian, taken by
+      automatic differentiation, which is the Euler-Lagrange equation itself;
+    - triples: t3 from the closed form of eq. cc3-t3-no-pert, lambda3 from
+      eq. cc3-l3 in its spin-adapted form (eq. cc3-l3-exp), and their
+      contributions X1 (eq. cc3-x1-exp), X2 (eq. cc3-x2-exp), Y1
+      (eq. cc3-y1-exp) and Y2 (eq. cc3-y2-exp), evaluated for one occupied
+      triple (i,j,k) at a time (Sec. 2.1) or, for tiny systems, with the full
+      six-index tensors;
+* the one-electron density (CCSD part plus the triples terms of eq. cc3-dij
+  and the following two equations) and the dipole Tr(D mu) (Sec. 2.2.3);
+* classic RK4 propagation (Sec. 3).
+
+Readings of places where the paper is silent or garbled are listed with the
+code that takes them (search for "Reading").
+
+Layouts: t1[i,a], t2[i,j,a,b] = t_ij^ab, l1[i,a] = lambda_a^i,
+l2[i,j,a,b] = lambda_ab^ij, t3[i,j,k,a,b,c] = t_ijk^abc.  Integrals are
+Mulliken (pq|rs); the paper's physicist <pq|rs> equals (pr|qs).
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import torch
+
+R64 = torch.float64
+C128 = torch.complex128
+
+# Reading: pairing of the Lagrangian.  The Lagrangian used is
+#   L = E + sum_ia l1_ia Omega_ia + C2 * sum_ijab l2_ijab Omega_ijab
+# over all tensor elements.  Its value is fixed by requiring the paper's
+# printed triples equations (lambda3, Y1, Y2, density) to be its derivatives;
+# the tests pin it (test_oracle_lagrangian.py).
+C2 = 0.5
+
+
+def _t(x, dtype=C128):
+    return torch.as_tensor(np.asarray(x), dtype=dtype)
+
+
+class Model:
+    """Bare (field-free) integrals and dipole matrices of one system."""
+
+    def __init__(self, o, v, eps, B, mu):
+        self.o, self.v = int(o), int(v)
+        self.n = self.o + self.v
+        self.eps = _t(eps, R64)
+        self.B = _t(B, R64)
+        self.mu = _t(mu, R64)
+        o = self.o
+        # Bare one-electron operator h0 such that the Fock matrix built from it
+        # with the closed-shell reference is diag(eps):
+        #   f_pq = h_pq + sum_i [2 (pq|ii) - (pi|iq)]   (normal-ordered H, App. A)
+        Bd = torch.einsum("Pii->P", self.B[:, :o, :o])
+        J = torch.einsum("Ppq,P->pq", self.B, Bd)
+        K = torch.einsum("Ppi,Piq->pq", self.B[:, :, :o], self.B[:, :o, :])
+        self.h0 = torch.diag(self.eps) - (2.0 * J - K)
+        eo, ev = self.eps[:o], self.eps[o:]
+        self.d3 = (eo[:, None, None, None, None, None] + eo[None, :, None, None, None, None]
+                   + eo[None, None, :, None, None, None] - ev[None, None, None, :, None, None]
+                   - ev[None, None, None, None, :, None] - ev[None, None, None, None, None, :])
+
+    @classmethod
+    def from_system(cls, s):
+        return cls(s.o, s.v, s.eps, s.B, s.mu)
+
+    def h(self, E):
+        """One-electron operator with the dipole coupling V = -mu.E (Sec. 2.2.1)."""
+        E = torch.as_tensor(np.asarray(E, dtype=np.float64))
+        return self.h0 - torch.einsum("x,xpq->pq", E, self.mu)
+
+    def denom3(self, i, j, k):
+        """D_ijk^abc = e_i + e_j + e_k - e_a - e_b - e_c = -epsilon_mu3 (App. A)."""
+        o = self.o
+        eo, ev = self.eps[:o], self.eps[o:]
+        return (eo[i] + eo[j] + eo[k]) - ev[:, None, None] - ev[None, :, None] - ev[None, None, :]
+
+
+# -----------------------------------------------------------------------------
+# T1 transformation (Sec. 2.1; Appendix A)
+# -----------------------------------------------------------------------------
+
+class Dressed:
+    """T1-transformed one-electron operator, DF factors and Fock matrix.
+
+    exp(-T1) a+_i exp(T1) = a+_i - sum_a t_i^a a+_a and
+    exp(-T1) a_a exp(T1) = a_a + sum_i t_i^a a_i, so every one-index object
+    x_pq transforms as (1 - T) x (1 + T), where T[a,i] = t_i^a is the only
+    non-zero block of the n x n matrix T.
+    """
+
+    def __init__(self, m: Model, t1, h):
+        o, n = m.o, m.n
+        Tm = torch.zeros((n, n), dtype=C128)
+        Tm = Tm.index_put((torch.arange(o, n)[:, None], torch.arange(o)[None, :]), t1.transpose(0, 1))
+        eye = torch.eye(n, dtype=C128)
+        self.X = eye - Tm
+        self.Y = eye + Tm
+        self.o = o
+        self.h = self.X @ h.to(C128) @ self.Y
+        self.B = torch.einsum("pr,Prs,sq->Ppq", self.X, m.B.to(C128), self.Y)
+        Bd = torch.einsum("Pkk->P", self.B[:, :o, :o])
+        J = torch.einsum("Ppq,P->pq", self.B, Bd)
+        K = torch.einsum("Ppk,Pkq->pq", self.B[:, :, :o], self.B[:, :o, :])
+        self.F = self.h + 2.0 * J - K
+
+    def g(self, s: str):
+        """Dressed Mulliken block (pq|rs)~ for an index-space string like 'ovov'."""
+        o = self.o
+        sl = {"o": slice(0, o), "v": slice(o, None)}
+        p, q, r, t = (sl[c] for c in s)
+        return torch.einsum("Ppq,Prs->pqrs", self.B[:, p, q], self.B[:, r, t])
+
+    def transform(self, x):
+        return self.X @ x.to(C128) @ self.Y
+
+
+# -----------------------------------------------------------------------------
+# CCSD parts: closed-shell T1-transformed CCSD (standard theory; the paper's
+# "existing CCSD equations", Sec. 2.1).  Omega = expansion coefficients of
+# exp(-T2) H exp(T2)|0> in {E_ai|0>, 1/2 E_ai E_bj|0>} (pinned in the tests
+# against a determinant-space construction).
+# -----------------------------------------------------------------------------
+
+def _perm_ijab(x):
+    """P_ij^ab x = x_ij^ab + x_ji^ba (eq. cc3-pijab)."""
+    return x + x.permute(1, 0, 3, 2)
+
+
+def ccsd_energy(d: Dressed, t2):
+    o = d.o
+    gov = d.g("ovov")
+    L = 2.0 * gov - gov.permute(0, 3, 2, 1)
+    e_ref = torch.einsum("ii->", d.h[:o, :o]) + torch.einsum("ii->", d.F[:o, :o])
+    return e_ref + torch.einsum("ijab,iajb->", t2, L)
+
+
+def ccsd_omega(d: Dressed, t2):
+    o = d.o
+    F = d.F
+    Foo, Fov, Fvo, Fvv = F[:o, :o], F[:o, o:], F[o:, :o], F[o:, o:]
+    u = 2.0 * t2 - t2.permute(0, 1, 3, 2)
+    g_ovov = d.g("ovov")
+    L_ovov = 2.0 * g_ovov - g_ovov.permute(0, 3, 2, 1)
+    # singles
+    r1 = (torch.einsum("kicd,adkc->ia", u, d.g("vvov"))
+          - torch.einsum("klac,kilc->ia", u, d.g("ooov"))
+          + torch.einsum("ikac,kc->ia", u, Fov)
+          + Fvo.transpose(0, 1))
+    # doubles
+    A2 = d.g("vovo").permute(1, 3, 0, 2) + torch.einsum("ijcd,acbd->ijab", t2, d.g("vvvv"))
+    Xkl = d.g("oooo").permute(0, 2, 1, 3) + torch.einsum("ijcd,kcld->klij", t2, g_ovov)
+    B2 = torch.einsum("klab,klij->ijab", t2, Xkl)
+    Y = d.g("oovv") - 0.5 * torch.einsum("liad,kdlc->kiac", t2, g_ovov)
+    Cx = -0.5 * torch.einsum("kjbc,kiac->ijab", t2, Y) - torch.einsum("kibc,kjac->ijab", t2, Y)
+    Lt_voov = 2.0 * d.g("voov") - d.g("vvoo").permute(0, 3, 2, 1)
+    Z = Lt_voov + 0.5 * torch.einsum("ilad,ldkc->aikc", u, L_ovov)
+    D2 = 0.5 * torch.einsum("jkbc,aikc->ijab", u, Z)
+    E2 = (torch.einsum("ijac,bc->ijab", t2, Fvv - torch.einsum("klbd,ldkc->bc", u, g_ovov))
+          - torch.einsum("ikab,kj->ijab", t2, Foo + torch.einsum("ljcd,kdlc->kj", u, g_ovov)))
+    r2 = A2 + B2 + _perm_ijab(Cx + D2 + E2)
+    return r1, r2
+
+
+# -----------------------------------------------------------------------------
+# Triples (eq. cc3-t3-no-pert, eq. cc3-x1-exp, eq. cc3-x2-exp, eq. cc3-l3-exp,
+# eq. cc3-y1-exp, eq. cc3-y2-exp, eq. cc3-dij and the following two)
+# -----------------------------------------------------------------------------
+
+# P_ijk^abc (eq. cc3-pijkabc) as permutations of (i,j,k) applied to both the
+# occupied and virtual slots: f_ijk^abc, f_jik^bac, f_ikj^acb, f_kji^cba,
+# f_kij^cab, f_jki^bca.
+_P3 = [(0, 1, 2), (1, 0, 2), (0, 2, 1), (2, 1, 0), (2, 0, 1), (1, 2, 0)]
+
+
+def p3_full(x):
+    """P_ijk^abc on a full [o,o,o,v,v,v] tensor."""
+    out = torch.zeros_like(x)
+    for s in _P3:
+        # term[i,j,k,a,b,c] = x[s-permuted (i,j,k)], same for (a,b,c)
+        inv = [s.index(q) for q in range(3)]
+        out = out + x.permute(*inv, *[3 + q for q in inv])
+    return out
+
+
+class TriplesIntegrals:
+    """Integral blocks the triples equations use (dressed where the paper puts a tilde)."""
+
+    def __init__(self, d: Dressed):
+        self.g_vovv = d.g("vovv")  # (ck|be)~  = <cb|ke>~
+        self.g_oovo = d.g("oovo")  # (mj|ck)~  = <mc|jk>~
+        self.g_vvov = d.g("vvov")  # (ac|ke)~  = <ak|ce>~
+        self.g_ooov = d.g("ooov")  # (ki|mc)~  = <km|ic>~
+        self.g_ovoo = d.g("ovoo")  # (ka|jl)~  = <kj|al>~
+        self.g_ovvv = d.g("ovvv")  # (ka|db)~  = <kd|ab>~
+        self.g_vvvo = d.g("vvvo")  # (da|el)~  = <de|al>~
+        self.g_oovv = d.g("oovv")  # (jl|da)~  = <jd|la>~
+        self.g_voov = d.g("voov")  # (dl|ja)~  = <dj|la>~
+        self.g_vvvv = d.g("vvvv")  # (da|eb)~  = <de|ab>~
+        self.g_oooo = d.g("oooo")  # (il|jm)~  = <ij|lm>~
+        gov = d.g("ovov")           # (ia|jb), dressing-invariant
+        self.g_ovov = gov
+        self.L_ovov = 2.0 * gov - gov.permute(0, 3, 2, 1)  # L_iajb = 2(ia|jb) - (ib|ja)
+        o = d.o
+        self.Fov = d.F[:o, o:]
+        # Lt_ijal = 2<ij|al>~ - <ij|la>~ = 2(ia|jl)~ - (il|ja)~
+        self.Lt_ovoo = 2.0 * self.g_ovoo - self.g_ooov.permute(0, 3, 2, 1)
+        # Lt_djab = 2<dj|ab>~ - <dj|ba>~ = 2(da|jb)~ - (db|ja)~
+        self.Lt_vvov = 2.0 * self.g_vvov - self.g_vvov.permute(0, 3, 2, 1)
+
+
+def w_prime_block(ti: TriplesIntegrals, t2, i, j, k):
+    """W'_ijk^abc = sum_e t_ij^ae <cb|ke>~ - sum_m t_im^ab <mc|jk>~ (eq. cc3-t3-no-pert, spin-adapted)."""
+    return (torch.einsum("ae,cbe->abc", t2[i, j], ti.g_vovv[:, k, :, :])
+            - torch.einsum("mab,mc->abc", t2[i], ti.g_oovo[:, j, :, k]))
+
+
+def m_prime_block(ti: TriplesIntegrals, l1, l2, i, j, k):
+    """The bracket of eq. cc3-l3-exp for one ordered (i,j,k), before P_ijk^abc."""
+    L = ti.L_ovov
+    Fov = ti.Fov
+    x = (torch.einsum("ab,c->abc", L[i, :, j, :], l1[k])
+         - torch.einsum("ac,b->abc", L[i, :, j, :], l1[k])
+         + torch.einsum("a,bc->abc", Fov[i], l2[j, k])
+         + torch.einsum("al,lbc->abc", ti.g_ovoo[k, :, j, :], l2[:, i])
+         - torch.einsum("adb,cd->abc", ti.g_ovvv[k], l2[i, j]))
+
+    def half(i, j, ab):
+        y = (-torch.einsum("a,bc->abc", Fov[j], l2[i, k])
+             - torch.einsum("al,lbc->abc", ti.Lt_ovoo[i, :, j, :], l2[:, k])
+             + torch.einsum("dab,cd->abc", ti.Lt_vvov[:, :, j, :], l2[k, i]))
+        return y if not ab else y.permute(1, 0, 2)
+
+    # 1/2 P_ij^ab (...): the term plus its (i<->j, a<->b) image
+    x = x + 0.5 * (half(i, j, False) + half(j, i, True))
+    return x
+
+
+_PERM_BLOCK = {
+    # block of the permuted occupied triple, rearranged into [a,b,c] order
+    (0, 1, 2): (0, 1, 2),
+    (1, 0, 2): (1, 0, 2),
+    (0, 2, 1): (0, 2, 1),
+    (2, 1, 0): (2, 1, 0),
+    (2, 0, 1): (1, 2, 0),
+    (1, 2, 0): (2, 0, 1),
+}
+
+
+def sym_block(fn, i, j, k):
+    """P_ijk^abc applied blockwise: sum over the six (i,j,k)/(a,b,c) permutations."""
+    occ = (i, j, k)
+    out = None
+    for s in _P3:
+        blk = fn(occ[s[0]], occ[s[1]], occ[s[2]])
+        term = blk.permute(*_PERM_BLOCK[s])
+        out = term if out is None else out + term
+    return out
+
+
+def t3_block(m: Model, ti, t2, i, j, k):
+    """t_ijk^abc = P_ijk^abc W'_ijk^abc / D_ijk^abc for one ordered triple."""
+    w = sym_block(lambda a, b, c: w_prime_block(ti, t2, a, b, c), i, j, k)
+    return w / m.denom3(i, j, k)
+
+
+def l3_block(m: Model, ti, l1, l2, i, j, k):
+    """lambda_abc^ijk = P_ijk^abc {...} / D_ijk^abc (eq. cc3-l3-exp with eq. cc3-l3's denominator)."""
+    w = sym_block(lambda a, b, c: m_prime_block(ti, l1, l2, a, b, c), i, j, k)
+    return w / m.denom3(i, j, k)
+
+
+def t3_full(m: Model, ti, t2):
+    wp = (torch.einsum("ijae,ckbe->ijkabc", t2, ti.g_vovv)
+          - torch.einsum("imab,mjck->ijkabc", t2, ti.g_oovo))
+    return p3_full(wp) / m.d3
+
+
+def l3_full(m: Model, ti, l1, l2):
+    L, Fov = ti.L_ovov, ti.Fov
+    x = (torch.einsum("iajb,kc->ijkabc", L, l1)
+         - torch.einsum("iajc,kb->ijkabc", L, l1)
+         + torch.einsum("ia,jkbc->ijkabc", Fov, l2)
+         + torch.einsum("kajl,libc->ijkabc", ti.g_ovoo, l2)
+         - torch.einsum("kadb,ijcd->ijkabc", ti.g_ovvv, l2))
+    y = (-torch.einsum("ja,ikbc->ijkabc", Fov, l2)
+         - torch.einsum("iajl,lkbc->ijkabc", ti.Lt_ovoo, l2)
+         + torch.einsum("dajb,kicd->ijkabc", ti.Lt_vvov, l2))
+    x = x + 0.5 * (y + y.permute(1, 0, 2, 4, 3, 5))
+    return p3_full(x) / m.d3
+
+
+def x_full(ti: TriplesIntegrals, t3):
+    """X1 (eq. cc3-x1-exp) and X2 (eq. cc3-x2-exp) from a full t3."""
+    tz = t3 - t3.permute(0, 1, 2, 5, 4, 3)  # t_ijk^abc - t_ijk^cba
+    X1 = torch.einsum("ijkabc,jbkc->ia", tz, ti.L_ovov)
+    x2 = torch.einsum("ijkabc,kc->ijab", tz, ti.Fov)
+    z = 2.0 * t3 - t3.permute(0, 1, 2, 3, 5, 4) - t3.permute(0, 1, 2, 5, 4, 3)  # [ijk, c b e]
+    x2 = x2 + torch.einsum("ijkcbe,acke->ijab", z, ti.g_vvov)
+    zh = 2.0 * t3.permute(0, 1, 2, 5, 4, 3) - t3.permute(0, 1, 2, 5, 3, 4) - t3  # [mjk, a b c]
+    x2 = x2 - torch.einsum("mjkabc,kimc->ijab", zh, ti.g_ooov)
+    return X1, _perm_ijab(x2)
+
+
+def y_full(ti: TriplesIntegrals, t2, l2, t3, l3):
+    """Y1 (eq. cc3-y1-exp) and Y2 (eq. cc3-y2-exp) from full t3 and lambda3."""
+    gov, L = ti.g_ovov, ti.L_ovov
+    Y1 = (torch.einsum("jklbcd,icjd,klab->ia", t3, gov, l2)
+          + torch.einsum("jklbcd,kalb,ijcd->ia", t3, gov, l2)
+          + torch.einsum("jklbcd,iajb,klcd->ia", t3, L, l2)
+          - torch.einsum("jklbcd,iajc,klbd->ia", t3, L, l2)
+          - torch.einsum("jklbcd,jbic,klad->ia", t3, L, l2)
+          # Reading: the printed L_ijab of this term carries the wrong occupied
+          # index; the derivative of the lambda2.X2 pairing with respect to t1
+          # gives L_kjab = 2(ka|jb) - (kb|ja).
+          - torch.einsum("jklbcd,kajb,ilcd->ia", t3, L, l2)
+          - torch.einsum("jkbc,jlda,lkibcd->ia", t2, ti.g_oovv, l3)
+          - torch.einsum("jkbc,dlja,iklbcd->ia", t2, ti.g_voov, l3)
+          - torch.einsum("jkbc,ildb,lkjacd->ia", t2, ti.g_oovv, l3)
+          # Reading: the printed <di|la> repeats 'a' and leaves 'b' free; the
+          # term is read as <di|lb>~ = (dl|ib)~, the exchange partner of the
+          # preceding <id|lb>~ term.
+          - torch.einsum("jkbc,dlib,jklacd->ia", t2, ti.g_voov, l3)
+          + torch.einsum("jkbc,daeb,kijcde->ia", t2, ti.g_vvvv, l3)
+          + torch.einsum("jkbc,iljm,lmkabc->ia", t2, ti.g_oooo, l3))
+    y2 = torch.einsum("dael,ijldbe->ijab", ti.g_vvvo, l3)
+    y2 = y2 - torch.einsum("imdl,mjlabd->ijab", ti.g_oovo, l3)
+    return Y1, _perm_ijab(y2)
+
+
+def density_triples_full(t2, l2, t3, l3):
+    """D_ij, D_ab, D_ia of eq. cc3-dij and the two equations after it."""
+    Dij = -0.5 * torch.einsum("ilkabc,jlkabc->ij", t3, l3)
+    Dab = 0.5 * torch.einsum("ijkbdc,ijkadc->ab", t3, l3)
+    Dia = (torch.einsum("ijkabc,jkbc->ia", t3 - t3.permute(0, 1, 2, 4, 3, 5), l2)
+           - torch.einsum("jklbcd,ilcd,kjab->ia", l3, t2, t2))
+    return Dij, Dab, Dia
+
+
+def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False):
+    """Triples contributions evaluated one occupied triple at a time (Sec. 2.1).
+
+    The loop runs over (l,k) and, inside, over i, building the [v,v,v] blocks
+    t3_{ilk} and lambda3_{ilk}; the o blocks sharing (l,k) serve D_ij.
+    Every other contraction takes the block of one ordered triple at a time.
+    """
+    o, v = m.o, m.v
+    X1 = torch.zeros((o, v), dtype=C128)
+    x2 = torch.zeros((o, o, v, v), dtype=C128)
+    Y1 = torch.zeros((o, v), dtype=C128)
+    y2 = torch.zeros((o, o, v, v), dtype=C128)
+    Dij = torch.zeros((o, o), dtype=C128)
+    Dab = torch.zeros((v, v), dtype=C128)
+    Dia = torch.zeros((o, v), dtype=C128)
+    gov, L = ti.g_ovov, ti.L_ovov
+    for J in range(o):
+        for K in range(o):
+            tstack, lstack = [], []
+            for I in range(o):
+                t = t3_block(m, ti, t2, I, J, K)
+                lam = l3_block(m, ti, l1, l2, I, J, K)
+                tstack.append(t)
+                lstack.append(lam)
+                # --- X1, X2 (block (I,J,K) as (i,j,k), and as (m,j,k))
+                tz = t - t.permute(2, 1, 0)
+                X1[I] += torch.einsum("abc,bc->a", tz, L[J, :, K, :])
+                x2[I, J] += torch.einsum("abc,c->ab", tz, ti.Fov[K])
+                z = 2.0 * t - t.permute(0, 2, 1) - t.permute(2, 1, 0)
+                x2[I, J] += torch.einsum("cbe,ace->ab", z, ti.g_vvov[:, :, K, :])
+                zh = 2.0 * t.permute(2, 1, 0) - t.permute(2, 0, 1) - t
+                x2[:, J] -= torch.einsum("abc,xc->xab", zh, ti.g_ooov[K, :, I, :])
+                # --- Y2 (block as (i,j,l) and as (m,j,l))
+                y2[I, J] += torch.einsum("dbe,dae->ab", lam, ti.g_vvvo[:, :, :, K])
+                y2[:, J] -= torch.einsum("abd,xd->xab", lam, ti.g_oovo[:, I, :, K])
+                # --- Y1: t3 lambda2 terms, block t3 as (j,k,l) = (I,J,K)
+                Y1 += torch.einsum("bcd,xcd,ab->xa", t, gov[:, :, I, :], l2[J, K])
+                Y1 += torch.einsum("bcd,ab,xcd->xa", t, gov[J, :, K, :], l2[:, I])
+                Y1 += torch.einsum("bcd,cd,xab->xa", t, l2[J, K], L[:, :, I, :])
+                Y1 -= torch.einsum("bcd,bd,xac->xa", t, l2[J, K], L[:, :, I, :])
+                Y1 -= torch.einsum("bcd,ad,bxc->xa", t, l2[J, K], L[I])
+                Y1 -= torch.einsum("bcd,ab,xcd->xa", t, L[J, :, I, :], l2[:, K])
+                # --- Y1: t2 lambda3 terms
+                # lambda_bcd^{lki}: block (I,J,K) = (l,k,i) -> output i = K
+                Y1[K] -= torch.einsum("jbc,jda,bcd->a", t2[:, J], ti.g_oovv[:, I], lam)
+                # lambda_bcd^{ikl}: block = (i,k,l) -> output i = I
+                Y1[I] -= torch.einsum("jbc,dja,bcd->a", t2[:, J], ti.g_voov[:, K], lam)
+                # lambda_acd^{lkj}: block = (l,k,j)
+                Y1 -= torch.einsum("bc,xdb,acd->xa", t2[K, J], ti.g_oovv[:, I], lam)
+                # lambda_acd^{jkl}: block = (j,k,l)
+                Y1 -= torch.einsum("bc,dxb,acd->xa", t2[I, J], ti.g_voov[:, K], lam)
+                # lambda_cde^{kij}: block = (k,i,j) -> output i = J
+                zb = torch.einsum("bc,cde->bde", t2[K, I], lam)
+                Y1[J] += torch.einsum("bde,daeb->a", zb, ti.g_vvvv)
+                # lambda_abc^{lmk}: block = (l,m,k)
+                Y1 += torch.einsum("jbc,xj,abc->xa", t2[:, K], ti.g_oooo[:, I, :, J], lam)
+                if want_density:
+                    Dab += 0.5 * torch.einsum("bdc,adc->ab", t, lam)
+                    Dia[I] += torch.einsum("abc,bc->a", t - t.permute(1, 0, 2), l2[J, K])
+                    # - sum lambda_bcd^{jkl} t_il^cd t_kj^ab, block = (j,k,l)
+                    zz = torch.einsum("bcd,xcd->bx", lam, t2[:, K])
+                    Dia -= torch.einsum("bx,ab->xa", zz, t2[J, I])
+            if want_density:
+                # D_ij = -1/2 sum t_{ilk} lambda_{jlk}, here (l,k) = (J,K)
+                ts = torch.stack(tstack)
+                ls = torch.stack(lstack)
+                Dij -= 0.5 * torch.einsum("iabc,jabc->ij", ts, ls)
+    out = dict(X1=X1, X2=_perm_ijab(x2), Y1=Y1, Y2=_perm_ijab(y2))
+    if want_density:
+        out.update(Dij=Dij, Dab=Dab, Dia=Dia)
+    return out
+
+
+def triples_explicit(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False):
+    t3 = t3_full(m, ti, t2)
+    l3 = l3_full(m, ti, l1, l2)
+    X1, X2 = x_full(ti, t3)
+    Y1, Y2 = y_full(ti, t2, l2, t3, l3)
+    out = dict(X1=X1, X2=X2, Y1=Y1, Y2=Y2, t3=t3, l3=l3)
+    if want_density:
+        Dij, Dab, Dia = density_triples_full(t2, l2, t3, l3)
+        out.update(Dij=Dij, Dab=Dab, Dia=Dia)
+    return out
+
+
+# -----------------------------------------------------------------------------
+# Right-hand side, density, dipole, RK4
+# -----------------------------------------------------------------------------
+
+_ONE = torch.ones((), dtype=C128)
+
+
+def _holo_grad(L, inputs):
+    """Holomorphic derivative dL/dz (torch returns its conjugate for grad_outputs = 1)."""
+    gs = torch.autograd.grad(L, inputs, grad_outputs=_ONE)
+    return [g.conj() for g in gs]
+
+
+def unpack(m: Model, y):
+    o, v = m.o, m.v
+    y = torch.as_tensor(np.asarray(y), dtype=C128)
+    ov, oovv = o * v, o * o * v * v
+    return (y[:ov].reshape(o, v), y[ov:ov + oovv].reshape(o, o, v, v),
+            y[ov + oovv:2 * ov + oovv].reshape(o, v), y[2 * ov + oovv:].reshape(o, o, v, v))
+
+
+def pack(t1, t2, l1, l2):
+    return torch.cat([x.reshape(-1) for x in (t1, t2, l1, l2)])
+
+
+def rhs(m: Model, y, E, triples="loop", with_dipole=False, with_triples=True):
+    """dy/dt for y = (t1, t2, l1, l2) at field E (three Cartesian components).
+
+    i dt/dt = Omega(t) + X(t3)                      (eq. cc3-rt-t)
+    -i dl/dt = dL/dt, with the CCSD part of L differentiated automatically
+               and the triples part from Y1, Y2     (eq. cc3-rt-l)
+    The doubles pairing carries C2, so -i dl2/dt = sym(dL/dt2) / C2.
+    """
+    t1, t2, l1, l2 = unpack(m, y)
+    t1v = t1.clone().requires_grad_(True)
+    t2v = t2.clone().requires_grad_(True)
+    d = Dressed(m, t1v, m.h(E))
+    r1, r2 = ccsd_omega(d, t2v)
+    L = ccsd_energy(d, t2v) + (l1 * r1).sum() + C2 * (l2 * r2).sum()
+    g1, g2, gh = _holo_grad(L, [t1v, t2v, d.h])
+    r1, r2 = r1.detach(), r2.detach()
+    g2 = 0.5 * (g2 + g2.permute(1, 0, 3, 2)) / C2
+    o, v = m.o, m.v
+    zero1 = torch.zeros((o, v), dtype=C128)
+    zero2 = torch.zeros((o, o, v, v), dtype=C128)
+    tri = None
+    with torch.no_grad():
+        dd = Dressed(m, t1, m.h(E))
+        if with_triples:
+            ti = TriplesIntegrals(dd)
+            fn = triples_loop if triples == "loop" else triples_explicit
+            tri = fn(m, ti, t2, l1, l2, want_density=with_dipole)
+            X1, X2, Y1, Y2 = tri["X1"], tri["X2"], tri["Y1"], tri["Y2"]
+        else:
+            X1, X2, Y1, Y2 = zero1, zero2, zero1, zero2
+        dy = pack(-1j * (r1 + X1), -1j * (r2 + X2), 1j * (g1 + Y1), 1j * (g2 + Y2))
+        if not with_dipole:
+            return dy
+        D = gh.detach().clone()
+        if tri is not None:
+            D[:o, :o] += tri["Dij"]
+            D[o:, o:] += tri["Dab"]
+            D[:o, o:] += tri["Dia"]
+        mu = torch.stack([(D * dd.transform(m.mu[x])).sum() for x in range(3)])
+        return dy, mu
+
+
+def density_dressed(m: Model, y, E, triples="loop", with_triples=True):
+    """One-electron density in the T1-transformed frame (coefficients of h~_pq)."""
+    t1, t2, l1, l2 = unpack(m, y)
+    t1v = t1.clone()
+    d0 = Dressed(m, t1v, m.h(E))
+    hl = d0.h.detach().clone().requires_grad_(True)
+    # rebuild the Lagrangian with h~ as a leaf
+    d0.h = hl
+    Bd = torch.einsum("Pkk->P", d0.B[:, :m.o, :m.o])
+    J = torch.einsum("Ppq,P->pq", d0.B, Bd)
+    K = torch.einsum("Ppk,Pkq->pq", d0.B[:, :, :m.o], d0.B[:, :m.o, :])
+    d0.F = hl + 2.0 * J - K
+    r1, r2 = ccsd_omega(d0, t2)
+    L = ccsd_energy(d0, t2) + (l1 * r1).sum() + C2 * (l2 * r2).sum()
+    (D,) = _holo_grad(L, [hl])
+    if with_triples:
+        with torch.no_grad():
+            ti = TriplesIntegrals(d0)
+            fn = triples_loop if triples == "loop" else triples_explicit
+            tri = fn(m, ti, t2, l1, l2, want_density=True)
+        o = m.o
+        D = D.clone()
+        D[:o, :o] += tri["Dij"]
+        D[o:, o:] += tri["Dab"]
+        D[:o, o:] += tri["Dia"]
+    return D, d0
+
+
+def dipole(m: Model, y, E, triples="loop", with_triples=True):
+    """mu_x = sum_pq D~_pq mu~^x_pq (Sec. 2.2.3), complex; D~, mu~ T1-transformed."""
+    D, d0 = density_dressed(m, y, E, triples, with_triples)
+    with torch.no_grad():
+        return torch.stack([(D * d0.transform(m.mu[x])).sum() for x in range(3)])
+
+
+def propagate(m: Model, y0, dt, field, steps=None, triples="loop", with_triples=True, callback=None):
+    """Classic RK4 (Sec. 3) with the field sampled at t, t+dt/2, t+dt/2, t+dt.
+
+    field: [(2*steps+1), 3] samples E(k dt / 2).  Returns (y_final, mu[steps+1, 3]).
+    The dipole at t_n comes from the first stage of step n (same amplitudes and field).
+    """
+    field = np.asarray(field, dtype=np.float64)
+    if steps is None:
+        steps = (field.shape[0] - 1) // 2
+    y = torch.as_tensor(np.asarray(y0), dtype=C128).clone()
+    mus = []
+    kw = dict(triples=triples, with_triples=with_triples)
+    for n in range(steps):
+        k1, mu = rhs(m, y, field[2 * n], with_dipole=True, **kw)
+        mus.append(mu)
+        k2 = rhs(m, y + 0.5 * dt * k1, field[2 * n + 1], **kw)
+        k3 = rhs(m, y + 0.5 * dt * k2, field[2 * n + 1], **kw)
+        k4 = rhs(m, y + dt * k3, field[2 * n + 2], **kw)
+        y = y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        if callback is not None:
+            callback(n, y)
+    mus.append(dipole(m, y, field[2 * steps], **kw))
+    return y, torch.stack(mus)
+
+
+def lagrangian(m: Model, y, E, triples="explicit", with_triples=True):
+    """L = E + l1.(Omega1 + X1) + C2 l2.(Omega2 + X2) with t3 at its closed form."""
+    t1, t2, l1, l2 = unpack(m, y)
+    d = Dressed(m, t1, m.h(E))
+    r1, r2 = ccsd_omega(d, t2)
+    val = ccsd_energy(d, t2) + (l1 * r1).sum() + C2 * (l2 * r2).sum()
+    if with_triples:
+        ti = TriplesIntegrals(d)
+        t3 = t3_full(m, ti, t2)
+        X1, X2 = x_full(ti, t3)
+        val = val + (l1 * X1).sum() + C2 * (l2 * X2).sum()
+    return val

@@ -1,0 +1,122 @@
+/*
+ * rtcc3.h -- C ABI of the MI355X real-time CC3 library (librtcc3.so).
+ *
+ * The library propagates the complex closed-shell amplitudes (t1, t2, l1, l2)
+ * of real-time CC3 (arXiv 2407.18947) under an electric field in the dipole
+ * approximation and returns the induced dipole moment.
+ *
+ *   Hamiltonian      H(t) = F + U - mu.E(t)                 (Sec. 2.1, eq. cc3-h-pert; Sec. 2.2.1)
+ *   amplitude EOMs   i dt/dt = <mu|Hbar|0>, -i dl/dt = dL/dt (eq. cc3-rt-t, eq. cc3-rt-l, Appendix A)
+ *   triples          t3 closed form built per occupied triple (i,j,k), divided by the
+ *                    orbital-energy denominator, contracted into the singles/doubles
+ *                    residuals (eq. cc3-t3-no-pert, cc3-l3, cc3-x1-exp ... cc3-y2-exp; Sec. 2.1)
+ *   dipole           mu_x = sum_pq D_pq mu^x_pq with the CC3 one-electron density
+ *                    (Sec. 2.2.3; eq. cc3-dij and the two equations after it)
+ *   propagation      classic RK4 (Sec. 3)
+ *
+ * Conventions.  o occupied and v virtual orbitals, n = o + v, occupied first.
+ * All arrays are row-major.  Complex numbers are interleaved (re, im) doubles,
+ * layout-compatible with std::complex<double> and torch.complex128.
+ * State vector y (length 2*(o*v + o*o*v*v)): [ t1[i][a] | t2[i][j][a][b] | l1[i][a] | l2[i][j][a][b] ]
+ * with t2[i][j][a][b] = t_ij^ab = t2[j][i][b][a] (same for l2).  The doubles
+ * multipliers pair with the residual as 1/2 sum_ijab l2_ijab Omega_ijab, i.e.
+ * l2_ijab = <Lambda| E_ai E_bj |0>.
+ *
+ * Errors.  Every function returns RTCC3_OK (0) or a negative RTCC3_* code;
+ * no exception or abort crosses the ABI.  rtcc3_last_error() gives a message.
+ * Ownership.  Host arrays passed in are copied; the caller keeps them.  Device
+ * pointers passed to rtcc3_rhs / rtcc3_rhs_terms are caller-owned and must stay
+ * valid for the call; all work is ordered on the context's stream and the
+ * functions return after that stream has been synchronised.  A context serves
+ * one thread at a time.
+ */
+#ifndef RTCC3_H
+#define RTCC3_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtcc3_ctx rtcc3_ctx;
+
+typedef struct {
+  double re, im;
+} rtcc3_c64;
+
+enum {
+  RTCC3_OK = 0,
+  RTCC3_EINVAL = -1,    /* bad argument (sizes, NULL, non-finite, asymmetric input) */
+  RTCC3_ENOMEM = -2,    /* device allocation failed */
+  RTCC3_EDEVICE = -3,   /* HIP runtime error (message from hipGetErrorString) */
+  RTCC3_ESTATE = -4,    /* call not valid in the context's current state */
+  RTCC3_EDIVERGED = -5  /* the propagated state became non-finite */
+};
+
+/* Precision of the triples contractions.  Denominators, residual accumulation,
+ * RK4 and the dipole always stay in FP64. */
+enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1 };
+
+/* Create a context.
+ *   o, v     numbers of occupied / virtual orbitals (o >= 1, v >= 1)
+ *   fock     [n*n] host, canonical Fock matrix; must be diagonal (|off-diag| <= 1e-12), finite
+ *   naux, B  [naux*n*n] host, density-fitting factors, (pq|rs) = sum_P B[P][p][q] B[P][r][s];
+ *            each B[P] symmetric (<= 1e-12)
+ *   dipole   [3*n*n] host, electric dipole matrices mu^x, mu^y, mu^z, symmetric
+ *   precision RTCC3_FP64 or RTCC3_FP32
+ *   hip_stream a hipStream_t to order work on, or NULL for a stream owned by the context
+ *   out      receives the context
+ * Returns EINVAL, ENOMEM or EDEVICE on failure (message via rtcc3_last_error(NULL)). */
+int rtcc3_create(int o, int v, const double *fock, int naux, const double *B, const double *dipole,
+                 int precision, void *hip_stream, rtcc3_ctx **out);
+
+/* Set / get the state vector y (layout above).  y_on_device: 0 = host pointer,
+ * 1 = device pointer (caller-owned). */
+int rtcc3_set_state(rtcc3_ctx *ctx, const rtcc3_c64 *y, int y_on_device);
+int rtcc3_get_state(rtcc3_ctx *ctx, rtcc3_c64 *y, int y_on_device);
+
+/* dy = f(y) at field E[3] (host).  y_dev, dy_dev: device arrays of the state length. */
+int rtcc3_rhs(rtcc3_ctx *ctx, const double E[3], const rtcc3_c64 *y_dev, rtcc3_c64 *dy_dev);
+
+/* Individual terms of the right-hand side at state y_dev and field E (device
+ * output terms_dev, caller-owned), concatenated in this order:
+ *   Omega1[o*v]  Omega2[o*o*v*v]     CCSD part of <mu|Hbar|0>
+ *   G1[o*v]      G2[o*o*v*v]         CCSD part of dL/dt1, sym(dL/dt2)/(1/2)
+ *   X1[o*v]      X2[o*o*v*v]         triples into the T equations (eq. cc3-x1-exp, cc3-x2-exp)
+ *   Y1[o*v]      Y2[o*o*v*v]         triples into the Lambda equations (eq. cc3-y1-exp, cc3-y2-exp)
+ *   D[n*n]                           one-electron density, T1-transformed frame
+ *   mu[3]                            dipole moment
+ * with_triples = 0 gives the CCSD model (X, Y and the triples density zero). */
+int rtcc3_rhs_terms(rtcc3_ctx *ctx, const double E[3], const rtcc3_c64 *y_dev, rtcc3_c64 *terms_dev,
+                    int with_triples);
+
+/* Propagate the context's state by `steps` RK4 steps of size dt (dt != 0).
+ *   field       [(2*steps+1)*3] host: E(k*dt/2), k = 0..2*steps
+ *   dipole_out  [(steps+1)*3] host: mu(t_n) for n = 0..steps (complex; may be NULL)
+ * On EDIVERGED the state is left at the last finite step. */
+int rtcc3_propagate(rtcc3_ctx *ctx, int steps, double dt, const double *field, rtcc3_c64 *dipole_out);
+
+/* Dipole of the context's current state at field E[3] (host) -> out[3] (host). */
+int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
+
+/* Options: RTCC3_OPT_TRIPLES (1 = CC3, 0 = CCSD model), RTCC3_OPT_PRECISION. */
+enum { RTCC3_OPT_TRIPLES = 1, RTCC3_OPT_PRECISION = 2 };
+int rtcc3_set_option(rtcc3_ctx *ctx, int option, int value);
+
+/* Timing of the last rtcc3_propagate (milliseconds, from HIP events on the
+ * context's stream): total and the part spent in the triples kernels.
+ * kernel_ms[0] = total, [1] = triples, [2] = triples launches counted. */
+int rtcc3_last_timing(rtcc3_ctx *ctx, double kernel_ms[3]);
+
+/* Library self-test of the complex GEMM the contractions run on:
+ * C[m][n] = sum_k A[m][k] B[k][n] for host row-major complex arrays, computed
+ * on the device with FP64 (precision 0) or FP32 (1) matrix-core arithmetic.
+ * Returns EINVAL for non-positive sizes or NULL pointers. */
+int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rtcc3_c64 *A, const rtcc3_c64 *B, rtcc3_c64 *C);
+
+const char *rtcc3_last_error(const rtcc3_ctx *ctx); /* ctx == NULL: last create() error of this thread */
+void rtcc3_destroy(rtcc3_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTCC3_H */

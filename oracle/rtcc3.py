@@ -450,7 +450,7 @@ _ONE = torch.ones((), dtype=C128)
 def _holo_grad(L, inputs):
     """Holomorphic derivative dL/dz (torch returns its conjugate for grad_outputs = 1)."""
     gs = torch.autograd.grad(L, inputs, grad_outputs=_ONE)
-    return [g.conj() for g in gs]
+    return [g.conj().resolve_conj() for g in gs]
 
 
 def unpack(m: Model, y):
@@ -465,13 +465,12 @@ def pack(t1, t2, l1, l2):
     return torch.cat([x.reshape(-1) for x in (t1, t2, l1, l2)])
 
 
-def rhs(m: Model, y, E, triples="loop", with_dipole=False, with_triples=True):
-    """dy/dt for y = (t1, t2, l1, l2) at field E (three Cartesian components).
+def rhs_terms(m: Model, y, E, triples="loop", with_triples=True, with_density=True):
+    """The separate pieces of the right-hand side at state y and field E.
 
-    i dt/dt = Omega(t) + X(t3)                      (eq. cc3-rt-t)
-    -i dl/dt = dL/dt, with the CCSD part of L differentiated automatically
-               and the triples part from Y1, Y2     (eq. cc3-rt-l)
-    The doubles pairing carries C2, so -i dl2/dt = sym(dL/dt2) / C2.
+    R1, R2: CCSD part of <mu|Hbar|0>; G1 = dL/dt1 and G2 = sym(dL/dt2)/C2 of
+    the CCSD Lagrangian; X1, X2, Y1, Y2: triples contributions; D: the
+    T1-frame one-electron density; mu: the dipole.
     """
     t1, t2, l1, l2 = unpack(m, y)
     t1v = t1.clone().requires_grad_(True)
@@ -480,31 +479,45 @@ def rhs(m: Model, y, E, triples="loop", with_dipole=False, with_triples=True):
     r1, r2 = ccsd_omega(d, t2v)
     L = ccsd_energy(d, t2v) + (l1 * r1).sum() + C2 * (l2 * r2).sum()
     g1, g2, gh = _holo_grad(L, [t1v, t2v, d.h])
-    r1, r2 = r1.detach(), r2.detach()
-    g2 = 0.5 * (g2 + g2.permute(1, 0, 3, 2)) / C2
     o, v = m.o, m.v
-    zero1 = torch.zeros((o, v), dtype=C128)
-    zero2 = torch.zeros((o, o, v, v), dtype=C128)
-    tri = None
+    out = dict(R1=r1.detach(), R2=r2.detach(), G1=g1, G2=0.5 * (g2 + g2.permute(1, 0, 3, 2)) / C2)
     with torch.no_grad():
         dd = Dressed(m, t1, m.h(E))
         if with_triples:
             ti = TriplesIntegrals(dd)
             fn = triples_loop if triples == "loop" else triples_explicit
-            tri = fn(m, ti, t2, l1, l2, want_density=with_dipole)
-            X1, X2, Y1, Y2 = tri["X1"], tri["X2"], tri["Y1"], tri["Y2"]
+            tri = fn(m, ti, t2, l1, l2, want_density=with_density)
+            for k in ("X1", "X2", "Y1", "Y2"):
+                out[k] = tri[k]
         else:
-            X1, X2, Y1, Y2 = zero1, zero2, zero1, zero2
-        dy = pack(-1j * (r1 + X1), -1j * (r2 + X2), 1j * (g1 + Y1), 1j * (g2 + Y2))
-        if not with_dipole:
-            return dy
-        D = gh.detach().clone()
-        if tri is not None:
-            D[:o, :o] += tri["Dij"]
-            D[o:, o:] += tri["Dab"]
-            D[:o, o:] += tri["Dia"]
-        mu = torch.stack([(D * dd.transform(m.mu[x])).sum() for x in range(3)])
-        return dy, mu
+            tri = None
+            out.update(X1=torch.zeros((o, v), dtype=C128), X2=torch.zeros((o, o, v, v), dtype=C128),
+                       Y1=torch.zeros((o, v), dtype=C128), Y2=torch.zeros((o, o, v, v), dtype=C128))
+        if with_density:
+            D = gh.detach().clone()
+            if tri is not None:
+                D[:o, :o] += tri["Dij"]
+                D[o:, o:] += tri["Dab"]
+                D[:o, o:] += tri["Dia"]
+            out["D"] = D
+            out["mu"] = torch.stack([(D * dd.transform(m.mu[x])).sum() for x in range(3)])
+    return out
+
+
+def rhs(m: Model, y, E, triples="loop", with_dipole=False, with_triples=True):
+    """dy/dt for y = (t1, t2, l1, l2) at field E (three Cartesian components).
+
+    i dt/dt = Omega(t) + X(t3)                      (eq. cc3-rt-t)
+    -i dl/dt = dL/dt, with the CCSD part of L differentiated automatically
+               and the triples part from Y1, Y2     (eq. cc3-rt-l)
+    The doubles pairing carries C2, so -i dl2/dt = sym(dL/dt2) / C2.
+    """
+    tm = rhs_terms(m, y, E, triples, with_triples, with_density=with_dipole)
+    dy = pack(-1j * (tm["R1"] + tm["X1"]), -1j * (tm["R2"] + tm["X2"]),
+              1j * (tm["G1"] + tm["Y1"]), 1j * (tm["G2"] + tm["Y2"]))
+    if with_dipole:
+        return dy, tm["mu"]
+    return dy
 
 
 def density_dressed(m: Model, y, E, triples="loop", with_triples=True):

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of librtcc3.so (declared in include/rtcc3.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch supplies device memory (complex128 tensors) and the
+stream; no computation happens here.  If the library is missing the calls
+raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "librtcc3.so")
+
+RTCC3_OK, RTCC3_EINVAL, RTCC3_ENOMEM, RTCC3_EDEVICE, RTCC3_ESTATE, RTCC3_EDIVERGED = 0, -1, -2, -3, -4, -5
+RTCC3_FP64, RTCC3_FP32 = 0, 1
+RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION = 1, 2
+
+EXPORTS = [
+    "rtcc3_create", "rtcc3_set_state", "rtcc3_get_state", "rtcc3_rhs", "rtcc3_rhs_terms", "rtcc3_propagate",
+    "rtcc3_dipole", "rtcc3_set_option", "rtcc3_last_timing", "rtcc3_zgemm_selftest", "rtcc3_last_error",
+    "rtcc3_destroy",
+]
+
+_lib = None
+
+
+class RTCC3Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rtcc3 error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load librtcc3.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIBPATH)
+    P, I, D, VP = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    L.rtcc3_create.argtypes = [I, I, VP, I, VP, VP, I, VP, P(VP)]
+    L.rtcc3_set_state.argtypes = [VP, VP, I]
+    L.rtcc3_get_state.argtypes = [VP, VP, I]
+    L.rtcc3_rhs.argtypes = [VP, VP, VP, VP]
+    L.rtcc3_rhs_terms.argtypes = [VP, VP, VP, VP, I]
+    L.rtcc3_propagate.argtypes = [VP, I, D, VP, VP]
+    L.rtcc3_dipole.argtypes = [VP, VP, VP]
+    L.rtcc3_set_option.argtypes = [VP, I, I]
+    L.rtcc3_last_timing.argtypes = [VP, VP]
+    L.rtcc3_zgemm_selftest.argtypes = [I, I, I, I, VP, VP, VP]
+    L.rtcc3_last_error.argtypes = [VP]
+    L.rtcc3_last_error.restype = ctypes.c_char_p
+    L.rtcc3_destroy.argtypes = [VP]
+    L.rtcc3_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("rtcc3_last_error", "rtcc3_destroy"):
+            getattr(L, name).restype = I
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(a.data_ptr())  # torch tensor
+
+
+def _check(rc, ctx=None):
+    if rc != RTCC3_OK:
+        msg = load().rtcc3_last_error(ctx)
+        raise RTCC3Error(rc, msg.decode() if msg else "")
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _c128(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+
+
+# ---------------------------------------------------------------- same names as the C ABI
+def rtcc3_create(o, v, fock, B, dipole, precision=RTCC3_FP64, stream=None):
+    L = load()
+    fock, B, dipole = _f64(fock), _f64(B), _f64(dipole)
+    naux = B.shape[0]
+    out = ctypes.c_void_p()
+    rc = L.rtcc3_create(o, v, _ptr(fock), naux, _ptr(B), _ptr(dipole), precision, stream, ctypes.byref(out))
+    _check(rc, None)
+    return out
+
+
+def rtcc3_set_state(ctx, y):
+    if isinstance(y, np.ndarray) or not hasattr(y, "data_ptr"):
+        yh = _c128(y)
+        _check(load().rtcc3_set_state(ctx, _ptr(yh), 0), ctx)
+    else:
+        _check(load().rtcc3_set_state(ctx, _ptr(y), 1), ctx)
+
+
+def rtcc3_get_state(ctx, n):
+    y = np.empty(n, dtype=np.complex128)
+    _check(load().rtcc3_get_state(ctx, _ptr(y), 0), ctx)
+    return y
+
+
+def rtcc3_rhs(ctx, E, y_dev, dy_dev):
+    E = _f64(E)
+    _check(load().rtcc3_rhs(ctx, _ptr(E), _ptr(y_dev), _ptr(dy_dev)), ctx)
+
+
+def rtcc3_rhs_terms(ctx, E, y_dev, terms_dev, with_triples=1):
+    E = _f64(E)
+    _check(load().rtcc3_rhs_terms(ctx, _ptr(E), _ptr(y_dev), _ptr(terms_dev), int(with_triples)), ctx)
+
+
+def rtcc3_propagate(ctx, steps, dt, field):
+    field = _f64(field)
+    if field.shape != (2 * steps + 1, 3):
+        raise ValueError("field must have shape (2*steps+1, 3)")
+    mu = np.empty((steps + 1, 3), dtype=np.complex128)
+    _check(load().rtcc3_propagate(ctx, int(steps), float(dt), _ptr(field), _ptr(mu)), ctx)
+    return mu
+
+
+def rtcc3_dipole(ctx, E):
+    E = _f64(E)
+    out = np.empty(3, dtype=np.complex128)
+    _check(load().rtcc3_dipole(ctx, _ptr(E), _ptr(out)), ctx)
+    return out
+
+
+def rtcc3_set_option(ctx, option, value):
+    _check(load().rtcc3_set_option(ctx, int(option), int(value)), ctx)
+
+
+def rtcc3_last_timing(ctx):
+    out = np.zeros(3)
+    _check(load().rtcc3_last_timing(ctx, _ptr(out)), ctx)
+    return out
+
+
+def rtcc3_zgemm_selftest(A, B, precision=RTCC3_FP64):
+    A, B = _c128(A), _c128(B)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    C = np.empty((M, N), dtype=np.complex128)
+    _check(load().rtcc3_zgemm_selftest(M, N, K, precision, _ptr(A), _ptr(B), _ptr(C)), None)
+    return C
+
+
+def rtcc3_last_error(ctx=None):
+    m = load().rtcc3_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def rtcc3_destroy(ctx):
+    if ctx:
+        load().rtcc3_destroy(ctx)
+
+
+class Context:
+    """Owning wrapper of an rtcc3 context for one system."""
+
+    def __init__(self, system, precision=RTCC3_FP64, stream=None):
+        self.o, self.v = system.o, system.v
+        self.n = self.o + self.v
+        self.ylen = 2 * (self.o * self.v + self.o ** 2 * self.v ** 2)
+        self.ctx = rtcc3_create(self.o, self.v, system.fock, system.B, system.mu, precision, stream)
+
+    def close(self):
+        if self.ctx:
+            rtcc3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, y):
+        rtcc3_set_state(self.ctx, y)
+
+    def get_state(self):
+        return rtcc3_get_state(self.ctx, self.ylen)
+
+    def set_option(self, option, value):
+        rtcc3_set_option(self.ctx, option, value)
+
+    def propagate(self, steps, dt, field):
+        return rtcc3_propagate(self.ctx, steps, dt, field)
+
+    def dipole(self, E):
+        return rtcc3_dipole(self.ctx, E)
+
+    def terms_size(self):
+        o, v, n = self.o, self.v, self.n
+        return 4 * (o * v + o * o * v * v) + n * n + 3
+
+    def split_terms(self, t):
+        o, v, n = self.o, self.v, self.n
+        ov, oovv = o * v, o * o * v * v
+        out, p = {}, 0
+        for name, sh in [("R1", (o, v)), ("R2", (o, o, v, v)), ("G1", (o, v)), ("G2", (o, o, v, v)),
+                         ("X1", (o, v)), ("X2", (o, o, v, v)), ("Y1", (o, v)), ("Y2", (o, o, v, v)),
+                         ("D", (n, n)), ("mu", (3,))]:
+            k = int(np.prod(sh))
+            out[name] = t[p:p + k].reshape(sh)
+            p += k
+        return out

@@ -1,0 +1,77 @@
+// Shared host/device definitions of the RT-CC3 library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace rtcc3 {
+
+struct cplx {
+  double re, im;
+};
+
+// Host-side error carrying an RTCC3_* code.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define RTCC3_HIP(call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      throw ::rtcc3::Error(-3, std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+#define RTCC3_CHECK(cond, msg)                                                                \
+  do {                                                                                        \
+    if (!(cond)) throw ::rtcc3::Error(-1, msg);                                               \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel entry points (kernels.hip)
+// ---------------------------------------------------------------------------
+
+// Batched complex GEMM: C[b][m][n] += alpha * sum_k A[b][m][k] B[b][k][n].
+// Each of M, N, K is split in two levels (m = m1*M0 + m0, ...) with its own
+// element strides, so a tensor index group made of two runs of contiguous
+// indices needs no copy.  Batch entry b starts at A + b*sAb (same for B, C),
+// or, when a block table bl is given (4 ints per entry: I, J, K, n), at
+//   A + cA[0]*I + cA[1]*J + cA[2]*K + cA[3]*n   (same for B and C).
+// atomic: accumulate with atomics (several batch entries may share C).
+// prec 0: FP64 MFMA; 1: operands rounded to FP32, FP32 MFMA and accumulate.
+struct GemmDesc {
+  int M, N, K, batch;
+  int M0, N0, K0;
+  const cplx* A;
+  int64_t sAm1, sAm0, sAk1, sAk0, sAb;
+  const cplx* B;
+  int64_t sBk1, sBk0, sBn1, sBn0, sBb;
+  cplx* C;
+  int64_t sCm1, sCm0, sCn1, sCn0, sCb;
+  const int* bl;
+  int64_t cA[4], cB[4], cC[4];
+  cplx alpha;
+  int atomic;
+  int prec;
+};
+void gemm(const GemmDesc& d, hipStream_t s);
+
+// Strided elementwise: Y[idx] += alpha * X[idx] over an nd-dim box (nd <= 8).
+struct AxpyDesc {
+  int nd;
+  int64_t shape[8];
+  const cplx* X;
+  int64_t sx[8];
+  cplx* Y;
+  int64_t sy[8];
+  cplx alpha;
+};
+void axpy_strided(const AxpyDesc& d, hipStream_t s);
+
+void fill(cplx* p, int64_t n, cplx val, hipStream_t s);
+
+}  // namespace rtcc3

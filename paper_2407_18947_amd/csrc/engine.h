@@ -1,0 +1,94 @@
+// Tensor views, an einsum-style contraction engine on the batched MFMA GEMM,
+// and a reverse-mode tape over its operations.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace rtcc3 {
+
+// A strided view into a device buffer owned by the Engine.
+struct View {
+  cplx* p = nullptr;
+  int nd = 0;
+  int64_t sh[8] = {0};
+  int64_t st[8] = {0};
+  int buf = -1;     // owning buffer id (-1: untracked memory)
+  int64_t off = 0;  // element offset of p inside the buffer
+  int64_t numel() const {
+    int64_t n = 1;
+    for (int k = 0; k < nd; ++k) n *= sh[k];
+    return n;
+  }
+};
+
+class Engine {
+ public:
+  explicit Engine(hipStream_t s) : stream(s) {}
+  ~Engine();
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
+
+  hipStream_t stream;
+  int prec = 0;  // GEMM precision used by einsum (0 = FP64)
+
+  // Named buffers, allocated once and reused (get-or-create).
+  int buffer(const std::string& name, int64_t n);
+  View tensor(const std::string& name, std::vector<int64_t> shape);  // contiguous, zeroed on request
+  View tensor_of(int buf, std::vector<int64_t> shape);
+  void zero(const View& v);
+  void zero_buffer(int buf);
+  cplx* data(int buf) { return bufs_[buf].p; }
+  int64_t size(int buf) { return bufs_[buf].n; }
+
+  static View slice(View v, int dim, int64_t lo, int64_t hi);
+  static View permute(View v, std::vector<int> perm);  // out dim d = in dim perm[d]
+  static View diag(View v, int d0, int d1);             // diagonal of dims d0,d1 (equal extents) at d0
+  static View raw(cplx* p, std::vector<int64_t> shape); // untracked contiguous view
+
+  // C += alpha * einsum(spec, A, B).  Every index of A (B) must appear in B (A)
+  // or in C; spec like "ijcd,acbd->ijab".
+  void einsum(const char* spec, cplx alpha, const View& A, const View& B, const View& C);
+  // Y += alpha * X elementwise (same shape; either may be a permuted view).
+  void axpy(cplx alpha, const View& X, const View& Y);
+
+  // Reverse mode.  Buffers flagged with requires_grad propagate the flag to
+  // the outputs of recorded operations; backward() then accumulates
+  // gradients (holomorphic derivatives) into shadow buffers.
+  void set_requires_grad(int buf, bool on);
+  bool requires_grad(int buf) const { return buf >= 0 && bufs_[buf].rg; }
+  View grad(const View& v);
+  void tape_begin();
+  void tape_end() { recording_ = false; }
+  void zero_grads();
+  void backward();
+
+ private:
+  struct Buf {
+    std::string name;
+    cplx* p = nullptr;
+    cplx* g = nullptr;
+    int64_t n = 0;
+    bool rg = false;
+  };
+  struct Op {
+    int kind;  // 0 einsum, 1 axpy
+    std::string spec;
+    cplx alpha;
+    View A, B, C;
+  };
+  std::vector<Buf> bufs_;
+  std::map<std::string, int> names_;
+  std::vector<Op> tape_;
+  bool recording_ = false;
+  cplx* scratch_ = nullptr;
+  int64_t scratch_n_ = 0;
+
+  cplx* scratch(int64_t n);
+  void einsum_exec(const std::string& spec, cplx alpha, const View& A, const View& B, const View& C);
+};
+
+}  // namespace rtcc3

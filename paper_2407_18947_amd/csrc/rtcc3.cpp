@@ -1,0 +1,474 @@
+// C ABI of the RT-CC3 library: context, validation, right-hand side, RK4.
+#include "../../include/rtcc3.h"
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ccsd.h"
+#include "engine.h"
+#include "triples.h"
+
+using namespace rtcc3;
+
+struct rtcc3_ctx {
+  Dims d{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::unique_ptr<Engine> e;
+  std::unique_ptr<Triples> tri;
+  int precision = RTCC3_FP64;
+  int with_triples = 1;
+  int64_t ylen = 0;
+  View B, mu, h0, I, ones_o, h;
+  cplx *y = nullptr, *ytmp = nullptr, *k = nullptr, *acc = nullptr;
+  double last_ms[3] = {0, 0, 0};
+  std::string err;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(rtcc3_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(rtcc3_ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const Error& ex) {
+    return fail(c, ex.code, ex.what());
+  } catch (const std::bad_alloc&) {
+    return fail(c, RTCC3_ENOMEM, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(c, RTCC3_EDEVICE, ex.what());
+  }
+}
+
+constexpr cplx ONE{1.0, 0.0};
+inline cplx C(double re, double im = 0.0) { return cplx{re, im}; }
+
+View sub(cplx* p, int64_t off, std::vector<int64_t> shape) { return Engine::raw(p + off, shape); }
+
+// h = h0 - sum_x E_x mu^x
+void build_h(rtcc3_ctx* c, const double E[3]) {
+  Engine& e = *c->e;
+  const int64_t n = c->d.n;
+  RTCC3_HIP(hipMemcpyAsync(c->h.p, c->h0.p, sizeof(cplx) * n * n, hipMemcpyDeviceToDevice, c->stream));
+  for (int x = 0; x < 3; ++x)
+    if (E[x] != 0.0) e.axpy(C(-E[x]), Engine::raw(c->mu.p + x * n * n, {n, n}), c->h);
+}
+
+struct TermsOut {
+  cplx* terms = nullptr;  // optional rtcc3_rhs_terms layout
+  cplx* mu = nullptr;     // optional dipole (device, 3)
+};
+
+// dy = f(y) at field E; optionally the individual terms and/or the dipole.
+void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const TermsOut& t, bool with_triples) {
+  Engine& e = *c->e;
+  const Dims& d = c->d;
+  const int64_t o = d.o, v = d.v, n = d.n;
+  const int64_t ov = o * v, oovv = o * o * v * v;
+  build_h(c, E);
+  CCSDResult r = ccsd_evaluate(e, d, y, c->h, c->B, c->I, c->ones_o, true);
+  const bool want_density = t.terms || t.mu;
+
+  TriplesOut to;
+  if (with_triples) {
+    to = c->tri->run(e, d, r, y, want_density);
+  }
+
+  if (dy) {
+    fill(dy, c->ylen, cplx{0, 0}, c->stream);
+    View dt1 = sub(dy, 0, {o, v}), dt2 = sub(dy, ov, {o, o, v, v});
+    View dl1 = sub(dy, ov + oovv, {o, v}), dl2 = sub(dy, 2 * ov + oovv, {o, o, v, v});
+    e.axpy(C(0, -1), r.R1, dt1);
+    e.axpy(C(0, -1), r.R2, dt2);
+    e.axpy(C(0, 1), r.G1, dl1);
+    // -i dl2/dt = sym(dL/dt2) / (1/2) = G2 + G2^T(ij,ab)
+    e.axpy(C(0, 1), r.G2, dl2);
+    e.axpy(C(0, 1), Engine::permute(r.G2, {1, 0, 3, 2}), dl2);
+    if (with_triples) {
+      e.axpy(C(0, -1), to.X1, dt1);
+      e.axpy(C(0, -1), to.X2, dt2);
+      e.axpy(C(0, 1), to.Y1, dl1);
+      e.axpy(C(0, 1), to.Y2, dl2);
+    }
+  }
+
+  if (want_density) {
+    // D = D_ccsd + triples terms (T1-transformed frame); mu_x = sum_pq D_pq mu~^x_pq
+    View D = e.tensor("Dtot", {n, n});
+    e.zero(D);
+    e.axpy(ONE, r.Dt, D);
+    if (with_triples) {
+      e.axpy(ONE, to.Dij, Engine::slice(Engine::slice(D, 0, 0, o), 1, 0, o));
+      e.axpy(ONE, to.Dab, Engine::slice(Engine::slice(D, 0, o, n), 1, o, n));
+      e.axpy(ONE, to.Dia, Engine::slice(Engine::slice(D, 0, 0, o), 1, o, n));
+    }
+    View muX = e.tensor("muX", {3, n, n});
+    e.zero(muX);
+    e.einsum("pr,xrs->xps", ONE, r.X, c->mu, muX);
+    View mut = e.tensor("mut", {3, n, n});
+    e.zero(mut);
+    e.einsum("xps,sq->xpq", ONE, muX, r.Y, mut);
+    View m3 = e.tensor("mu3", {3});
+    e.zero(m3);
+    e.einsum("pq,xpq->x", ONE, D, mut, m3);
+    if (t.mu) RTCC3_HIP(hipMemcpyAsync(t.mu, m3.p, sizeof(cplx) * 3, hipMemcpyDeviceToDevice, c->stream));
+    if (t.terms) {
+      cplx* p = t.terms;
+      auto put = [&](const View& src, int64_t len) {
+        if (src.p)
+          RTCC3_HIP(hipMemcpyAsync(p, src.p, sizeof(cplx) * len, hipMemcpyDeviceToDevice, c->stream));
+        else
+          fill(p, len, cplx{0, 0}, c->stream);
+        p += len;
+      };
+      put(r.R1, ov);
+      put(r.R2, oovv);
+      put(r.G1, ov);
+      // G2 reported symmetrised: G2 + G2^T
+      {
+        View g = sub(p, 0, {o, o, v, v});
+        fill(p, oovv, cplx{0, 0}, c->stream);
+        e.axpy(ONE, r.G2, g);
+        e.axpy(ONE, Engine::permute(r.G2, {1, 0, 3, 2}), g);
+        p += oovv;
+      }
+      put(with_triples ? to.X1 : View(), ov);
+      put(with_triples ? to.X2 : View(), oovv);
+      put(with_triples ? to.Y1 : View(), ov);
+      put(with_triples ? to.Y2 : View(), oovv);
+      put(D, n * n);
+      put(m3, 3);
+    }
+  }
+}
+
+bool finite(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// =============================================================================
+
+extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const double* B, const double* dipole,
+                            int precision, void* hip_stream, rtcc3_ctx** out) {
+  if (!out) return fail(nullptr, RTCC3_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (o < 1 || v < 1) return fail(nullptr, RTCC3_EINVAL, "need o >= 1 and v >= 1");
+  if (naux < 1) return fail(nullptr, RTCC3_EINVAL, "need naux >= 1");
+  if (!fock || !B || !dipole) return fail(nullptr, RTCC3_EINVAL, "NULL input array");
+  if (precision != RTCC3_FP64 && precision != RTCC3_FP32) return fail(nullptr, RTCC3_EINVAL, "unknown precision");
+  const int64_t n = (int64_t)o + v;
+  if (n > 4096 || (int64_t)naux * n * n > (int64_t)1 << 34)
+    return fail(nullptr, RTCC3_ENOMEM, "system too large");
+  if (!finite(fock, n * n) || !finite(B, (int64_t)naux * n * n) || !finite(dipole, 3 * n * n))
+    return fail(nullptr, RTCC3_EINVAL, "non-finite input");
+  for (int64_t p = 0; p < n; ++p)
+    for (int64_t q = 0; q < n; ++q)
+      if (p != q && std::fabs(fock[p * n + q]) > 1e-12) return fail(nullptr, RTCC3_EINVAL, "Fock matrix is not diagonal");
+  for (int64_t P = 0; P < naux; ++P)
+    for (int64_t p = 0; p < n; ++p)
+      for (int64_t q = 0; q < p; ++q)
+        if (std::fabs(B[(P * n + p) * n + q] - B[(P * n + q) * n + p]) > 1e-12)
+          return fail(nullptr, RTCC3_EINVAL, "B[P] is not symmetric");
+  for (int x = 0; x < 3; ++x)
+    for (int64_t p = 0; p < n; ++p)
+      for (int64_t q = 0; q < p; ++q)
+        if (std::fabs(dipole[(x * n + p) * n + q] - dipole[(x * n + q) * n + p]) > 1e-12)
+          return fail(nullptr, RTCC3_EINVAL, "dipole matrix is not symmetric");
+  for (int64_t p = 0; p < o; ++p)
+    for (int64_t a = o; a < n; ++a)
+      if (!(fock[p * n + p] < fock[a * n + a]))
+        return fail(nullptr, RTCC3_EINVAL, "occupied orbital energies must lie below the virtual ones");
+
+  std::unique_ptr<rtcc3_ctx> c(new rtcc3_ctx());
+  int rc = guarded(nullptr, [&]() -> int {
+    c->d = Dims{o, v, (int)n, naux};
+    c->precision = precision;
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      RTCC3_HIP(hipStreamCreate(&c->stream));
+      c->own_stream = true;
+    }
+    RTCC3_HIP(hipEventCreate(&c->ev0));
+    RTCC3_HIP(hipEventCreate(&c->ev1));
+    c->e.reset(new Engine(c->stream));
+    Engine& e = *c->e;
+    // constants in complex form
+    std::vector<cplx> hb((size_t)naux * n * n);
+    for (size_t i = 0; i < hb.size(); ++i) hb[i] = cplx{B[i], 0.0};
+    c->B = e.tensor("B", {naux, n, n});
+    RTCC3_HIP(hipMemcpyAsync(c->B.p, hb.data(), sizeof(cplx) * hb.size(), hipMemcpyHostToDevice, c->stream));
+    std::vector<cplx> hm((size_t)3 * n * n);
+    for (size_t i = 0; i < hm.size(); ++i) hm[i] = cplx{dipole[i], 0.0};
+    c->mu = e.tensor("mu", {3, n, n});
+    RTCC3_HIP(hipMemcpyAsync(c->mu.p, hm.data(), sizeof(cplx) * hm.size(), hipMemcpyHostToDevice, c->stream));
+    // h0 = f - sum_i [2 (pq|ii) - (pi|iq)] so that the reference Fock matrix is f
+    std::vector<double> J((size_t)n * n, 0.0), K((size_t)n * n, 0.0), bd(naux, 0.0);
+    for (int64_t P = 0; P < naux; ++P)
+      for (int64_t i = 0; i < o; ++i) bd[P] += B[(P * n + i) * n + i];
+    for (int64_t P = 0; P < naux; ++P) {
+      const double* b = B + P * n * n;
+      for (int64_t p = 0; p < n; ++p)
+        for (int64_t q = 0; q < n; ++q) {
+          J[p * n + q] += b[p * n + q] * bd[P];
+          double s = 0.0;
+          for (int64_t i = 0; i < o; ++i) s += b[p * n + i] * b[i * n + q];
+          K[p * n + q] += s;
+        }
+    }
+    std::vector<cplx> h0((size_t)n * n);
+    for (int64_t p = 0; p < n; ++p)
+      for (int64_t q = 0; q < n; ++q)
+        h0[p * n + q] = cplx{(p == q ? fock[p * n + p] : 0.0) - (2.0 * J[p * n + q] - K[p * n + q]), 0.0};
+    c->h0 = e.tensor("h0", {n, n});
+    RTCC3_HIP(hipMemcpyAsync(c->h0.p, h0.data(), sizeof(cplx) * h0.size(), hipMemcpyHostToDevice, c->stream));
+    c->h = e.tensor("h", {n, n});
+    std::vector<cplx> eye((size_t)n * n, cplx{0, 0});
+    for (int64_t p = 0; p < n; ++p) eye[p * n + p] = cplx{1, 0};
+    c->I = e.tensor("I", {n, n});
+    RTCC3_HIP(hipMemcpyAsync(c->I.p, eye.data(), sizeof(cplx) * eye.size(), hipMemcpyHostToDevice, c->stream));
+    std::vector<cplx> ones(o, cplx{1, 0});
+    c->ones_o = e.tensor("ones_o", {o});
+    RTCC3_HIP(hipMemcpyAsync(c->ones_o.p, ones.data(), sizeof(cplx) * o, hipMemcpyHostToDevice, c->stream));
+    std::vector<double> eps(n);
+    for (int64_t p = 0; p < n; ++p) eps[p] = fock[p * n + p];
+    c->tri.reset(new Triples(e, c->d, eps, precision));
+    c->ylen = 2 * ((int64_t)o * v + (int64_t)o * o * v * v);
+    c->y = e.tensor("y", {c->ylen}).p;
+    c->ytmp = e.tensor("ytmp", {c->ylen}).p;
+    c->k = e.tensor("k", {c->ylen}).p;
+    c->acc = e.tensor("acc", {c->ylen}).p;
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+  if (rc != RTCC3_OK) {
+    g_create_error = c->err.empty() ? g_create_error : c->err;
+    return rc;
+  }
+  *out = c.release();
+  return RTCC3_OK;
+}
+
+extern "C" int rtcc3_set_state(rtcc3_ctx* c, const rtcc3_c64* y, int y_on_device) {
+  if (!c) return RTCC3_EINVAL;
+  if (!y) return fail(c, RTCC3_EINVAL, "y is NULL");
+  return guarded(c, [&]() -> int {
+    if (!y_on_device) {
+      const double* p = (const double*)y;
+      if (!finite(p, 2 * c->ylen)) return fail(c, RTCC3_EINVAL, "non-finite state");
+    }
+    RTCC3_HIP(hipMemcpyAsync(c->y, y, sizeof(cplx) * c->ylen, y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_get_state(rtcc3_ctx* c, rtcc3_c64* y, int y_on_device) {
+  if (!c) return RTCC3_EINVAL;
+  if (!y) return fail(c, RTCC3_EINVAL, "y is NULL");
+  return guarded(c, [&]() -> int {
+    RTCC3_HIP(hipMemcpyAsync(y, c->y, sizeof(cplx) * c->ylen, y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+}
+
+static bool field_ok(const double* E) { return E && std::isfinite(E[0]) && std::isfinite(E[1]) && std::isfinite(E[2]); }
+
+extern "C" int rtcc3_rhs(rtcc3_ctx* c, const double E[3], const rtcc3_c64* y_dev, rtcc3_c64* dy_dev) {
+  if (!c) return RTCC3_EINVAL;
+  if (!field_ok(E)) return fail(c, RTCC3_EINVAL, "field must be 3 finite numbers");
+  if (!y_dev || !dy_dev) return fail(c, RTCC3_EINVAL, "NULL state pointer");
+  return guarded(c, [&]() -> int {
+    rhs_impl(c, E, (const cplx*)y_dev, (cplx*)dy_dev, TermsOut{}, c->with_triples != 0);
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_rhs_terms(rtcc3_ctx* c, const double E[3], const rtcc3_c64* y_dev, rtcc3_c64* terms_dev,
+                               int with_triples) {
+  if (!c) return RTCC3_EINVAL;
+  if (!field_ok(E)) return fail(c, RTCC3_EINVAL, "field must be 3 finite numbers");
+  if (!y_dev || !terms_dev) return fail(c, RTCC3_EINVAL, "NULL pointer");
+  return guarded(c, [&]() -> int {
+    TermsOut t;
+    t.terms = (cplx*)terms_dev;
+    rhs_impl(c, E, (const cplx*)y_dev, nullptr, t, with_triples != 0);
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_dipole(rtcc3_ctx* c, const double E[3], rtcc3_c64 out[3]) {
+  if (!c) return RTCC3_EINVAL;
+  if (!field_ok(E) || !out) return fail(c, RTCC3_EINVAL, "bad argument");
+  return guarded(c, [&]() -> int {
+    View m = c->e->tensor("mu_out", {3});
+    TermsOut t;
+    t.mu = m.p;
+    rhs_impl(c, E, c->y, nullptr, t, c->with_triples != 0);
+    RTCC3_HIP(hipMemcpyAsync(out, m.p, sizeof(cplx) * 3, hipMemcpyDeviceToHost, c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double* field, rtcc3_c64* dipole_out) {
+  if (!c) return RTCC3_EINVAL;
+  if (steps < 0) return fail(c, RTCC3_EINVAL, "steps < 0");
+  if (!(std::isfinite(dt)) || dt == 0.0) return fail(c, RTCC3_EINVAL, "dt must be finite and non-zero");
+  if (!field) return fail(c, RTCC3_EINVAL, "field is NULL");
+  if (!finite(field, (int64_t)(2 * steps + 1) * 3)) return fail(c, RTCC3_EINVAL, "non-finite field");
+  return guarded(c, [&]() -> int {
+    Engine& e = *c->e;
+    const int64_t L = c->ylen;
+    View mus = e.tensor("mu_series", {(int64_t)steps + 1, 3});
+    const bool tri = c->with_triples != 0;
+    View Y = Engine::raw(c->y, {L}), YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}),
+         A = Engine::raw(c->acc, {L});
+    auto copy = [&](cplx* dst, const cplx* src) {
+      RTCC3_HIP(hipMemcpyAsync(dst, src, sizeof(cplx) * L, hipMemcpyDeviceToDevice, c->stream));
+    };
+    c->tri->reset_timing();
+    RTCC3_HIP(hipEventRecord(c->ev0, c->stream));
+    for (int s = 0; s < steps; ++s) {
+      const double* E0 = field + 3 * (2 * s);
+      const double* Eh = field + 3 * (2 * s + 1);
+      const double* E1 = field + 3 * (2 * s + 2);
+      TermsOut t;
+      t.mu = mus.p + 3 * s;
+      rhs_impl(c, E0, c->y, c->k, t, tri);  // k1 (and mu(t_s))
+      copy(c->acc, c->k);
+      copy(c->ytmp, c->y);
+      e.axpy(C(0.5 * dt), K, YT);
+      rhs_impl(c, Eh, c->ytmp, c->k, TermsOut{}, tri);  // k2
+      e.axpy(C(2.0), K, A);
+      copy(c->ytmp, c->y);
+      e.axpy(C(0.5 * dt), K, YT);
+      rhs_impl(c, Eh, c->ytmp, c->k, TermsOut{}, tri);  // k3
+      e.axpy(C(2.0), K, A);
+      copy(c->ytmp, c->y);
+      e.axpy(C(dt), K, YT);
+      rhs_impl(c, E1, c->ytmp, c->k, TermsOut{}, tri);  // k4
+      e.axpy(ONE, K, A);
+      e.axpy(C(dt / 6.0), A, Y);
+    }
+    {
+      TermsOut t;
+      t.mu = mus.p + 3 * steps;
+      rhs_impl(c, field + 3 * (2 * steps), c->y, nullptr, t, tri);
+    }
+    RTCC3_HIP(hipEventRecord(c->ev1, c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    RTCC3_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms[0] = ms;
+    c->tri->timing(c->last_ms[1], c->last_ms[2]);
+    std::vector<cplx> mh((size_t)(steps + 1) * 3);
+    RTCC3_HIP(hipMemcpy(mh.data(), mus.p, sizeof(cplx) * mh.size(), hipMemcpyDeviceToHost));
+    if (dipole_out) std::memcpy(dipole_out, mh.data(), sizeof(cplx) * mh.size());
+    for (auto& z : mh)
+      if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(c, RTCC3_EDIVERGED, "state became non-finite");
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
+  if (!c) return RTCC3_EINVAL;
+  if (option == RTCC3_OPT_TRIPLES) {
+    c->with_triples = value ? 1 : 0;
+    return RTCC3_OK;
+  }
+  if (option == RTCC3_OPT_PRECISION) {
+    if (value != RTCC3_FP64 && value != RTCC3_FP32) return fail(c, RTCC3_EINVAL, "unknown precision");
+    c->precision = value;
+    c->tri->set_precision(value);
+    return RTCC3_OK;
+  }
+  return fail(c, RTCC3_EINVAL, "unknown option");
+}
+
+extern "C" int rtcc3_last_timing(rtcc3_ctx* c, double kernel_ms[3]) {
+  if (!c || !kernel_ms) return RTCC3_EINVAL;
+  for (int i = 0; i < 3; ++i) kernel_ms[i] = c->last_ms[i];
+  return RTCC3_OK;
+}
+
+extern "C" const char* rtcc3_last_error(const rtcc3_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  c->tri.reset();
+  c->e.reset();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rtcc3_c64* A, const rtcc3_c64* B,
+                                    rtcc3_c64* Cout) {
+  if (M < 1 || N < 1 || K < 1 || !A || !B || !Cout) return fail(nullptr, RTCC3_EINVAL, "bad gemm arguments");
+  if (precision != RTCC3_FP64 && precision != RTCC3_FP32) return fail(nullptr, RTCC3_EINVAL, "unknown precision");
+  if ((int64_t)M * K > (1LL << 28) || (int64_t)K * N > (1LL << 28) || (int64_t)M * N > (1LL << 28))
+    return fail(nullptr, RTCC3_EINVAL, "gemm self-test too large");
+  cplx *dA = nullptr, *dB = nullptr, *dC = nullptr;
+  int rc = guarded(nullptr, [&]() -> int {
+    RTCC3_HIP(hipMalloc(&dA, sizeof(cplx) * M * K));
+    RTCC3_HIP(hipMalloc(&dB, sizeof(cplx) * K * N));
+    RTCC3_HIP(hipMalloc(&dC, sizeof(cplx) * M * N));
+    RTCC3_HIP(hipMemcpy(dA, A, sizeof(cplx) * M * K, hipMemcpyHostToDevice));
+    RTCC3_HIP(hipMemcpy(dB, B, sizeof(cplx) * K * N, hipMemcpyHostToDevice));
+    RTCC3_HIP(hipMemset(dC, 0, sizeof(cplx) * M * N));
+    GemmDesc g;
+    std::memset(&g, 0, sizeof(g));
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.M0 = M;
+    g.N0 = N;
+    g.K0 = K;
+    g.batch = 1;
+    g.A = dA;
+    g.sAm0 = K;
+    g.sAk0 = 1;
+    g.B = dB;
+    g.sBk0 = N;
+    g.sBn0 = 1;
+    g.C = dC;
+    g.sCm0 = N;
+    g.sCn0 = 1;
+    g.alpha = cplx{1, 0};
+    g.prec = precision;
+    gemm(g, nullptr);
+    RTCC3_HIP(hipDeviceSynchronize());
+    RTCC3_HIP(hipMemcpy(Cout, dC, sizeof(cplx) * M * N, hipMemcpyDeviceToHost));
+    return RTCC3_OK;
+  });
+  if (dA) (void)hipFree(dA);
+  if (dB) (void)hipFree(dB);
+  if (dC) (void)hipFree(dC);
+  return rc;
+}

@@ -1,0 +1,775 @@
+// Triples engine: for windows of ordered occupied triples (i,j,k), build the
+// [v,v,v] blocks
+//   t_ijk   = P_ijk^abc { sum_e t_ij^ae <cb|ke>~ - sum_m t_im^ab <mc|jk>~ } / D_ijk^abc
+//                                         (eq. cc3-t3-no-pert, spin-adapted form in App. A)
+//   lambda_ijk = P_ijk^abc { ... } / D_ijk^abc   (eq. cc3-l3-exp with the denominator of eq. cc3-l3)
+// on the matrix cores, keep them only for the window, and contract them into
+// X1, X2 (eq. cc3-x1-exp, cc3-x2-exp), Y1, Y2 (eq. cc3-y1-exp, cc3-y2-exp) and,
+// on request, the density terms (eq. cc3-dij and the two after it).
+//
+// Y1 uses intermediates accumulated over all blocks and contracted once at the
+// end (the factorisation strategy of Sec. 4.1).  The sixth t3.lambda2 term is
+// taken with L_kjab and the tenth with <di|lb>, the readings under which the
+// printed Y1 equals the derivative of the Lagrangian.
+#include "triples.h"
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "triples_kernels.h"
+
+namespace rtcc3 {
+
+namespace {
+
+constexpr cplx ONE{1.0, 0.0};
+inline cplx R(double x) { return cplx{x, 0.0}; }
+
+GemmDesc base(int M, int N, int K, int nb, const int* bl, int prec) {
+  GemmDesc g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.M0 = M;
+  g.N0 = N;
+  g.K0 = K;
+  g.batch = nb;
+  g.bl = bl;
+  g.alpha = ONE;
+  g.prec = prec;
+  return g;
+}
+
+// Upper bound of the element offset reached by an index of extent X split as
+// (X/X0, X0) with strides (s1, s0).
+int64_t span(int64_t X, int64_t X0, int64_t s1, int64_t s0) {
+  if (X <= 0) return 0;
+  RTCC3_CHECK(s1 >= 0 && s0 >= 0, "triples: negative stride");
+  RTCC3_CHECK(X % X0 == 0, "triples: split does not divide the extent");
+  return (X / X0 - 1) * s1 + (X0 - 1) * s0;
+}
+
+// Launch a GEMM after checking, on the host, that every batch entry stays
+// inside the operand buffers (lengths in elements).
+void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
+  if (g.batch <= 0) return;
+  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + span(g.K, g.K0, g.sAk1, g.sAk0);
+  const int64_t eB = span(g.K, g.K0, g.sBk1, g.sBk0) + span(g.N, g.N0, g.sBn1, g.sBn0);
+  const int64_t eC = span(g.M, g.M0, g.sCm1, g.sCm0) + span(g.N, g.N0, g.sCn1, g.sCn0);
+  for (int b = 0; b < g.batch; ++b) {
+    int64_t oA, oB, oC;
+    if (g.bl) {
+      const int* q = bl_host + 4 * b;
+      oA = g.cA[0] * q[0] + g.cA[1] * q[1] + g.cA[2] * q[2] + g.cA[3] * q[3];
+      oB = g.cB[0] * q[0] + g.cB[1] * q[1] + g.cB[2] * q[2] + g.cB[3] * q[3];
+      oC = g.cC[0] * q[0] + g.cC[1] * q[1] + g.cC[2] * q[2] + g.cC[3] * q[3];
+    } else {
+      oA = b * g.sAb;
+      oB = b * g.sBb;
+      oC = b * g.sCb;
+    }
+    RTCC3_CHECK(oA >= 0 && oA + eA < lenA, "triples: A operand out of bounds");
+    RTCC3_CHECK(oB >= 0 && oB + eB < lenB, "triples: B operand out of bounds");
+    RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
+  }
+  gemm(g, s);
+}
+
+void set4(int64_t* c, int64_t a, int64_t b, int64_t d, int64_t n) {
+  c[0] = a;
+  c[1] = b;
+  c[2] = d;
+  c[3] = n;
+}
+
+}  // namespace
+
+Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int precision) : d_(d), prec_(precision) {
+  RTCC3_HIP(hipMalloc(&eps_, sizeof(double) * eps.size()));
+  RTCC3_HIP(hipMemcpy(eps_, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice));
+  build_windows();
+  for (auto& w : rhs_windows_) upload(w);
+  for (auto& w : den_windows_) upload(w);
+  (void)e;
+}
+
+Triples::~Triples() {
+  for (auto* ws : {&rhs_windows_, &den_windows_})
+    for (auto& w : *ws) {
+      if (w.d_bl) (void)hipFree(w.d_bl);
+      if (w.d_part) (void)hipFree(w.d_part);
+      if (w.d_owned) (void)hipFree(w.d_owned);
+    }
+  if (eps_) (void)hipFree(eps_);
+}
+
+namespace {
+
+std::vector<std::array<int, 3>> orderings(int x, int y, int z) {
+  std::array<int, 3> t{x, y, z};
+  std::sort(t.begin(), t.end());
+  std::vector<std::array<int, 3>> out;
+  do out.push_back(t);
+  while (std::next_permutation(t.begin(), t.end()));
+  return out;
+}
+
+void finish_window(Window& w, const std::vector<std::array<int, 3>>& blocks) {
+  std::map<std::array<int, 3>, int> idx;
+  for (int n = 0; n < (int)blocks.size(); ++n) idx[blocks[n]] = n;
+  w.nw = (int)blocks.size();
+  w.bl.resize(4 * w.nw);
+  w.part.resize(6 * w.nw);
+  for (int n = 0; n < w.nw; ++n) {
+    const int I = blocks[n][0], J = blocks[n][1], K = blocks[n][2];
+    w.bl[4 * n] = I;
+    w.bl[4 * n + 1] = J;
+    w.bl[4 * n + 2] = K;
+    w.bl[4 * n + 3] = n;
+    const std::array<int, 3> ps[6] = {{I, J, K}, {J, I, K}, {I, K, J}, {K, J, I}, {K, I, J}, {J, K, I}};
+    for (int s = 0; s < 6; ++s) {
+      auto it = idx.find(ps[s]);
+      RTCC3_CHECK(it != idx.end(), "triples: window not closed under permutation");
+      w.part[6 * n + s] = it->second;
+    }
+  }
+}
+
+}  // namespace
+
+void Triples::build_windows() {
+  const int o = d_.o;
+  const int64_t v3 = (int64_t)d_.v * d_.v * d_.v;
+  // Four window buffers of nw blocks each; keep them within a 4 GiB budget.
+  const int64_t budget = (int64_t)4 << 30;
+  int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * v3));
+  // ---- RHS windows: canonical triples i <= j <= k with all their orderings
+  std::vector<std::array<int, 3>> cur;
+  auto flush = [&]() {
+    if (cur.empty()) return;
+    Window w;
+    finish_window(w, cur);
+    rhs_windows_.push_back(w);
+    cur.clear();
+  };
+  for (int i = 0; i < o; ++i)
+    for (int j = i; j < o; ++j)
+      for (int k = j; k < o; ++k) {
+        auto ords = orderings(i, j, k);
+        if ((int)(cur.size() + ords.size()) > wmax) flush();
+        for (auto& t : ords) cur.push_back(t);
+      }
+  flush();
+  // ---- density windows: for each pair l <= k, all orderings of {i,l,k} for every i,
+  // with the slabs (i,l,k) and (i,k,l) first and in order of i.
+  for (int l = 0; l < o; ++l)
+    for (int k = l; k < o; ++k) {
+      std::vector<std::array<int, 3>> bl;
+      std::map<std::array<int, 3>, int> seen;
+      auto add = [&](std::array<int, 3> t) {
+        if (seen.count(t)) return;
+        seen[t] = (int)bl.size();
+        bl.push_back(t);
+      };
+      for (int i = 0; i < o; ++i) add({i, l, k});
+      if (l != k)
+        for (int i = 0; i < o; ++i) add({i, k, l});
+      for (int i = 0; i < o; ++i)
+        for (auto& t : orderings(i, l, k)) add(t);
+      Window w;
+      finish_window(w, bl);
+      w.slab_lk[0] = l;
+      w.slab_lk[1] = k;
+      w.slab_start[0] = 0;
+      w.slab_start[1] = (l != k) ? o : -1;
+      // blocks owned by this window: orderings of {i,l,k} whose two smallest
+      // indices are (l,k), i.e. i >= k
+      for (int i = k; i < o; ++i)
+        for (auto& t : orderings(i, l, k)) {
+          const int n = seen.at(t);
+          w.owned.insert(w.owned.end(), {t[0], t[1], t[2], n});
+        }
+      den_windows_.push_back(w);
+    }
+  max_nw_ = 0;
+  for (auto& w : rhs_windows_) max_nw_ = std::max(max_nw_, w.nw);
+  for (auto& w : den_windows_) max_nw_ = std::max(max_nw_, w.nw);
+}
+
+void Triples::upload(Window& w) {
+  RTCC3_HIP(hipMalloc(&w.d_bl, sizeof(int) * w.bl.size()));
+  RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
+  RTCC3_HIP(hipMalloc(&w.d_part, sizeof(int) * w.part.size()));
+  RTCC3_HIP(hipMemcpy(w.d_part, w.part.data(), sizeof(int) * w.part.size(), hipMemcpyHostToDevice));
+  if (!w.owned.empty()) {
+    RTCC3_HIP(hipMalloc(&w.d_owned, sizeof(int) * w.owned.size()));
+    RTCC3_HIP(hipMemcpy(w.d_owned, w.owned.data(), sizeof(int) * w.owned.size(), hipMemcpyHostToDevice));
+  }
+}
+
+// T1-transformed integral blocks in the layouts the triples contractions read.
+void Triples::blocks(Engine& e, const CCSDResult& r) {
+  const int64_t o = d_.o, v = d_.v, n = d_.n;
+  auto B = [&](char a, char b) {
+    return Engine::slice(Engine::slice(r.Bt, 1, a == 'o' ? 0 : o, a == 'o' ? o : n), 2, b == 'o' ? 0 : o,
+                         b == 'o' ? o : n);
+  };
+  auto make = [&](const char* name, std::vector<int64_t> shape) {
+    View t = e.tensor(name, shape);
+    e.zero(t);
+    return t;
+  };
+  View t;
+  t = make("tb_W1", {o, v, v, v});  // (ck|be) at [k][b][c][e]
+  e.einsum("Pck,Pbe->kbce", ONE, B('v', 'o'), B('v', 'v'), t);
+  t = make("tb_W2", {o, o, o, v});  // (mj|ck) at [j][k][m][c]
+  e.einsum("Pmj,Pck->jkmc", ONE, B('o', 'o'), B('v', 'o'), t);
+  t = make("tb_LA", {o, v, v, v});  // (ka|db) at [k][a][b][d]
+  e.einsum("Pka,Pdb->kabd", ONE, B('o', 'v'), B('v', 'v'), t);
+  t = make("tb_LB", {o, v, v, v});  // 2(da|jb) - (db|ja) at [j][a][b][d]
+  e.einsum("Pda,Pjb->jabd", R(2), B('v', 'v'), B('o', 'v'), t);
+  e.einsum("Pdb,Pja->jabd", R(-1), B('v', 'v'), B('o', 'v'), t);
+  t = make("tb_LC", {o, v, o, o});  // (ka|jl) at [k][a][j][l]
+  e.einsum("Pka,Pjl->kajl", ONE, B('o', 'v'), B('o', 'o'), t);
+  t = make("tb_LD", {o, o, v, o});  // 2(ia|jl) - (il|ja) at [i][j][a][l]
+  e.einsum("Pia,Pjl->ijal", R(2), B('o', 'v'), B('o', 'o'), t);
+  e.einsum("Pil,Pja->ijal", R(-1), B('o', 'o'), B('o', 'v'), t);
+  t = make("tb_X2a", {o, v, v, v});  // (ac|ke) at [k][a][c][e]
+  e.einsum("Pac,Pke->kace", ONE, B('v', 'v'), B('o', 'v'), t);
+  t = make("tb_X2b", {o, o, o, v});  // (ki|mc) at [k][m][i][c]
+  e.einsum("Pki,Pmc->kmic", ONE, B('o', 'o'), B('o', 'v'), t);
+  t = make("tb_Y2a", {o, v, v, v});  // (da|el) at [l][a][d][e]
+  e.einsum("Pda,Pel->lade", ONE, B('v', 'v'), B('v', 'o'), t);
+  t = make("tb_Y2b", {o, o, o, v});  // (xi|dk) at [i][k][x][d]
+  e.einsum("Pxi,Pdk->ikxd", ONE, B('o', 'o'), B('v', 'o'), t);
+  t = make("tb_G1", {o, o, v, v});  // (xc|jd) at [j][x][c][d]
+  e.einsum("Pxc,Pjd->jxcd", ONE, B('o', 'v'), B('o', 'v'), t);
+  t = make("tb_G5", {o, o, v, v});  // L_jbxc = 2(jb|xc) - (jc|xb) at [j][x][b][c]
+  e.einsum("Pjb,Pxc->jxbc", R(2), B('o', 'v'), B('o', 'v'), t);
+  e.einsum("Pjc,Pxb->jxbc", R(-1), B('o', 'v'), B('o', 'v'), t);
+  t = make("tb_G9", {o, o, v, v});  // (xl|db) at [l][x][d][b]
+  e.einsum("Pxl,Pdb->lxdb", ONE, B('o', 'o'), B('v', 'v'), t);
+  t = make("tb_G10", {o, o, v, v});  // (dl|xb) at [l][x][d][b]
+  e.einsum("Pdl,Pxb->lxdb", ONE, B('v', 'o'), B('o', 'v'), t);
+}
+
+void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_terms, bool density_terms) {
+  const int o = d_.o, v = d_.v;
+  const int64_t v2 = (int64_t)v * v, v3 = v2 * v, ov = (int64_t)o * v, oovv = (int64_t)o * o * v2;
+  const int64_t ylen = 2 * (ov + oovv);
+  const int nw = w.nw;
+  hipStream_t s = e.stream;
+  const cplx* t2 = y + ov;
+  const cplx* l1 = y + ov + oovv;
+  const cplx* l2 = y + 2 * ov + oovv;
+  const int64_t t2len = oovv, l2len = oovv;
+  (void)ylen;
+  const int64_t winlen = (int64_t)max_nw_ * v3;
+  cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, v}).p;
+  cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, v}).p;
+  cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, v}).p;
+  cplx* Z = e.tensor("tw_Z", {(int64_t)max_nw_, v, v, v}).p;
+  cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
+  auto P = [&](const char* name, std::vector<int64_t> shape) { return e.tensor(name, shape).p; };
+  const cplx* gW1 = P("tb_W1", {o, v, v, v});
+  const cplx* gW2 = P("tb_W2", {o, o, o, v});
+  const cplx* gLA = P("tb_LA", {o, v, v, v});
+  const cplx* gLB = P("tb_LB", {o, v, v, v});
+  const cplx* gLC = P("tb_LC", {o, v, o, o});
+  const cplx* gLD = P("tb_LD", {o, o, v, o});
+  const cplx* gX2a = P("tb_X2a", {o, v, v, v});
+  const cplx* gX2b = P("tb_X2b", {o, o, o, v});
+  const cplx* gY2a = P("tb_Y2a", {o, v, v, v});
+  const cplx* gY2b = P("tb_Y2b", {o, o, o, v});
+  const cplx* gG1 = P("tb_G1", {o, o, v, v});
+  const cplx* gG5 = P("tb_G5", {o, o, v, v});
+  const cplx* gG9 = P("tb_G9", {o, o, v, v});
+  const cplx* gG10 = P("tb_G10", {o, o, v, v});
+  const cplx* Lov = P("Lov", {o, v, o, v});
+  const cplx* F = P("F", {(int64_t)d_.n, (int64_t)d_.n});
+  const int64_t lOVVV = (int64_t)o * v3, lOOOV = (int64_t)o * o * o * v, lOOVV = oovv;
+  const int* bl = w.d_bl;
+  const int* blh = w.bl.data();
+  const int pr = prec_;
+
+  // ---------------- t3 blocks
+  fill(W, (int64_t)nw * v3, cplx{0, 0}, s);
+  {  // W[n][a][(b,c)] += sum_e t2[I][J][a][e] (ck|be)~[K][(b,c)][e]
+    GemmDesc g = base(v, (int)v2, v, nw, bl, pr);
+    g.A = t2;
+    g.sAm0 = v;
+    g.sAk0 = 1;
+    set4(g.cA, (int64_t)o * v2, v2, 0, 0);
+    g.B = gW1;
+    g.sBk0 = 1;
+    g.sBn0 = v;
+    set4(g.cB, 0, 0, v3, 0);
+    g.C = W;
+    g.sCm0 = v2;
+    g.sCn0 = 1;
+    set4(g.cC, 0, 0, 0, v3);
+    checked_gemm(g, blh, t2len, lOVVV, winlen, s);
+  }
+  {  // W[n][(a,b)][c] -= sum_m t2[I][m][(a,b)] (mj|ck)~[J][K][m][c]
+    GemmDesc g = base((int)v2, v, o, nw, bl, pr);
+    g.alpha = R(-1);
+    g.A = t2;
+    g.sAm0 = 1;
+    g.sAk0 = v2;
+    set4(g.cA, (int64_t)o * v2, 0, 0, 0);
+    g.B = gW2;
+    g.sBk0 = v;
+    g.sBn0 = 1;
+    set4(g.cB, 0, (int64_t)o * o * v, (int64_t)o * v, 0);
+    g.C = W;
+    g.sCm0 = v;
+    g.sCn0 = 1;
+    set4(g.cC, 0, 0, 0, v3);
+    checked_gemm(g, blh, t2len, lOOOV, winlen, s);
+  }
+  launch_sym_div(W, T, w.d_part, bl, eps_, o, v, nw, s);
+
+  // ---------------- lambda3 blocks
+  fill(W, (int64_t)nw * v3, cplx{0, 0}, s);
+  {  // W[n][(a,b)][c] -= sum_d (ka|db)~[K][(a,b)][d] l2[I][J][c][d]
+    GemmDesc g = base((int)v2, v, v, nw, bl, pr);
+    g.alpha = R(-1);
+    g.A = gLA;
+    g.sAm0 = v;
+    g.sAk0 = 1;
+    set4(g.cA, 0, 0, v3, 0);
+    g.B = l2;
+    g.sBk0 = 1;
+    g.sBn0 = v;
+    set4(g.cB, (int64_t)o * v2, v2, 0, 0);
+    g.C = W;
+    g.sCm0 = v;
+    g.sCn0 = 1;
+    set4(g.cC, 0, 0, 0, v3);
+    checked_gemm(g, blh, lOVVV, l2len, winlen, s);
+    // W[n][(a,b)][c] += sum_d Lt_djab[J][(a,b)][d] l2[K][I][c][d]
+    g.alpha = ONE;
+    g.A = gLB;
+    set4(g.cA, 0, v3, 0, 0);
+    set4(g.cB, v2, 0, (int64_t)o * v2, 0);
+    checked_gemm(g, blh, lOVVV, l2len, winlen, s);
+  }
+  {  // W[n][a][(b,c)] += sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)]
+    GemmDesc g = base(v, (int)v2, o, nw, bl, pr);
+    g.A = gLC;
+    g.sAm0 = (int64_t)o * o;
+    g.sAk0 = 1;
+    set4(g.cA, 0, o, (int64_t)v * o * o, 0);
+    g.B = l2;
+    g.sBk0 = (int64_t)o * v2;
+    g.sBn0 = 1;
+    set4(g.cB, v2, 0, 0, 0);
+    g.C = W;
+    g.sCm0 = v2;
+    g.sCn0 = 1;
+    set4(g.cC, 0, 0, 0, v3);
+    checked_gemm(g, blh, (int64_t)o * v * o * o, l2len, winlen, s);
+    // W[n][a][(b,c)] -= sum_l Lt_ijal[I][J][a][l] l2[l][K][(b,c)]
+    g.alpha = R(-1);
+    g.A = gLD;
+    g.sAm0 = o;
+    set4(g.cA, (int64_t)o * v * o, (int64_t)v * o, 0, 0);
+    set4(g.cB, 0, 0, v2, 0);
+    checked_gemm(g, blh, (int64_t)o * o * v * o, l2len, winlen, s);
+  }
+  launch_lam_elem(W, bl, Lov, F, l1, l2, o, v, nw, s);
+  launch_sym_div(W, L, w.d_part, bl, eps_, o, v, nw, s);
+  launches_ += 10;
+
+  if (rhs_terms) {
+    cplx* X1 = P("tr_X1", {o, v});
+    cplx* X2p = P("tr_X2p", {o, o, v, v});
+    cplx* Y1 = P("tr_Y1", {o, v});
+    cplx* Y2p = P("tr_Y2p", {o, o, v, v});
+    cplx* Z34 = P("tr_Z34", {o, v});
+    cplx* R15 = P("tr_R15", {o, o, v, o});
+    cplx* R2t = P("tr_R2", {o, o, v, o});
+    cplx* R6 = P("tr_R6", {o, o, v, o});
+    cplx* R7 = P("tr_R7", {o, o, v, o});
+    cplx* R8 = P("tr_R8", {o, o, v, o});
+    cplx* Zi = P("tr_Zi", {o, v, v, v});
+    cplx* R12 = P("tr_R12", {o, o, o, v});
+    const int64_t lR = (int64_t)o * o * v * o;
+
+    // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ with Z1 = 2t[c,b,e] - t[c,e,b] - t[e,b,c]
+    launch_comb(T, Z, bl, v, nw, 0, s);
+    {
+      GemmDesc g = base(v, v, (int)v2, nw, bl, pr);
+      g.atomic = 1;
+      g.A = gX2a;
+      g.sAm0 = v2;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, v3, 0);
+      g.B = Z;
+      g.sBk0 = 1;
+      g.sBn0 = v2;
+      set4(g.cB, 0, 0, 0, v3);
+      g.C = X2p;
+      g.sCm0 = v;
+      g.sCn0 = 1;
+      set4(g.cC, (int64_t)o * v2, v2, 0, 0);
+      checked_gemm(g, blh, lOVVV, winlen, oovv, s);
+    }
+    // X2: -sum_c Zh[(a,b)][c] (Ki|Ic)~ into X2p[x][J] with Zh = 2t[c,b,a] - t[b,c,a] - t[a,b,c]
+    launch_comb(T, Z, bl, v, nw, 1, s);
+    {
+      GemmDesc g = base((int)v2, o, v, nw, bl, pr);
+      g.atomic = 1;
+      g.alpha = R(-1);
+      g.A = Z;
+      g.sAm0 = v;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = gX2b;
+      g.sBk0 = 1;
+      g.sBn0 = v;
+      set4(g.cB, (int64_t)o * v, 0, (int64_t)o * o * v, 0);
+      g.C = X2p;
+      g.sCm0 = 1;
+      g.sCn0 = (int64_t)o * v2;
+      set4(g.cC, 0, v2, 0, 0);
+      checked_gemm(g, blh, winlen, lOOOV, oovv, s);
+    }
+    // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1)
+    launch_small_t3(T, bl, nw, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
+    {  // Y2: sum_de (da|eK)~ lambda[d][b][e] into Y2p[I][J][a][b]
+      GemmDesc g = base(v, v, (int)v2, nw, bl, pr);
+      g.atomic = 1;
+      g.K0 = v;
+      g.A = gY2a;
+      g.sAm0 = v2;
+      g.sAk1 = v;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, v3, 0);
+      g.B = L;
+      g.sBk1 = v2;
+      g.sBk0 = 1;
+      g.sBn0 = v;
+      set4(g.cB, 0, 0, 0, v3);
+      g.C = Y2p;
+      g.sCm0 = v;
+      g.sCn0 = 1;
+      set4(g.cC, (int64_t)o * v2, v2, 0, 0);
+      checked_gemm(g, blh, lOVVV, winlen, oovv, s);
+    }
+    {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J]
+      GemmDesc g = base((int)v2, o, v, nw, bl, pr);
+      g.atomic = 1;
+      g.alpha = R(-1);
+      g.A = L;
+      g.sAm0 = v;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = gY2b;
+      g.sBk0 = 1;
+      g.sBn0 = v;
+      set4(g.cB, (int64_t)o * o * v, 0, (int64_t)o * v, 0);
+      g.C = Y2p;
+      g.sCm0 = 1;
+      g.sCn0 = (int64_t)o * v2;
+      set4(g.cC, 0, v2, 0, 0);
+      checked_gemm(g, blh, winlen, lOOOV, oovv, s);
+    }
+    // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates over (b,x)
+    auto tl = [&](const cplx* Bp, int64_t lenB, int64_t sbk, int64_t sbn, const int64_t* cb, cplx* Cp,
+                  const int64_t* cc, double alpha, bool tmajor) {
+      // C[b][x] += alpha * sum_{(c,d)} t[b][(c,d)] B[(c,d)][x]   (tmajor: t[n][b][cd])
+      // or, !tmajor: C[d][x] += alpha * sum_{(b,c)} t[(b,c)][d] B[(b,c)][x]
+      GemmDesc g = base(v, o, (int)v2, nw, bl, pr);
+      g.atomic = 1;
+      g.alpha = R(alpha);
+      g.A = T;
+      g.sAm0 = tmajor ? v2 : 1;
+      g.sAk0 = tmajor ? 1 : v;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = Bp;
+      g.sBk0 = sbk;
+      g.sBn0 = sbn;
+      std::memcpy(g.cB, cb, sizeof(g.cB));
+      g.C = Cp;
+      g.sCm0 = o;
+      g.sCn0 = 1;
+      std::memcpy(g.cC, cc, sizeof(g.cC));
+      checked_gemm(g, blh, winlen, lenB, lR, s);
+    };
+    {
+      const int64_t cb1[4] = {(int64_t)o * v2, 0, 0, 0}, cc1[4] = {0, (int64_t)o * v * o, (int64_t)v * o, 0};
+      tl(gG1, lOOVV, 1, v2, cb1, R15, cc1, 1.0, true);    // term 1: (xc|Id)
+      tl(gG5, lOOVV, 1, v2, cb1, R15, cc1, -1.0, false);  // term 5: L_Ibxc
+      const int64_t cb2[4] = {v2, 0, 0, 0};
+      tl(l2, l2len, 1, (int64_t)o * v2, cb2, R2t, cc1, 1.0, true);  // term 2: l2[x][I]
+      const int64_t cb6[4] = {0, 0, v2, 0}, cc6[4] = {(int64_t)o * v * o, (int64_t)v * o, 0, 0};
+      tl(l2, l2len, 1, (int64_t)o * v2, cb6, R6, cc6, 1.0, true);  // term 6: l2[x][K]
+    }
+    {  // terms 7, 8: Q[d][j] = sum_bc lambda[(b,c)][d] t2[j][J][(b,c)] into R7[K][I], R8[I][K]
+      GemmDesc g = base(v, o, (int)v2, nw, bl, pr);
+      g.atomic = 1;
+      g.A = L;
+      g.sAm0 = 1;
+      g.sAk0 = v;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = t2;
+      g.sBk0 = 1;
+      g.sBn0 = (int64_t)o * v2;
+      set4(g.cB, 0, v2, 0, 0);
+      g.C = R7;
+      g.sCm0 = o;
+      g.sCn0 = 1;
+      set4(g.cC, (int64_t)v * o, 0, (int64_t)o * v * o, 0);
+      checked_gemm(g, blh, winlen, t2len, lR, s);
+      g.C = R8;
+      set4(g.cC, (int64_t)o * v * o, 0, (int64_t)v * o, 0);
+      checked_gemm(g, blh, winlen, t2len, lR, s);
+    }
+    {  // terms 9, 10: S[n][c][d][x] = sum_b t2[K][J][b][c] (xI|db)~ + sum_b t2[I][J][b][c] (dK|xb)~
+      fill(S, (int64_t)nw * v2 * o, cplx{0, 0}, s);
+      GemmDesc g = base(v, (int)(o * v), v, nw, bl, pr);
+      g.N0 = v;
+      g.A = t2;
+      g.sAm0 = 1;
+      g.sAk0 = v;
+      set4(g.cA, 0, v2, (int64_t)o * v2, 0);
+      g.B = gG9;
+      g.sBk0 = 1;
+      g.sBn1 = v2;
+      g.sBn0 = v;
+      set4(g.cB, (int64_t)o * v2, 0, 0, 0);
+      g.C = S;
+      g.sCm0 = (int64_t)v * o;
+      g.sCn1 = 1;
+      g.sCn0 = o;
+      set4(g.cC, 0, 0, 0, v2 * o);
+      const int64_t lS = (int64_t)max_nw_ * v2 * o;
+      checked_gemm(g, blh, t2len, lOOVV, lS, s);
+      set4(g.cA, (int64_t)o * v2, v2, 0, 0);
+      g.B = gG10;
+      set4(g.cB, 0, 0, (int64_t)o * v2, 0);
+      checked_gemm(g, blh, t2len, lOOVV, lS, s);
+      // Y1[x][a] -= sum_{n,(c,d)} S[n][(c,d)][x] lambda[n][a][(c,d)], split over chunks of blocks
+      const int CH = 8;
+      const int full = nw / CH, tail = nw % CH;
+      auto ylaunch = [&](int first, int nblk, int nbatch) {
+        if (nbatch <= 0 || nblk <= 0) return;
+        GemmDesc h = base(o, v, (int)(nblk * v2), nbatch, nullptr, pr);
+        h.atomic = 1;
+        h.alpha = R(-1);
+        h.K0 = (int)v2;
+        h.A = S + (int64_t)first * v2 * o;
+        h.sAm0 = 1;
+        h.sAk1 = v2 * o;
+        h.sAk0 = o;
+        h.sAb = (int64_t)nblk * v2 * o;
+        h.B = L + (int64_t)first * v3;
+        h.sBk1 = v3;
+        h.sBk0 = 1;
+        h.sBn0 = v2;
+        h.sBb = (int64_t)nblk * v3;
+        h.C = Y1;
+        h.sCm0 = v;
+        h.sCn0 = 1;
+        h.sCb = 0;
+        checked_gemm(h, nullptr, lS - (int64_t)first * v2 * o, winlen - (int64_t)first * v3, ov, s);
+      };
+      ylaunch(0, CH, full);
+      ylaunch(full * CH, tail, 1);
+    }
+    {  // term 11: Zi[J][(d,e)][b] += sum_c lambda[c][(d,e)] t2[K][I][b][c]   (block (k,i,j) = (I,J,K))
+      GemmDesc g = base((int)v2, v, v, nw, bl, pr);
+      g.atomic = 1;
+      g.A = L;
+      g.sAm0 = 1;
+      g.sAk0 = v2;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = t2;
+      g.sBk0 = 1;
+      g.sBn0 = v;
+      set4(g.cB, v2, 0, (int64_t)o * v2, 0);
+      g.C = Zi;
+      g.sCm0 = v;
+      g.sCn0 = 1;
+      set4(g.cC, 0, v3, 0, 0);
+      checked_gemm(g, blh, winlen, t2len, lOVVV, s);
+    }
+    {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
+      GemmDesc g = base(o, v, (int)v2, nw, bl, pr);
+      g.atomic = 1;
+      g.A = t2;
+      g.sAm0 = (int64_t)o * v2;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, v2, 0);
+      g.B = L;
+      g.sBk0 = 1;
+      g.sBn0 = v2;
+      set4(g.cB, 0, 0, 0, v3);
+      g.C = R12;
+      g.sCm0 = (int64_t)o * v;
+      g.sCn0 = 1;
+      set4(g.cC, (int64_t)o * o * v, v, 0, 0);
+      checked_gemm(g, blh, t2len, winlen, (int64_t)o * o * o * v, s);
+    }
+    launches_ += 18;
+  }
+
+  if (density_terms && !w.owned.empty()) {
+    const int no = (int)w.owned.size() / 4;
+    cplx* Dab = P("td_Dab", {v, v});
+    cplx* Z34 = P("td_Z34", {o, v});
+    cplx* Rd = P("td_Rd", {o, o, v, o});
+    {  // D_ab += 1/2 sum_{(d,c)} lambda[a][(d,c)] t[b][(d,c)]
+      GemmDesc g = base(v, v, (int)v2, no, w.d_owned, pr);
+      g.atomic = 1;
+      g.alpha = R(0.5);
+      g.A = L;
+      g.sAm0 = v2;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = T;
+      g.sBk0 = 1;
+      g.sBn0 = v2;
+      set4(g.cB, 0, 0, 0, v3);
+      g.C = Dab;
+      g.sCm0 = v;
+      g.sCn0 = 1;
+      checked_gemm(g, w.owned.data(), winlen, winlen, v2, s);
+    }
+    // D_ia first term: sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]
+    launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, 2, s);
+    {  // D_ia second term: Rd[J][I][b][x] += sum_cd lambda[b][(c,d)] t2[x][K][(c,d)]
+      GemmDesc g = base(v, o, (int)v2, no, w.d_owned, pr);
+      g.atomic = 1;
+      g.A = L;
+      g.sAm0 = v2;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = t2;
+      g.sBk0 = 1;
+      g.sBn0 = (int64_t)o * v2;
+      set4(g.cB, 0, 0, v2, 0);
+      g.C = Rd;
+      g.sCm0 = o;
+      g.sCn0 = 1;
+      set4(g.cC, (int64_t)v * o, (int64_t)o * v * o, 0, 0);
+      checked_gemm(g, w.owned.data(), winlen, t2len, (int64_t)o * o * v * o, s);
+    }
+  }
+  if (density_terms) {
+    // D_ij += -1/2 sum_abc t_{ilk} lambda_{jlk} over the slabs (., l, k) and (., k, l)
+    cplx* Dij = P("td_Dij", {o, o});
+    for (int sl = 0; sl < 2; ++sl) {
+      if (w.slab_start[sl] < 0) continue;
+      const int64_t base0 = (int64_t)w.slab_start[sl] * v3;
+      const int64_t KC = std::min<int64_t>(v3, 4096);
+      const int64_t full = v3 / KC, rem = v3 % KC;
+      auto dl = [&](int64_t k0, int64_t kc, int64_t nb) {
+        if (nb <= 0 || kc <= 0) return;
+        GemmDesc g = base(o, o, (int)kc, (int)nb, nullptr, pr);
+        g.atomic = 1;
+        g.alpha = R(-0.5);
+        g.A = T + base0 + k0;
+        g.sAm0 = v3;
+        g.sAk0 = 1;
+        g.sAb = kc;
+        g.B = L + base0 + k0;
+        g.sBk0 = 1;
+        g.sBn0 = v3;
+        g.sBb = kc;
+        g.C = Dij;
+        g.sCm0 = o;
+        g.sCn0 = 1;
+        checked_gemm(g, nullptr, winlen - base0 - k0, winlen - base0 - k0, (int64_t)o * o, s);
+      };
+      dl(0, KC, full);
+      dl(full * KC, rem, 1);
+    }
+  }
+}
+
+TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density) {
+  const int64_t o = d.o, v = d.v;
+  const int64_t ov = o * v, oovv = o * o * v * v;
+  hipStream_t s = e.stream;
+  if (!t0_) {
+    RTCC3_HIP(hipEventCreate(&t0_));
+    RTCC3_HIP(hipEventCreate(&t1_));
+  }
+  RTCC3_HIP(hipEventRecord(t0_, s));
+  blocks(e, r);
+  // accumulators
+  const char* names[] = {"tr_X1", "tr_X2p", "tr_Y1", "tr_Y2p", "tr_Z34", "tr_R15", "tr_R2",
+                         "tr_R6", "tr_R7",  "tr_R8", "tr_Zi",  "tr_R12"};
+  std::vector<std::vector<int64_t>> shapes = {{o, v},       {o, o, v, v}, {o, v},       {o, o, v, v},
+                                              {o, v},       {o, o, v, o}, {o, o, v, o}, {o, o, v, o},
+                                              {o, o, v, o}, {o, o, v, o}, {o, v, v, v}, {o, o, o, v}};
+  for (size_t i = 0; i < shapes.size(); ++i) e.zero(e.tensor(names[i], shapes[i]));
+  for (auto& w : rhs_windows_) window_pass(e, w, y, true, false);
+
+  // ---- final contractions of the Y1 intermediates
+  View Y1 = e.tensor("tr_Y1", {o, v});
+  View l2 = Engine::raw(const_cast<cplx*>(y) + 2 * ov + oovv, {o, o, v, v});
+  View Lov = e.tensor("Lov", {o, v, o, v});
+  View g_ovov = e.tensor("g_ovov", {o, v, o, v});
+  View g_oovv = e.tensor("g_oovv", {o, o, v, v});
+  View g_voov = e.tensor("g_voov", {v, o, o, v});
+  View g_vvvv = e.tensor("g_vvvv", {v, v, v, v});
+  View g_oooo = e.tensor("g_oooo", {o, o, o, o});
+  e.einsum("klbx,klab->xa", ONE, e.tensor("tr_R15", {o, o, v, o}), l2, Y1);
+  e.einsum("klbx,kalb->xa", ONE, e.tensor("tr_R2", {o, o, v, o}), g_ovov, Y1);
+  e.einsum("jkbx,kajb->xa", R(-1), e.tensor("tr_R6", {o, o, v, o}), Lov, Y1);
+  e.einsum("xajb,jb->xa", ONE, Lov, e.tensor("tr_Z34", {o, v}), Y1);
+  e.einsum("ildj,jlda->ia", R(-1), e.tensor("tr_R7", {o, o, v, o}), g_oovv, Y1);
+  e.einsum("ildj,dlja->ia", R(-1), e.tensor("tr_R8", {o, o, v, o}), g_voov, Y1);
+  e.einsum("ideb,daeb->ia", ONE, e.tensor("tr_Zi", {o, v, v, v}), g_vvvv, Y1);
+  e.einsum("xljm,ljma->xa", ONE, g_oooo, e.tensor("tr_R12", {o, o, o, v}), Y1);
+
+  TriplesOut out;
+  out.X1 = e.tensor("tr_X1", {o, v});
+  out.Y1 = Y1;
+  // P_ij^ab symmetrisation of X2 and Y2
+  View X2 = e.tensor("tr_X2", {o, o, v, v});
+  e.zero(X2);
+  View X2p = e.tensor("tr_X2p", {o, o, v, v});
+  e.axpy(ONE, X2p, X2);
+  e.axpy(ONE, Engine::permute(X2p, {1, 0, 3, 2}), X2);
+  View Y2 = e.tensor("tr_Y2", {o, o, v, v});
+  e.zero(Y2);
+  View Y2p = e.tensor("tr_Y2p", {o, o, v, v});
+  e.axpy(ONE, Y2p, Y2);
+  e.axpy(ONE, Engine::permute(Y2p, {1, 0, 3, 2}), Y2);
+  out.X2 = X2;
+  out.Y2 = Y2;
+
+  if (want_density) {
+    View Dij = e.tensor("td_Dij", {o, o}), Dab = e.tensor("td_Dab", {v, v}), Z34 = e.tensor("td_Z34", {o, v}),
+         Rd = e.tensor("td_Rd", {o, o, v, o});
+    e.zero(Dij);
+    e.zero(Dab);
+    e.zero(Z34);
+    e.zero(Rd);
+    for (auto& w : den_windows_) window_pass(e, w, y, false, true);
+    View Dia = e.tensor("td_Dia", {o, v});
+    e.zero(Dia);
+    e.axpy(ONE, Z34, Dia);
+    View t2 = Engine::raw(const_cast<cplx*>(y) + ov, {o, o, v, v});
+    e.einsum("kjbx,kjab->xa", R(-1), Rd, t2, Dia);
+    out.Dij = Dij;
+    out.Dab = Dab;
+    out.Dia = Dia;
+  }
+  RTCC3_HIP(hipEventRecord(t1_, s));
+  RTCC3_HIP(hipEventSynchronize(t1_));
+  float ms = 0;
+  RTCC3_HIP(hipEventElapsedTime(&ms, t0_, t1_));
+  ms_ += ms;
+  return out;
+}
+
+}  // namespace rtcc3

@@ -1,0 +1,58 @@
+// Approximate triples of CC3 evaluated one occupied triple (i,j,k) at a time.
+#pragma once
+
+#include <vector>
+
+#include "ccsd.h"
+#include "engine.h"
+
+namespace rtcc3 {
+
+struct TriplesOut {
+  View X1, X2, Y1, Y2;  // contributions to the T and Lambda residuals
+  View Dij, Dab, Dia;   // triples part of the T1-frame density (when requested)
+};
+
+// A window: a set of ordered occupied triples that is closed under permutation,
+// so every block's P_ijk^abc partners are in it.
+struct Window {
+  int nw = 0;                 // ordered blocks
+  std::vector<int> bl;        // [nw][4]: I, J, K, n (host copy)
+  std::vector<int> part;      // [nw][6]: window indices of (ijk),(jik),(ikj),(kji),(kij),(jki)
+  std::vector<int> owned;     // [*][4]: blocks whose density terms this window accumulates
+  int slab_lk[2] = {-1, -1};  // density windows: the occupied pair (l,k) of the D_ij slabs
+  int slab_start[2] = {0, 0}; // window index of block (0,l,k) and (0,k,l); blocks (i,l,k) are consecutive in i
+  int* d_bl = nullptr;
+  int* d_part = nullptr;
+  int* d_owned = nullptr;
+};
+
+class Triples {
+ public:
+  Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int precision);
+  ~Triples();
+  // Run all windows.  want_density: also the triples density terms (separate
+  // pass over slab windows that hold, for an occupied pair (l,k), the blocks
+  // (i,l,k) of every i).
+  TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density);
+  void set_precision(int p) { prec_ = p; }
+  void reset_timing() { ms_ = 0; launches_ = 0; }
+  void timing(double& ms, double& launches) const { ms = ms_; launches = (double)launches_; }
+
+ private:
+  Dims d_;
+  int prec_;
+  double* eps_ = nullptr;  // device
+  std::vector<Window> rhs_windows_, den_windows_;
+  int max_nw_ = 0;
+  double ms_ = 0;
+  long launches_ = 0;
+  hipEvent_t t0_ = nullptr, t1_ = nullptr;
+
+  void build_windows();
+  void upload(Window& w);
+  void blocks(Engine& e, const CCSDResult& r);
+  void window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_terms, bool density_terms);
+};
+
+}  // namespace rtcc3

@@ -1,0 +1,164 @@
+// Element-wise and reduction kernels of the triples engine (one block of
+// [v,v,v] per ordered occupied triple n, row-major [a][b][c]).
+#include "triples_kernels.h"
+
+namespace rtcc3 {
+
+namespace {
+
+__device__ __forceinline__ cplx cadd(cplx x, cplx y) { return cplx{x.re + y.re, x.im + y.im}; }
+__device__ __forceinline__ cplx csub(cplx x, cplx y) { return cplx{x.re - y.re, x.im - y.im}; }
+__device__ __forceinline__ cplx cmul(cplx x, cplx y) {
+  return cplx{x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re};
+}
+__device__ __forceinline__ cplx cscale(double s, cplx x) { return cplx{s * x.re, s * x.im}; }
+__device__ __forceinline__ void catomic(cplx* p, cplx x) {
+  unsafeAtomicAdd(&p->re, x.re);
+  unsafeAtomicAdd(&p->im, x.im);
+}
+
+// t_ijk^abc = P_ijk^abc W'_ijk^abc / D_ijk^abc with
+// P f_ijk^abc = f_ijk^abc + f_jik^bac + f_ikj^acb + f_kji^cba + f_kij^cab + f_jki^bca.
+__global__ void sym_div_kernel(const cplx* __restrict__ W, cplx* __restrict__ T, const int* __restrict__ part,
+                               const int* __restrict__ bl, const double* __restrict__ eps, int o, int v) {
+  const int q = blockIdx.y;
+  const int64_t v3 = (int64_t)v * v * v;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= v3) return;
+  const int a = (int)(e / ((int64_t)v * v)), b = (int)((e / v) % v), c = (int)(e % v);
+  const int* p = part + 6 * q;
+  const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
+  auto at = [&](int s, int x, int y, int z) { return W[(int64_t)p[s] * v3 + ((int64_t)x * v + y) * v + z]; };
+  cplx s = at(0, a, b, c);
+  s = cadd(s, at(1, b, a, c));
+  s = cadd(s, at(2, a, c, b));
+  s = cadd(s, at(3, c, b, a));
+  s = cadd(s, at(4, c, a, b));
+  s = cadd(s, at(5, b, c, a));
+  const double D = eps[I] + eps[J] + eps[K] - eps[o + a] - eps[o + b] - eps[o + c];
+  T[(int64_t)n * v3 + e] = cplx{s.re / D, s.im / D};
+}
+
+// Terms of the lambda3 bracket without a summation index:
+//   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik
+__global__ void lam_elem_kernel(cplx* __restrict__ W, const int* __restrict__ bl, const cplx* __restrict__ Lov,
+                                const cplx* __restrict__ F, const cplx* __restrict__ l1, const cplx* __restrict__ l2,
+                                int o, int v) {
+  const int q = blockIdx.y;
+  const int64_t v3 = (int64_t)v * v * v;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= v3) return;
+  const int a = (int)(e / ((int64_t)v * v)), b = (int)((e / v) % v), c = (int)(e % v);
+  const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
+  const int nn = o + v;
+  const cplx* Lij = Lov + (((int64_t)I * v + a) * o + J) * v;  // L[I,a,J,:]
+  cplx x = cmul(Lij[b], l1[(int64_t)K * v + c]);
+  x = csub(x, cmul(Lij[c], l1[(int64_t)K * v + b]));
+  x = cadd(x, cmul(F[(int64_t)I * nn + o + a], l2[(((int64_t)J * o + K) * v + b) * v + c]));
+  x = csub(x, cmul(F[(int64_t)J * nn + o + a], l2[(((int64_t)I * o + K) * v + b) * v + c]));
+  cplx* w = W + (int64_t)n * v3 + e;
+  *w = cadd(*w, x);
+}
+
+// mode 0: Z[n][b][c][e] = 2 t[c,b,e] - t[c,e,b] - t[e,b,c]
+// mode 1: Z[n][a][b][c] = 2 t[c,b,a] - t[b,c,a] - t[a,b,c]
+__global__ void comb_kernel(const cplx* __restrict__ T, cplx* __restrict__ Z, const int* __restrict__ bl, int v,
+                            int mode) {
+  const int q = blockIdx.y;
+  const int64_t v3 = (int64_t)v * v * v;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= v3) return;
+  const int n = bl[4 * q + 3];
+  const int x = (int)(e / ((int64_t)v * v)), y = (int)((e / v) % v), z = (int)(e % v);
+  const cplx* t = T + (int64_t)n * v3;
+  auto at = [&](int i, int j, int k) { return t[((int64_t)i * v + j) * v + k]; };
+  cplx r;
+  if (mode == 0) {  // x=b, y=c, z=e
+    r = csub(csub(cscale(2.0, at(y, x, z)), at(y, z, x)), at(z, x, y));
+  } else {  // x=a, y=b, z=c
+    r = csub(csub(cscale(2.0, at(z, y, x)), at(y, z, x)), at(x, y, z));
+  }
+  Z[(int64_t)n * v3 + e] = r;
+}
+
+// Contractions with one free virtual index per block (I,J,K):
+//   flags&1: X1[I][a]     += sum_bc (t[a,b,c] - t[c,b,a]) L[J,b,K,c]
+//            X2p[I,J][a,b]+= sum_c  (t[a,b,c] - t[c,b,a]) f~[K, c]
+//   flags&2: Z[I][a]      += sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]
+__global__ void small_t3_kernel(const cplx* __restrict__ T, const int* __restrict__ bl, const cplx* __restrict__ Lov,
+                                const cplx* __restrict__ F, const cplx* __restrict__ l2, cplx* __restrict__ X1,
+                                cplx* __restrict__ X2p, cplx* __restrict__ Z, int o, int v, int flags) {
+  const int q = blockIdx.y, a = blockIdx.x;
+  const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
+  const int64_t v3 = (int64_t)v * v * v;
+  const int nn = o + v;
+  const cplx* t = T + (int64_t)n * v3;
+  cplx x1{0, 0}, z{0, 0};
+  for (int b = threadIdx.x; b < v; b += blockDim.x) {
+    cplx x2f{0, 0};
+    const cplx* Lb = Lov + (((int64_t)J * v + b) * o + K) * v;
+    const cplx* l2b = l2 + (((int64_t)J * o + K) * v + b) * v;
+    for (int c = 0; c < v; ++c) {
+      const cplx tabc = t[((int64_t)a * v + b) * v + c];
+      if (flags & 1) {
+        const cplx tz = csub(tabc, t[((int64_t)c * v + b) * v + a]);
+        x1 = cadd(x1, cmul(tz, Lb[c]));
+        x2f = cadd(x2f, cmul(tz, F[(int64_t)K * nn + o + c]));
+      }
+      if (flags & 2) z = cadd(z, cmul(csub(tabc, t[((int64_t)b * v + a) * v + c]), l2b[c]));
+    }
+    if (flags & 1) catomic(&X2p[(((int64_t)I * o + J) * v + a) * v + b], x2f);
+  }
+  __shared__ cplx red[2][256];
+  red[0][threadIdx.x] = x1;
+  red[1][threadIdx.x] = z;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] = cadd(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = cadd(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (flags & 1) catomic(&X1[(int64_t)I * v + a], red[0][0]);
+    if (flags & 2) catomic(&Z[(int64_t)I * v + a], red[1][0]);
+  }
+}
+
+inline dim3 blocks_v3(int v, int nb) {
+  const int64_t v3 = (int64_t)v * v * v;
+  return dim3((unsigned)((v3 + 255) / 256), (unsigned)nb);
+}
+
+}  // namespace
+
+void launch_sym_div(const cplx* W, cplx* T, const int* part, const int* bl, const double* eps, int o, int v, int nb,
+                    hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(sym_div_kernel, blocks_v3(v, nb), dim3(256), 0, s, W, T, part, bl, eps, o, v);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void launch_lam_elem(cplx* W, const int* bl, const cplx* Lov, const cplx* F, const cplx* l1, const cplx* l2, int o,
+                     int v, int nb, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(lam_elem_kernel, blocks_v3(v, nb), dim3(256), 0, s, W, bl, Lov, F, l1, l2, o, v);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void launch_comb(const cplx* T, cplx* Z, const int* bl, int v, int nb, int mode, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(comb_kernel, blocks_v3(v, nb), dim3(256), 0, s, T, Z, bl, v, mode);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, const cplx* F, const cplx* l2, cplx* X1,
+                     cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(small_t3_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1, X2p, Z,
+                     o, v, flags);
+  RTCC3_HIP(hipGetLastError());
+}
+
+}  // namespace rtcc3

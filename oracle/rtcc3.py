@@ -355,7 +355,7 @@ def density_triples_full(t2, l2, t3, l3):
     return Dij, Dab, Dia
 
 
-def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False):
+def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False, max_blocks=None):
     """Triples contributions evaluated one occupied triple at a time (Sec. 2.1).
 
     The loop runs over (l,k) and, inside, over i, building the [v,v,v] blocks
@@ -371,10 +371,14 @@ def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False)
     Dab = torch.zeros((v, v), dtype=C128)
     Dia = torch.zeros((o, v), dtype=C128)
     gov, L = ti.g_ovov, ti.L_ovov
+    done = 0
     for J in range(o):
         for K in range(o):
+            if max_blocks is not None and done >= max_blocks:
+                break
             tstack, lstack = [], []
             for I in range(o):
+                done += 1
                 t = t3_block(m, ti, t2, I, J, K)
                 lam = l3_block(m, ti, l1, l2, I, J, K)
                 tstack.append(t)

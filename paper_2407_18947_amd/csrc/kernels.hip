@@ -1,5 +1,7 @@
 // Generic kernels: batched complex GEMM on the matrix cores (FP64 or FP32
 // MFMA, complex product as four real products), strided axpy/permute, fill.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rtcc3 {
@@ -43,14 +45,19 @@ __device__ __forceinline__ void atomic_add_cplx(cplx* p, double re, double im) {
 // Result layout: FP32 holds D[4*(l/16)+r][l%16] in register r, FP64 holds
 // D[4*r+l/16][l%16] (Frag<T>::row).
 template <typename T, bool ATOMIC>
-__global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d) {
+__global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
   typedef typename Frag<T>::acc acc_t;
   __shared__ T sAr[BK][BM + 1], sAi[BK][BM + 1], sBr[BK][BN + 1], sBi[BK][BN + 1];
 
   const int tilesN = (d.N + BN - 1) / BN;
-  const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
+  const int kz = blockIdx.x % ksplit;
+  const int tile = blockIdx.x / ksplit;
+  const int tm = tile / tilesN, tn = tile % tilesN;
   const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
   if (b >= d.batch) return;
+  const int kbeg = kz * kchunk;
+  const int kend = min(d.K, kbeg + kchunk);
+  if (kbeg >= kend) return;
   const cplx* __restrict__ A;
   const cplx* __restrict__ B;
   cplx* __restrict__ C;
@@ -69,7 +76,8 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
 
-  // loader geometry: 4 elements of each tile per thread
+  // loader geometry: 4 elements of each tile per thread, the fast thread
+  // index along the operand's unit-stride dimension when there is one
   const bool kfastA = (d.sAk0 == 1);
   const bool nfastB = (d.sBn0 == 1);
   int amm[4], akk[4], bnn[4], bkk[4];
@@ -99,19 +107,23 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d) {
       cim[i][j] = acc_t{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
-    cplx av[4], bv[4];
+  cplx av[4], bv[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int ka = k0 + akk[r];
       av[r] = cplx{0.0, 0.0};
-      if (aval[r] && ka < d.K)
+      if (aval[r] && ka < kend)
         av[r] = A[aoff[r] + (int64_t)(ka / d.K0) * d.sAk1 + (int64_t)(ka % d.K0) * d.sAk0];
       const int kb = k0 + bkk[r];
       bv[r] = cplx{0.0, 0.0};
-      if (bval[r] && kb < d.K)
+      if (bval[r] && kb < kend)
         bv[r] = B[boff[r] + (int64_t)(kb / d.K0) * d.sBk1 + (int64_t)(kb % d.K0) * d.sBk0];
     }
+  };
+
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -121,26 +133,36 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d) {
       sBi[bkk[r]][bnn[r]] = (T)bv[r].im;
     }
     __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);  // next tile in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
-      T ar[2], ai[2], br[2], bi[2];
+      T ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         ar[i] = sAr[kr][wm + 16 * i + c16];
         ai[i] = sAi[kr][wm + 16 * i + c16];
+        nai[i] = -ai[i];
         br[i] = sBr[kr][wn + 16 * i + c16];
         bi[i] = sBi[kr][wn + 16 * i + c16];
       }
+      // four independent MFMAs between two that update the same accumulator
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
-          cre[i][j] = Frag<T>::mfma(-ai[i], bi[j], cre[i][j]);
-          cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
-          cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
-        }
+        for (int j = 0; j < 2; ++j) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
     }
   }
 
@@ -207,23 +229,34 @@ void gemm(const GemmDesc& d, hipStream_t s) {
   if (d.K <= 0) return;
   RTCC3_CHECK(d.M0 >= 1 && d.N0 >= 1 && d.K0 >= 1, "gemm: inner extents must be >= 1");
   const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
-  RTCC3_CHECK(tiles < (1LL << 31), "gemm: too many tiles");
+  // Split K across workgroups when the grid is too small to fill the chip and
+  // K is long; the partial products are then added with atomics.
+  int ksplit = 1;
+  const int64_t wgs = tiles * d.batch;
+  if (wgs < 512 && d.K >= 8 * BK) {
+    const int64_t want = (1024 + wgs - 1) / wgs;
+    const int64_t maxs = d.K / (4 * BK);
+    ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
+  }
+  const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BK - 1) / BK * BK);
+  RTCC3_CHECK(tiles * ksplit < (1LL << 31), "gemm: too many tiles");
   int64_t by = d.batch, bz = 1;
   while (by > 65535) {
     by = (by + 1) / 2;
     bz *= 2;
   }
-  dim3 grid((unsigned)tiles, (unsigned)by, (unsigned)bz);
+  dim3 grid((unsigned)(tiles * ksplit), (unsigned)by, (unsigned)bz);
+  const bool atomic = d.atomic || ksplit > 1;
   if (d.prec == 0) {
-    if (d.atomic)
-      hipLaunchKernelGGL((zgemm_kernel<double, true>), grid, dim3(NT), 0, s, d);
+    if (atomic)
+      hipLaunchKernelGGL((zgemm_kernel<double, true>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
     else
-      hipLaunchKernelGGL((zgemm_kernel<double, false>), grid, dim3(NT), 0, s, d);
+      hipLaunchKernelGGL((zgemm_kernel<double, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   } else {
-    if (d.atomic)
-      hipLaunchKernelGGL((zgemm_kernel<float, true>), grid, dim3(NT), 0, s, d);
+    if (atomic)
+      hipLaunchKernelGGL((zgemm_kernel<float, true>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
     else
-      hipLaunchKernelGGL((zgemm_kernel<float, false>), grid, dim3(NT), 0, s, d);
+      hipLaunchKernelGGL((zgemm_kernel<float, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   }
   RTCC3_HIP(hipGetLastError());
 }

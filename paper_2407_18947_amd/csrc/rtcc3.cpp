@@ -25,6 +25,8 @@ struct rtcc3_ctx {
   View B, mu, h0, I, ones_o, h;
   cplx *y = nullptr, *ytmp = nullptr, *k = nullptr, *acc = nullptr;
   double last_ms[3] = {0, 0, 0};
+  cplx* mus = nullptr;  // dipole series of the last propagation (grows on demand)
+  int64_t mus_n = 0;
   std::string err;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -343,7 +345,16 @@ extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double*
   return guarded(c, [&]() -> int {
     Engine& e = *c->e;
     const int64_t L = c->ylen;
-    View mus = e.tensor("mu_series", {(int64_t)steps + 1, 3});
+    if (c->mus_n < 3 * ((int64_t)steps + 1)) {
+      RTCC3_HIP(hipStreamSynchronize(c->stream));
+      if (c->mus) RTCC3_HIP(hipFree(c->mus));
+      c->mus = nullptr;
+      c->mus_n = 0;
+      if (hipMalloc(&c->mus, sizeof(cplx) * 3 * ((int64_t)steps + 1)) != hipSuccess)
+        return fail(c, RTCC3_ENOMEM, "no device memory for the dipole series");
+      c->mus_n = 3 * ((int64_t)steps + 1);
+    }
+    View mus = Engine::raw(c->mus, {(int64_t)steps + 1, 3});
     const bool tri = c->with_triples != 0;
     View Y = Engine::raw(c->y, {L}), YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}),
          A = Engine::raw(c->acc, {L});
@@ -424,6 +435,7 @@ extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
   c->e.reset();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->mus) (void)hipFree(c->mus);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

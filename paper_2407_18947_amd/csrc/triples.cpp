@@ -103,6 +103,7 @@ Triples::~Triples() {
       if (w.d_bl) (void)hipFree(w.d_bl);
       if (w.d_part) (void)hipFree(w.d_part);
       if (w.d_owned) (void)hipFree(w.d_owned);
+      if (w.d_canon) (void)hipFree(w.d_canon);
     }
   if (eps_) (void)hipFree(eps_);
 }
@@ -136,6 +137,7 @@ void finish_window(Window& w, const std::vector<std::array<int, 3>>& blocks) {
       RTCC3_CHECK(it != idx.end(), "triples: window not closed under permutation");
       w.part[6 * n + s] = it->second;
     }
+    if (I <= J && J <= K) w.canon.insert(w.canon.end(), {I, J, K, n});
   }
 }
 
@@ -205,6 +207,8 @@ void Triples::upload(Window& w) {
   RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
   RTCC3_HIP(hipMalloc(&w.d_part, sizeof(int) * w.part.size()));
   RTCC3_HIP(hipMemcpy(w.d_part, w.part.data(), sizeof(int) * w.part.size(), hipMemcpyHostToDevice));
+  RTCC3_HIP(hipMalloc(&w.d_canon, sizeof(int) * w.canon.size()));
+  RTCC3_HIP(hipMemcpy(w.d_canon, w.canon.data(), sizeof(int) * w.canon.size(), hipMemcpyHostToDevice));
   if (!w.owned.empty()) {
     RTCC3_HIP(hipMalloc(&w.d_owned, sizeof(int) * w.owned.size()));
     RTCC3_HIP(hipMemcpy(w.d_owned, w.owned.data(), sizeof(int) * w.owned.size(), hipMemcpyHostToDevice));
@@ -331,7 +335,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, v3);
     checked_gemm(g, blh, t2len, lOOOV, winlen, s);
   }
-  launch_sym_div(W, T, w.d_part, bl, eps_, o, v, nw, s);
+  launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, s);
 
   // ---------------- lambda3 blocks
   fill(W, (int64_t)nw * v3, cplx{0, 0}, s);
@@ -382,7 +386,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     checked_gemm(g, blh, (int64_t)o * o * v * o, l2len, winlen, s);
   }
   launch_lam_elem(W, bl, Lov, F, l1, l2, o, v, nw, s);
-  launch_sym_div(W, L, w.d_part, bl, eps_, o, v, nw, s);
+  launch_sym_cube(W, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, s);
   launches_ += 10;
 
   if (rhs_terms) {

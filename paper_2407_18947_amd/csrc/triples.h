@@ -20,11 +20,13 @@ struct Window {
   std::vector<int> bl;        // [nw][4]: I, J, K, n (host copy)
   std::vector<int> part;      // [nw][6]: window indices of (ijk),(jik),(ikj),(kji),(kij),(jki)
   std::vector<int> owned;     // [*][4]: blocks whose density terms this window accumulates
+  std::vector<int> canon;     // [*][4]: I <= J <= K and the slot of that ordering, one per distinct triple
   int slab_lk[2] = {-1, -1};  // density windows: the occupied pair (l,k) of the D_ij slabs
   int slab_start[2] = {0, 0}; // window index of block (0,l,k) and (0,k,l); blocks (i,l,k) are consecutive in i
   int* d_bl = nullptr;
   int* d_part = nullptr;
   int* d_owned = nullptr;
+  int* d_canon = nullptr;
 };
 
 class Triples {

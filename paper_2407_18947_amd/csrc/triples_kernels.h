@@ -9,6 +9,10 @@ namespace rtcc3 {
 
 void launch_sym_div(const cplx* W, cplx* T, const int* part, const int* bl, const double* eps, int o, int v, int nb,
                     hipStream_t s);
+// Symmetrise and divide for the canonical triples of a window (canon: 4 ints
+// per entry, I <= J <= K and the slot of that ordering); writes all orderings.
+void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
+                     int v, hipStream_t s);
 void launch_lam_elem(cplx* W, const int* bl, const cplx* Lov, const cplx* F, const cplx* l1, const cplx* l2, int o,
                      int v, int nb, hipStream_t s);
 void launch_comb(const cplx* T, cplx* Z, const int* bl, int v, int nb, int mode, hipStream_t s);

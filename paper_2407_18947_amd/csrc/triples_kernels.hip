@@ -126,6 +126,80 @@ __global__ void small_t3_kernel(const cplx* __restrict__ T, const int* __restric
   }
 }
 
+// Tiled P_ijk^abc + denominator for one canonical triple c = (i<=j<=k) per
+// blockIdx.y, one 8x8x8 cube of (a,b,c) per blockIdx.x.  With p_s the six
+// permutations (identity, (12), (23), (13), cyclic, cyclic^2) of positions,
+//   t_c[t] = sum_s W[slot_s][t o p_s] / D(t),   T[slot_s][t o p_s] = t_c[t]
+// where slot_s is the window slot of the ordered triple (i,j,k) o p_s, because
+// t_{sigma(ijk)}^{sigma(abc)} = t_{ijk}^{abc}.  Sources are read and
+// destinations written along their unit-stride index through LDS.
+constexpr int CB = 8;
+__device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}};
+
+__global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ W, cplx* __restrict__ T,
+                                                         const int* __restrict__ canon, const int* __restrict__ part,
+                                                         const double* __restrict__ eps, int o, int v) {
+  __shared__ cplx acc[CB * CB * CB];
+  const int q = blockIdx.y;
+  const int I = canon[4 * q], J = canon[4 * q + 1], K = canon[4 * q + 2], n0 = canon[4 * q + 3];
+  const int* sl = part + 6 * n0;
+  const int nc = (v + CB - 1) / CB;
+  const int cube = blockIdx.x;
+  int t0[3];
+  t0[0] = (cube / (nc * nc)) * CB;
+  t0[1] = ((cube / nc) % nc) * CB;
+  t0[2] = (cube % nc) * CB;
+  const int64_t v3 = (int64_t)v * v * v;
+  for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) acc[e] = cplx{0, 0};
+  __syncthreads();
+  for (int s = 0; s < 6; ++s) {
+    const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
+    const int x0 = t0[p0], x1 = t0[p1], x2 = t0[p2];
+    const cplx* src = W + (int64_t)sl[s] * v3;
+    for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
+      const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
+      const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
+      if (X0 < v && X1 < v && X2 < v) {
+        int tl[3];
+        tl[p0] = u0;
+        tl[p1] = u1;
+        tl[p2] = u2;
+        const cplx w = src[((int64_t)X0 * v + X1) * v + X2];
+        cplx& r = acc[(tl[0] * CB + tl[1]) * CB + tl[2]];
+        r.re += w.re;
+        r.im += w.im;
+      }
+    }
+    __syncthreads();
+  }
+  const double eocc = eps[I] + eps[J] + eps[K];
+  for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
+    const int a = t0[0] + e / (CB * CB), b = t0[1] + (e / CB) % CB, c = t0[2] + e % CB;
+    if (a < v && b < v && c < v) {
+      const double D = eocc - eps[o + a] - eps[o + b] - eps[o + c];
+      acc[e].re /= D;
+      acc[e].im /= D;
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < 6; ++s) {
+    const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
+    const int x0 = t0[p0], x1 = t0[p1], x2 = t0[p2];
+    cplx* dst = T + (int64_t)sl[s] * v3;
+    for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
+      const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
+      const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
+      if (X0 < v && X1 < v && X2 < v) {
+        int tl[3];
+        tl[p0] = u0;
+        tl[p1] = u1;
+        tl[p2] = u2;
+        dst[((int64_t)X0 * v + X1) * v + X2] = acc[(tl[0] * CB + tl[1]) * CB + tl[2]];
+      }
+    }
+  }
+}
+
 inline dim3 blocks_v3(int v, int nb) {
   const int64_t v3 = (int64_t)v * v * v;
   return dim3((unsigned)((v3 + 255) / 256), (unsigned)nb);
@@ -137,6 +211,15 @@ void launch_sym_div(const cplx* W, cplx* T, const int* part, const int* bl, cons
                     hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(sym_div_kernel, blocks_v3(v, nb), dim3(256), 0, s, W, T, part, bl, eps, o, v);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
+                     int v, hipStream_t s) {
+  if (ncanon <= 0) return;
+  const int nc = (v + CB - 1) / CB;
+  hipLaunchKernelGGL(sym_cube_kernel, dim3((unsigned)(nc * nc * nc), (unsigned)ncanon), dim3(256), 0, s, W, T, canon,
+                     part, eps, o, v);
   RTCC3_HIP(hipGetLastError());
 }
 

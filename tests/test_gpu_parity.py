@@ -124,3 +124,24 @@ def test_propagate_short_matches_oracle():
     _close("mu", mu, mur.numpy(), 1e-12)
     _close("y", yg, yr.numpy(), 1e-12)
     ctx.close()
+
+
+def test_monomer_dipole_series_matches_stored_oracle():
+    """Monomer-sized workload (o=5, v=19, seed 1), delta kick 0.002 a.u. along z,
+    dt = 0.05, 20 RK4 steps: the dipole series agrees with the stored oracle
+    series (tests/golden/make_golden.py) to 1e-10 a.u."""
+    import os
+
+    from paper_2407_18947_amd.inputs import CONFIGS, config_field
+
+    _say("monomer 20 steps")
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "monomer_20steps.npz"))
+    c = CONFIGS["monomer"]
+    s = make_system(c["o"], c["v"], seed=c["seed"])
+    ctx = _lib.Context(s)
+    ctx.set_state(initial_state(s))
+    mu = ctx.propagate(c["steps"], c["dt"], config_field("monomer"))
+    y = ctx.get_state()
+    ctx.close()
+    assert np.abs(mu - g["mu"]).max() < 1e-10, np.abs(mu - g["mu"]).max()
+    assert np.abs(y - g["y"]).max() < 1e-9 * max(1, np.abs(g["y"]).max())

@@ -390,6 +390,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   launches_ += 10;
 
   if (rhs_terms) {
+    // Contractions run over the blocks this window is responsible for: all of
+    // them in a plain window, the owned ones in a pair window.
+    const bool pairwin = !w.owned.empty() && density_terms;
+    const int* cbl = pairwin ? w.d_owned : bl;
+    const int* cblh = pairwin ? w.owned.data() : blh;
+    const int cn = pairwin ? (int)w.owned.size() / 4 : nw;
     cplx* X1 = P("tr_X1", {o, v});
     cplx* X2p = P("tr_X2p", {o, o, v, v});
     cplx* Y1 = P("tr_Y1", {o, v});
@@ -398,16 +404,15 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     cplx* R15 = P("tr_R15", {o, o, v, o});
     cplx* R2t = P("tr_R2", {o, o, v, o});
     cplx* R6 = P("tr_R6", {o, o, v, o});
-    cplx* R7 = P("tr_R7", {o, o, v, o});
     cplx* R8 = P("tr_R8", {o, o, v, o});
     cplx* Zi = P("tr_Zi", {o, v, v, v});
     cplx* R12 = P("tr_R12", {o, o, o, v});
     const int64_t lR = (int64_t)o * o * v * o;
 
     // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ with Z1 = 2t[c,b,e] - t[c,e,b] - t[e,b,c]
-    launch_comb(T, Z, bl, v, nw, 0, s);
+    launch_comb(T, Z, cbl, v, cn, 0, s);
     {
-      GemmDesc g = base(v, v, (int)v2, nw, bl, pr);
+      GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
       g.A = gX2a;
       g.sAm0 = v2;
@@ -421,12 +426,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
-      checked_gemm(g, blh, lOVVV, winlen, oovv, s);
+      checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
     }
     // X2: -sum_c Zh[(a,b)][c] (Ki|Ic)~ into X2p[x][J] with Zh = 2t[c,b,a] - t[b,c,a] - t[a,b,c]
-    launch_comb(T, Z, bl, v, nw, 1, s);
+    launch_comb(T, Z, cbl, v, cn, 1, s);
     {
-      GemmDesc g = base((int)v2, o, v, nw, bl, pr);
+      GemmDesc g = base((int)v2, o, v, cn, cbl, pr);
       g.atomic = 1;
       g.alpha = R(-1);
       g.A = Z;
@@ -441,12 +446,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
-      checked_gemm(g, blh, winlen, lOOOV, oovv, s);
+      checked_gemm(g, cblh, winlen, lOOOV, oovv, s);
     }
     // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1)
-    launch_small_t3(T, bl, nw, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
+    launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
     {  // Y2: sum_de (da|eK)~ lambda[d][b][e] into Y2p[I][J][a][b]
-      GemmDesc g = base(v, v, (int)v2, nw, bl, pr);
+      GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
       g.K0 = v;
       g.A = gY2a;
@@ -463,10 +468,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
-      checked_gemm(g, blh, lOVVV, winlen, oovv, s);
+      checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
     }
     {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J]
-      GemmDesc g = base((int)v2, o, v, nw, bl, pr);
+      GemmDesc g = base((int)v2, o, v, cn, cbl, pr);
       g.atomic = 1;
       g.alpha = R(-1);
       g.A = L;
@@ -481,14 +486,14 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
-      checked_gemm(g, blh, winlen, lOOOV, oovv, s);
+      checked_gemm(g, cblh, winlen, lOOOV, oovv, s);
     }
     // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates over (b,x)
     auto tl = [&](const cplx* Bp, int64_t lenB, int64_t sbk, int64_t sbn, const int64_t* cb, cplx* Cp,
                   const int64_t* cc, double alpha, bool tmajor) {
       // C[b][x] += alpha * sum_{(c,d)} t[b][(c,d)] B[(c,d)][x]   (tmajor: t[n][b][cd])
       // or, !tmajor: C[d][x] += alpha * sum_{(b,c)} t[(b,c)][d] B[(b,c)][x]
-      GemmDesc g = base(v, o, (int)v2, nw, bl, pr);
+      GemmDesc g = base(v, o, (int)v2, cn, cbl, pr);
       g.atomic = 1;
       g.alpha = R(alpha);
       g.A = T;
@@ -503,7 +508,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = o;
       g.sCn0 = 1;
       std::memcpy(g.cC, cc, sizeof(g.cC));
-      checked_gemm(g, blh, winlen, lenB, lR, s);
+      checked_gemm(g, cblh, winlen, lenB, lR, s);
     };
     {
       const int64_t cb1[4] = {(int64_t)o * v2, 0, 0, 0}, cc1[4] = {0, (int64_t)o * v * o, (int64_t)v * o, 0};
@@ -514,8 +519,9 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       const int64_t cb6[4] = {0, 0, v2, 0}, cc6[4] = {(int64_t)o * v * o, (int64_t)v * o, 0, 0};
       tl(l2, l2len, 1, (int64_t)o * v2, cb6, R6, cc6, 1.0, true);  // term 6: l2[x][K]
     }
-    {  // terms 7, 8: Q[d][j] = sum_bc lambda[(b,c)][d] t2[j][J][(b,c)] into R7[K][I], R8[I][K]
-      GemmDesc g = base(v, o, (int)v2, nw, bl, pr);
+    {  // terms 7, 8: Q[d][j] = sum_bc lambda[(b,c)][d] t2[j][J][(b,c)] into R8[I][K]
+      // (the term-7 intermediate R7[K][I] is the same sum with the first two indices swapped)
+      GemmDesc g = base(v, o, (int)v2, cn, cbl, pr);
       g.atomic = 1;
       g.A = L;
       g.sAm0 = 1;
@@ -525,18 +531,15 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sBk0 = 1;
       g.sBn0 = (int64_t)o * v2;
       set4(g.cB, 0, v2, 0, 0);
-      g.C = R7;
+      g.C = R8;
       g.sCm0 = o;
       g.sCn0 = 1;
-      set4(g.cC, (int64_t)v * o, 0, (int64_t)o * v * o, 0);
-      checked_gemm(g, blh, winlen, t2len, lR, s);
-      g.C = R8;
       set4(g.cC, (int64_t)o * v * o, 0, (int64_t)v * o, 0);
-      checked_gemm(g, blh, winlen, t2len, lR, s);
+      checked_gemm(g, cblh, winlen, t2len, lR, s);
     }
     {  // terms 9, 10: S[n][c][d][x] = sum_b t2[K][J][b][c] (xI|db)~ + sum_b t2[I][J][b][c] (dK|xb)~
       fill(S, (int64_t)nw * v2 * o, cplx{0, 0}, s);
-      GemmDesc g = base(v, (int)(o * v), v, nw, bl, pr);
+      GemmDesc g = base(v, (int)(o * v), v, cn, cbl, pr);
       g.N0 = v;
       g.A = t2;
       g.sAm0 = 1;
@@ -553,41 +556,30 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCn0 = o;
       set4(g.cC, 0, 0, 0, v2 * o);
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
-      checked_gemm(g, blh, t2len, lOOVV, lS, s);
+      checked_gemm(g, cblh, t2len, lOOVV, lS, s);
       set4(g.cA, (int64_t)o * v2, v2, 0, 0);
       g.B = gG10;
       set4(g.cB, 0, 0, (int64_t)o * v2, 0);
-      checked_gemm(g, blh, t2len, lOOVV, lS, s);
-      // Y1[x][a] -= sum_{n,(c,d)} S[n][(c,d)][x] lambda[n][a][(c,d)], split over chunks of blocks
-      const int CH = 8;
-      const int full = nw / CH, tail = nw % CH;
-      auto ylaunch = [&](int first, int nblk, int nbatch) {
-        if (nbatch <= 0 || nblk <= 0) return;
-        GemmDesc h = base(o, v, (int)(nblk * v2), nbatch, nullptr, pr);
-        h.atomic = 1;
-        h.alpha = R(-1);
-        h.K0 = (int)v2;
-        h.A = S + (int64_t)first * v2 * o;
-        h.sAm0 = 1;
-        h.sAk1 = v2 * o;
-        h.sAk0 = o;
-        h.sAb = (int64_t)nblk * v2 * o;
-        h.B = L + (int64_t)first * v3;
-        h.sBk1 = v3;
-        h.sBk0 = 1;
-        h.sBn0 = v2;
-        h.sBb = (int64_t)nblk * v3;
-        h.C = Y1;
-        h.sCm0 = v;
-        h.sCn0 = 1;
-        h.sCb = 0;
-        checked_gemm(h, nullptr, lS - (int64_t)first * v2 * o, winlen - (int64_t)first * v3, ov, s);
-      };
-      ylaunch(0, CH, full);
-      ylaunch(full * CH, tail, 1);
+      checked_gemm(g, cblh, t2len, lOOVV, lS, s);
+      // Y1[x][a] -= sum_(c,d) S[n][(c,d)][x] lambda[n][a][(c,d)] for every block of the table
+      GemmDesc h = base(o, v, (int)v2, cn, cbl, pr);
+      h.atomic = 1;
+      h.alpha = R(-1);
+      h.A = S;
+      h.sAm0 = 1;
+      h.sAk0 = o;
+      set4(h.cA, 0, 0, 0, v2 * o);
+      h.B = L;
+      h.sBk0 = 1;
+      h.sBn0 = v2;
+      set4(h.cB, 0, 0, 0, v3);
+      h.C = Y1;
+      h.sCm0 = v;
+      h.sCn0 = 1;
+      checked_gemm(h, cblh, lS, winlen, ov, s);
     }
     {  // term 11: Zi[J][(d,e)][b] += sum_c lambda[c][(d,e)] t2[K][I][b][c]   (block (k,i,j) = (I,J,K))
-      GemmDesc g = base((int)v2, v, v, nw, bl, pr);
+      GemmDesc g = base((int)v2, v, v, cn, cbl, pr);
       g.atomic = 1;
       g.A = L;
       g.sAm0 = 1;
@@ -601,10 +593,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
-      checked_gemm(g, blh, winlen, t2len, lOVVV, s);
+      checked_gemm(g, cblh, winlen, t2len, lOVVV, s);
     }
     {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
-      GemmDesc g = base(o, v, (int)v2, nw, bl, pr);
+      GemmDesc g = base(o, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
       g.A = t2;
       g.sAm0 = (int64_t)o * v2;
@@ -618,7 +610,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = (int64_t)o * v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * o * v, v, 0, 0);
-      checked_gemm(g, blh, t2len, winlen, (int64_t)o * o * o * v, s);
+      checked_gemm(g, cblh, t2len, winlen, (int64_t)o * o * o * v, s);
     }
     launches_ += 18;
   }
@@ -645,8 +637,9 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCn0 = 1;
       checked_gemm(g, w.owned.data(), winlen, winlen, v2, s);
     }
-    // D_ia first term: sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]
-    launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, 2, s);
+    // D_ia first term: sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]; it equals the
+    // Y1 intermediate Z34 when the same pass also evaluates the right-hand side
+    if (!rhs_terms) launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, 2, s);
     {  // D_ia second term: Rd[J][I][b][x] += sum_cd lambda[b][(c,d)] t2[x][K][(c,d)]
       GemmDesc g = base(v, o, (int)v2, no, w.d_owned, pr);
       g.atomic = 1;
@@ -708,13 +701,22 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   RTCC3_HIP(hipEventRecord(t0_, s));
   blocks(e, r);
   // accumulators
-  const char* names[] = {"tr_X1", "tr_X2p", "tr_Y1", "tr_Y2p", "tr_Z34", "tr_R15", "tr_R2",
-                         "tr_R6", "tr_R7",  "tr_R8", "tr_Zi",  "tr_R12"};
+  const char* names[] = {"tr_X1", "tr_X2p", "tr_Y1", "tr_Y2p", "tr_Z34", "tr_R15",
+                         "tr_R2", "tr_R6", "tr_R8", "tr_Zi",  "tr_R12"};
   std::vector<std::vector<int64_t>> shapes = {{o, v},       {o, o, v, v}, {o, v},       {o, o, v, v},
                                               {o, v},       {o, o, v, o}, {o, o, v, o}, {o, o, v, o},
-                                              {o, o, v, o}, {o, o, v, o}, {o, v, v, v}, {o, o, o, v}};
+                                              {o, o, v, o}, {o, v, v, v}, {o, o, o, v}};
   for (size_t i = 0; i < shapes.size(); ++i) e.zero(e.tensor(names[i], shapes[i]));
-  for (auto& w : rhs_windows_) window_pass(e, w, y, true, false);
+  if (want_density) {
+    View Dij = e.tensor("td_Dij", {o, o}), Dab = e.tensor("td_Dab", {v, v}), Rd = e.tensor("td_Rd", {o, o, v, o});
+    e.zero(Dij);
+    e.zero(Dab);
+    e.zero(Rd);
+    // one pass over the pair windows: right-hand side for the owned blocks, density terms
+    for (auto& w : den_windows_) window_pass(e, w, y, true, true);
+  } else {
+    for (auto& w : rhs_windows_) window_pass(e, w, y, true, false);
+  }
 
   // ---- final contractions of the Y1 intermediates
   View Y1 = e.tensor("tr_Y1", {o, v});
@@ -729,7 +731,7 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   e.einsum("klbx,kalb->xa", ONE, e.tensor("tr_R2", {o, o, v, o}), g_ovov, Y1);
   e.einsum("jkbx,kajb->xa", R(-1), e.tensor("tr_R6", {o, o, v, o}), Lov, Y1);
   e.einsum("xajb,jb->xa", ONE, Lov, e.tensor("tr_Z34", {o, v}), Y1);
-  e.einsum("ildj,jlda->ia", R(-1), e.tensor("tr_R7", {o, o, v, o}), g_oovv, Y1);
+  e.einsum("lidj,jlda->ia", R(-1), e.tensor("tr_R8", {o, o, v, o}), g_oovv, Y1);
   e.einsum("ildj,dlja->ia", R(-1), e.tensor("tr_R8", {o, o, v, o}), g_voov, Y1);
   e.einsum("ideb,daeb->ia", ONE, e.tensor("tr_Zi", {o, v, v, v}), g_vvvv, Y1);
   e.einsum("xljm,ljma->xa", ONE, g_oooo, e.tensor("tr_R12", {o, o, o, v}), Y1);
@@ -752,13 +754,8 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   out.Y2 = Y2;
 
   if (want_density) {
-    View Dij = e.tensor("td_Dij", {o, o}), Dab = e.tensor("td_Dab", {v, v}), Z34 = e.tensor("td_Z34", {o, v}),
-         Rd = e.tensor("td_Rd", {o, o, v, o});
-    e.zero(Dij);
-    e.zero(Dab);
-    e.zero(Z34);
-    e.zero(Rd);
-    for (auto& w : den_windows_) window_pass(e, w, y, false, true);
+    View Dij = e.tensor("td_Dij", {o, o}), Dab = e.tensor("td_Dab", {v, v}), Rd = e.tensor("td_Rd", {o, o, v, o});
+    View Z34 = e.tensor("tr_Z34", {o, v});
     View Dia = e.tensor("td_Dia", {o, v});
     e.zero(Dia);
     e.axpy(ONE, Z34, Dia);

@@ -104,6 +104,7 @@ Triples::~Triples() {
       if (w.d_part) (void)hipFree(w.d_part);
       if (w.d_owned) (void)hipFree(w.d_owned);
       if (w.d_canon) (void)hipFree(w.d_canon);
+      if (w.d_slabs) (void)hipFree(w.d_slabs);
     }
   if (eps_) (void)hipFree(eps_);
 }
@@ -166,10 +167,24 @@ void Triples::build_windows() {
         for (auto& t : ords) cur.push_back(t);
       }
   flush();
-  // ---- density windows: for each pair l <= k, all orderings of {i,l,k} for every i,
-  // with the slabs (i,l,k) and (i,k,l) first and in order of i.
-  for (int l = 0; l < o; ++l)
-    for (int k = l; k < o; ++k) {
+  // ---- density (pair) windows.  The pairs (l,k), k >= l, of one l are grouped
+  // into windows up to the budget; a window holds every ordering of {i,l,k}
+  // for all i and its pairs, with the slabs (i,l,k) and (i,k,l) first and in
+  // order of i.  A canonical triple (x <= y <= z) is owned by the window of
+  // the pair (x,y); each triple is built in at most two windows.
+  for (int l = 0; l < o; ++l) {
+    int k0 = l;
+    while (k0 < o) {
+      // grow the pair range [k0, k1) while the union of blocks fits
+      int k1 = k0 + 1;
+      auto count = [&](int kend) {
+        std::map<std::array<int, 3>, int> seen;
+        for (int k = k0; k < kend; ++k)
+          for (int i = 0; i < o; ++i)
+            for (auto& t : orderings(i, l, k)) seen[t] = 1;
+        return (int)seen.size();
+      };
+      while (k1 < o && count(k1 + 1) <= wmax) ++k1;
       std::vector<std::array<int, 3>> bl;
       std::map<std::array<int, 3>, int> seen;
       auto add = [&](std::array<int, 3> t) {
@@ -177,26 +192,32 @@ void Triples::build_windows() {
         seen[t] = (int)bl.size();
         bl.push_back(t);
       };
-      for (int i = 0; i < o; ++i) add({i, l, k});
-      if (l != k)
-        for (int i = 0; i < o; ++i) add({i, k, l});
-      for (int i = 0; i < o; ++i)
-        for (auto& t : orderings(i, l, k)) add(t);
       Window w;
-      finish_window(w, bl);
-      w.slab_lk[0] = l;
-      w.slab_lk[1] = k;
-      w.slab_start[0] = 0;
-      w.slab_start[1] = (l != k) ? o : -1;
-      // blocks owned by this window: orderings of {i,l,k} whose two smallest
-      // indices are (l,k), i.e. i >= k
-      for (int i = k; i < o; ++i)
-        for (auto& t : orderings(i, l, k)) {
-          const int n = seen.at(t);
-          w.owned.insert(w.owned.end(), {t[0], t[1], t[2], n});
+      for (int k = k0; k < k1; ++k) {
+        w.slabs.insert(w.slabs.end(), {0, 0, 0, (int)bl.size()});
+        for (int i = 0; i < o; ++i) {
+          RTCC3_CHECK(!seen.count({i, l, k}), "triples: slab block listed twice");
+          add({i, l, k});
         }
+        if (k != l) {
+          w.slabs.insert(w.slabs.end(), {0, 0, 0, (int)bl.size()});
+          for (int i = 0; i < o; ++i) {
+            RTCC3_CHECK(!seen.count({i, k, l}), "triples: slab block listed twice");
+            add({i, k, l});
+          }
+        }
+      }
+      for (int k = k0; k < k1; ++k)
+        for (int i = 0; i < o; ++i)
+          for (auto& t : orderings(i, l, k)) add(t);
+      finish_window(w, bl);
+      for (int k = k0; k < k1; ++k)
+        for (int i = k; i < o; ++i)
+          for (auto& t : orderings(i, l, k)) w.owned.insert(w.owned.end(), {t[0], t[1], t[2], seen.at(t)});
       den_windows_.push_back(w);
+      k0 = k1;
     }
+  }
   max_nw_ = 0;
   for (auto& w : rhs_windows_) max_nw_ = std::max(max_nw_, w.nw);
   for (auto& w : den_windows_) max_nw_ = std::max(max_nw_, w.nw);
@@ -207,6 +228,10 @@ void Triples::upload(Window& w) {
   RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
   RTCC3_HIP(hipMalloc(&w.d_part, sizeof(int) * w.part.size()));
   RTCC3_HIP(hipMemcpy(w.d_part, w.part.data(), sizeof(int) * w.part.size(), hipMemcpyHostToDevice));
+  if (!w.slabs.empty()) {
+    RTCC3_HIP(hipMalloc(&w.d_slabs, sizeof(int) * w.slabs.size()));
+    RTCC3_HIP(hipMemcpy(w.d_slabs, w.slabs.data(), sizeof(int) * w.slabs.size(), hipMemcpyHostToDevice));
+  }
   RTCC3_HIP(hipMalloc(&w.d_canon, sizeof(int) * w.canon.size()));
   RTCC3_HIP(hipMemcpy(w.d_canon, w.canon.data(), sizeof(int) * w.canon.size(), hipMemcpyHostToDevice));
   if (!w.owned.empty()) {
@@ -658,35 +683,24 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       checked_gemm(g, w.owned.data(), winlen, t2len, (int64_t)o * o * v * o, s);
     }
   }
-  if (density_terms) {
-    // D_ij += -1/2 sum_abc t_{ilk} lambda_{jlk} over the slabs (., l, k) and (., k, l)
+  if (density_terms && !w.slabs.empty()) {
+    // D_ij += -1/2 sum_abc t_{ilk} lambda_{jlk}, one batch entry per slab (., l, k)
     cplx* Dij = P("td_Dij", {o, o});
-    for (int sl = 0; sl < 2; ++sl) {
-      if (w.slab_start[sl] < 0) continue;
-      const int64_t base0 = (int64_t)w.slab_start[sl] * v3;
-      const int64_t KC = std::min<int64_t>(v3, 4096);
-      const int64_t full = v3 / KC, rem = v3 % KC;
-      auto dl = [&](int64_t k0, int64_t kc, int64_t nb) {
-        if (nb <= 0 || kc <= 0) return;
-        GemmDesc g = base(o, o, (int)kc, (int)nb, nullptr, pr);
-        g.atomic = 1;
-        g.alpha = R(-0.5);
-        g.A = T + base0 + k0;
-        g.sAm0 = v3;
-        g.sAk0 = 1;
-        g.sAb = kc;
-        g.B = L + base0 + k0;
-        g.sBk0 = 1;
-        g.sBn0 = v3;
-        g.sBb = kc;
-        g.C = Dij;
-        g.sCm0 = o;
-        g.sCn0 = 1;
-        checked_gemm(g, nullptr, winlen - base0 - k0, winlen - base0 - k0, (int64_t)o * o, s);
-      };
-      dl(0, KC, full);
-      dl(full * KC, rem, 1);
-    }
+    GemmDesc g = base(o, o, (int)v3, (int)w.slabs.size() / 4, w.d_slabs, pr);
+    g.atomic = 1;
+    g.alpha = R(-0.5);
+    g.A = T;
+    g.sAm0 = v3;
+    g.sAk0 = 1;
+    set4(g.cA, 0, 0, 0, v3);
+    g.B = L;
+    g.sBk0 = 1;
+    g.sBn0 = v3;
+    set4(g.cB, 0, 0, 0, v3);
+    g.C = Dij;
+    g.sCm0 = o;
+    g.sCn0 = 1;
+    checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s);
   }
 }
 

@@ -21,21 +21,23 @@ struct Window {
   std::vector<int> part;      // [nw][6]: window indices of (ijk),(jik),(ikj),(kji),(kij),(jki)
   std::vector<int> owned;     // [*][4]: blocks whose density terms this window accumulates
   std::vector<int> canon;     // [*][4]: I <= J <= K and the slot of that ordering, one per distinct triple
-  int slab_lk[2] = {-1, -1};  // density windows: the occupied pair (l,k) of the D_ij slabs
-  int slab_start[2] = {0, 0}; // window index of block (0,l,k) and (0,k,l); blocks (i,l,k) are consecutive in i
+  std::vector<int> slabs;     // density windows: [*][4] = (0, 0, 0, slot of block (0,l,k)); the o blocks
+                              // (i,l,k) of a slab occupy consecutive slots in i
   int* d_bl = nullptr;
   int* d_part = nullptr;
   int* d_owned = nullptr;
   int* d_canon = nullptr;
+  int* d_slabs = nullptr;
 };
 
 class Triples {
  public:
   Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int precision);
   ~Triples();
-  // Run all windows.  want_density: also the triples density terms (separate
-  // pass over slab windows that hold, for an occupied pair (l,k), the blocks
-  // (i,l,k) of every i).
+  // Run all windows.  want_density: also the triples density terms; the pass
+  // then runs over pair windows that hold, for occupied pairs (l,k), the
+  // slabs of blocks (i,l,k) of every i, and evaluates the right-hand side for
+  // the blocks each window owns.
   TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density);
   void set_precision(int p) { prec_ = p; }
   void reset_timing() { ms_ = 0; launches_ = 0; }

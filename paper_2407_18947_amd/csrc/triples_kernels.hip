@@ -81,11 +81,21 @@ __global__ void comb_kernel(const cplx* __restrict__ T, cplx* __restrict__ Z, co
   Z[(int64_t)n * v3 + e] = r;
 }
 
+// Contractions with one free virtual index per block (I,J,K), all from one
+// coalesced sweep over t[x][y][z] (z fastest), slab by slab in x:
+//   flags&1: X1[I][a]      += sum_bc t[a,b,c] L[J,b,K,c]  - sum_bc t[c,b,a] L[J,b,K,c]
+//            X2p[I,J][a,b] += sum_c  t[a,b,c] f~[K,c]     - sum_c  t[c,b,a] f~[K,c]
+//   flags&2: Z[I][a]       += sum_bc t[a,b,c] l2[J,K,b,c] - sum_bc t[b,a,c] l2[J,K,b,c]
+// In sweep coordinates (x,y,z) the six pieces are: X1a[x] = sum_yz t L[y][z],
+// X1b[z] = sum_xy t L[y][x], X2a[x][y] = sum_z t f[z], X2b[z][y] = sum_x t f[x],
+// Za[x] = sum_yz t l2[y][z], Zb[y] = sum_xz t l2[x][z].
+// Same contractions, one (block, a) per workgroup; used when v*v is too large for
+// the slab buffer of small_t3_kernel.
 // Contractions with one free virtual index per block (I,J,K):
 //   flags&1: X1[I][a]     += sum_bc (t[a,b,c] - t[c,b,a]) L[J,b,K,c]
 //            X2p[I,J][a,b]+= sum_c  (t[a,b,c] - t[c,b,a]) f~[K, c]
 //   flags&2: Z[I][a]      += sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]
-__global__ void small_t3_kernel(const cplx* __restrict__ T, const int* __restrict__ bl, const cplx* __restrict__ Lov,
+__global__ void small_t3_simple_kernel(const cplx* __restrict__ T, const int* __restrict__ bl, const cplx* __restrict__ Lov,
                                 const cplx* __restrict__ F, const cplx* __restrict__ l2, cplx* __restrict__ X1,
                                 cplx* __restrict__ X2p, cplx* __restrict__ Z, int o, int v, int flags) {
   const int q = blockIdx.y, a = blockIdx.x;
@@ -123,6 +133,111 @@ __global__ void small_t3_kernel(const cplx* __restrict__ T, const int* __restric
   if (threadIdx.x == 0) {
     if (flags & 1) catomic(&X1[(int64_t)I * v + a], red[0][0]);
     if (flags & 2) catomic(&Z[(int64_t)I * v + a], red[1][0]);
+  }
+}
+
+// One workgroup of SW_NW waves per block; lane = z (unit stride), wave w owns
+// the rows y = w, w+SW_NW, ... (v <= 64).  Sums over z are wave reductions,
+// sums over x stay in registers, sums over y go through LDS once at the end.
+constexpr int SW_NW = 8;
+constexpr int SW_MAXY = 8;
+
+__global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* __restrict__ T, const int* __restrict__ bl,
+                                                              const cplx* __restrict__ Lov, const cplx* __restrict__ F,
+                                                              const cplx* __restrict__ l2, cplx* __restrict__ X1,
+                                                              cplx* __restrict__ X2p, cplx* __restrict__ Z, int o,
+                                                              int v, int flags) {
+  __shared__ cplx sx[2][SW_NW][64];  // per-wave partials of X1a[x], Za[x]
+  __shared__ cplx sz[SW_NW][64];     // per-wave partials of X1b[z]
+  const int q = blockIdx.x;
+  const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
+  const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
+  const int nn = o + v;
+  const cplx* t = T + (int64_t)n * v3;
+  const cplx* fK = F + (int64_t)K * nn + o;
+  const cplx* l2JK = l2 + ((int64_t)J * o + K) * v2;
+  const cplx* LJ = Lov + (int64_t)J * v * o * v + (int64_t)K * v;  // L[J,y,K,z] = LJ[y*o*v + z]
+  const int64_t Ly = (int64_t)o * v;
+  const bool doX = flags & 1, doZ = flags & 2;
+  const int z = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool zin = z < v;
+  const int ny = (v - w + SW_NW - 1) / SW_NW;  // rows of this wave
+  cplx a3[SW_MAXY], a5[SW_MAXY];
+#pragma unroll
+  for (int k = 0; k < SW_MAXY; ++k) {
+    a3[k] = cplx{0, 0};
+    a5[k] = cplx{0, 0};
+  }
+  cplx a4{0, 0};
+  const cplx fz = zin ? fK[z] : cplx{0, 0};
+  for (int x = 0; x < v; ++x) {
+    const cplx fx = fK[x];
+    const cplx* tx = t + (int64_t)x * v2;
+    cplx p1{0, 0}, p2{0, 0};
+#pragma unroll
+    for (int k = 0; k < SW_MAXY; ++k) {
+      if (k < ny) {
+        const int y = w + SW_NW * k;
+        const cplx tv = zin ? tx[(int64_t)y * v + z] : cplx{0, 0};
+        if (doX) {
+          if (zin) {
+            p1 = cadd(p1, cmul(tv, LJ[y * Ly + z]));
+            a3[k] = cadd(a3[k], cmul(tv, fx));
+            a4 = cadd(a4, cmul(tv, LJ[y * Ly + x]));
+          }
+          // X2a[x][y] = sum_z t[x,y,z] f[z]: wave reduction over the lanes
+          cplx r = cmul(tv, fz);
+          for (int off = 32; off > 0; off >>= 1) {
+            r.re += __shfl_xor(r.re, off);
+            r.im += __shfl_xor(r.im, off);
+          }
+          if (z == 0) catomic(&X2p[(((int64_t)I * o + J) * v + x) * v + y], r);
+        }
+        if (doZ && zin) {
+          p2 = cadd(p2, cmul(tv, l2JK[(int64_t)y * v + z]));
+          a5[k] = cadd(a5[k], cmul(tv, l2JK[(int64_t)x * v + z]));
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      p1.re += __shfl_xor(p1.re, off);
+      p1.im += __shfl_xor(p1.im, off);
+      p2.re += __shfl_xor(p2.re, off);
+      p2.im += __shfl_xor(p2.im, off);
+    }
+    if (z == 0) {
+      sx[0][w][x] = p1;
+      sx[1][w][x] = p2;
+    }
+  }
+  // X2b[z][y] = sum_x t[x,y,z] f[x] (subtracted); Zb[y] = sum_xz t l2[x][z] (subtracted)
+#pragma unroll
+  for (int k = 0; k < SW_MAXY; ++k) {
+    if (k < ny) {
+      const int y = w + SW_NW * k;
+      if (doX && zin) catomic(&X2p[(((int64_t)I * o + J) * v + z) * v + y], cplx{-a3[k].re, -a3[k].im});
+      if (doZ) {
+        cplx r = a5[k];
+        for (int off = 32; off > 0; off >>= 1) {
+          r.re += __shfl_xor(r.re, off);
+          r.im += __shfl_xor(r.im, off);
+        }
+        if (z == 0) catomic(&Z[(int64_t)I * v + y], cplx{-r.re, -r.im});
+      }
+    }
+  }
+  sz[w][z] = a4;
+  __syncthreads();
+  if (threadIdx.x < v) {
+    const int a = threadIdx.x;
+    cplx s1{0, 0}, s2{0, 0}, s4{0, 0};
+    for (int ww = 0; ww < SW_NW; ++ww) {
+      s1 = cadd(s1, sx[0][ww][a]);
+      s2 = cadd(s2, sx[1][ww][a]);
+      s4 = cadd(s4, sz[ww][a]);
+    }
+    if (doX) catomic(&X1[(int64_t)I * v + a], csub(s1, s4));
+    if (doZ) catomic(&Z[(int64_t)I * v + a], s2);
   }
 }
 
@@ -239,8 +354,13 @@ void launch_comb(const cplx* T, cplx* Z, const int* bl, int v, int nb, int mode,
 void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, const cplx* F, const cplx* l2, cplx* X1,
                      cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(small_t3_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1, X2p, Z,
-                     o, v, flags);
+  if (v <= 64) {
+    hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p, Z, o,
+                       v, flags);
+  } else {
+    hipLaunchKernelGGL(small_t3_simple_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1,
+                       X2p, Z, o, v, flags);
+  }
   RTCC3_HIP(hipGetLastError());
 }
 

@@ -57,6 +57,15 @@ struct GemmDesc {
   cplx alpha;
   int atomic;
   int prec;
+  // Optional second K segment with the same strides: when kseg > 0 the
+  // contraction length is K = 2*kseg and k >= kseg reads A2/B2 at k - kseg
+  // (block-table offsets cA2/cB2).
+  int kseg;
+  const cplx* A2;
+  const cplx* B2;
+  int64_t cA2[4], cB2[4];
+  // store = 1: C = alpha*AB without reading C (no split-K, not atomic).
+  int store;
 };
 void gemm(const GemmDesc& d, hipStream_t s);
 

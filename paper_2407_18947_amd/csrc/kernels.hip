@@ -60,16 +60,26 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   if (kbeg >= kend) return;
   const cplx* __restrict__ A;
   const cplx* __restrict__ B;
+  const cplx* __restrict__ A2 = nullptr;
+  const cplx* __restrict__ B2 = nullptr;
   cplx* __restrict__ C;
   if (d.bl) {
     const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
     A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
     B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
     C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
+    if (d.kseg) {
+      A2 = d.A2 + d.cA2[0] * I + d.cA2[1] * J + d.cA2[2] * K + d.cA2[3] * n;
+      B2 = d.B2 + d.cB2[0] * I + d.cB2[1] * J + d.cB2[2] * K + d.cB2[3] * n;
+    }
   } else {
     A = d.A + b * d.sAb;
     B = d.B + b * d.sBb;
     C = d.C + b * d.sCb;
+    if (d.kseg) {
+      A2 = d.A2 + b * d.sAb;
+      B2 = d.B2 + b * d.sBb;
+    }
   }
 
   const int tid = threadIdx.x;
@@ -108,17 +118,30 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     }
 
   cplx av[4], bv[4];
+  const int kseg = d.kseg;
   auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int ka = k0 + akk[r];
+      int ka = k0 + akk[r];
       av[r] = cplx{0.0, 0.0};
-      if (aval[r] && ka < kend)
-        av[r] = A[aoff[r] + (int64_t)(ka / d.K0) * d.sAk1 + (int64_t)(ka % d.K0) * d.sAk0];
-      const int kb = k0 + bkk[r];
+      if (aval[r] && ka < kend) {
+        const cplx* pa = A;
+        if (kseg && ka >= kseg) {
+          pa = A2;
+          ka -= kseg;
+        }
+        av[r] = pa[aoff[r] + (int64_t)(ka / d.K0) * d.sAk1 + (int64_t)(ka % d.K0) * d.sAk0];
+      }
+      int kb = k0 + bkk[r];
       bv[r] = cplx{0.0, 0.0};
-      if (bval[r] && kb < kend)
-        bv[r] = B[boff[r] + (int64_t)(kb / d.K0) * d.sBk1 + (int64_t)(kb % d.K0) * d.sBk0];
+      if (bval[r] && kb < kend) {
+        const cplx* pb = B;
+        if (kseg && kb >= kseg) {
+          pb = B2;
+          kb -= kseg;
+        }
+        bv[r] = pb[boff[r] + (int64_t)(kb / d.K0) * d.sBk1 + (int64_t)(kb % d.K0) * d.sBk0];
+      }
     }
   };
 
@@ -182,6 +205,8 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
                     (int64_t)(n / d.N0) * d.sCn1 + (int64_t)(n % d.N0) * d.sCn0;
           if (ATOMIC) {
             atomic_add_cplx(p, vr, vi);
+          } else if (d.store) {
+            *p = cplx{vr, vi};
           } else {
             cplx c = *p;
             c.re += vr;
@@ -231,9 +256,11 @@ void gemm(const GemmDesc& d, hipStream_t s) {
   const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   // Split K across workgroups when the grid is too small to fill the chip and
   // K is long; the partial products are then added with atomics.
+  RTCC3_CHECK(!d.kseg || (d.K == 2 * d.kseg && d.A2 && d.B2), "gemm: bad K segments");
+  RTCC3_CHECK(!d.store || !d.atomic, "gemm: store mode cannot be atomic");
   int ksplit = 1;
   const int64_t wgs = tiles * d.batch;
-  if (wgs < 512 && d.K >= 8 * BK) {
+  if (!d.store && wgs < 512 && d.K >= 8 * BK) {
     const int64_t want = (1024 + wgs - 1) / wgs;
     const int64_t maxs = d.K / (4 * BK);
     ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));

@@ -55,10 +55,12 @@ int64_t span(int64_t X, int64_t X0, int64_t s1, int64_t s0) {
 
 // Launch a GEMM after checking, on the host, that every batch entry stays
 // inside the operand buffers (lengths in elements).
-void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
+void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s,
+                  int64_t lenA2 = 0, int64_t lenB2 = 0) {
   if (g.batch <= 0) return;
-  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + span(g.K, g.K0, g.sAk1, g.sAk0);
-  const int64_t eB = span(g.K, g.K0, g.sBk1, g.sBk0) + span(g.N, g.N0, g.sBn1, g.sBn0);
+  const int kl = g.kseg ? g.kseg : g.K;  // contraction length per segment
+  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + span(kl, g.K0, g.sAk1, g.sAk0);
+  const int64_t eB = span(kl, g.K0, g.sBk1, g.sBk0) + span(g.N, g.N0, g.sBn1, g.sBn0);
   const int64_t eC = span(g.M, g.M0, g.sCm1, g.sCm0) + span(g.N, g.N0, g.sCn1, g.sCn0);
   for (int b = 0; b < g.batch; ++b) {
     int64_t oA, oB, oC;
@@ -75,6 +77,14 @@ void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t l
     RTCC3_CHECK(oA >= 0 && oA + eA < lenA, "triples: A operand out of bounds");
     RTCC3_CHECK(oB >= 0 && oB + eB < lenB, "triples: B operand out of bounds");
     RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
+    if (g.kseg) {
+      RTCC3_CHECK(g.bl, "triples: K segments need a block table");
+      const int* q = bl_host + 4 * b;
+      const int64_t oA2 = g.cA2[0] * q[0] + g.cA2[1] * q[1] + g.cA2[2] * q[2] + g.cA2[3] * q[3];
+      const int64_t oB2 = g.cB2[0] * q[0] + g.cB2[1] * q[1] + g.cB2[2] * q[2] + g.cB2[3] * q[3];
+      RTCC3_CHECK(oA2 >= 0 && oA2 + eA < lenA2, "triples: A2 operand out of bounds");
+      RTCC3_CHECK(oB2 >= 0 && oB2 + eB < lenB2, "triples: B2 operand out of bounds");
+    }
   }
   gemm(g, s);
 }
@@ -257,16 +267,16 @@ void Triples::blocks(Engine& e, const CCSDResult& r) {
   e.einsum("Pck,Pbe->kbce", ONE, B('v', 'o'), B('v', 'v'), t);
   t = make("tb_W2", {o, o, o, v});  // (mj|ck) at [j][k][m][c]
   e.einsum("Pmj,Pck->jkmc", ONE, B('o', 'o'), B('v', 'o'), t);
-  t = make("tb_LA", {o, v, v, v});  // (ka|db) at [k][a][b][d]
-  e.einsum("Pka,Pdb->kabd", ONE, B('o', 'v'), B('v', 'v'), t);
+  t = make("tb_LA", {o, v, v, v});  // -(ka|db) at [k][a][b][d]
+  e.einsum("Pka,Pdb->kabd", R(-1), B('o', 'v'), B('v', 'v'), t);
   t = make("tb_LB", {o, v, v, v});  // 2(da|jb) - (db|ja) at [j][a][b][d]
   e.einsum("Pda,Pjb->jabd", R(2), B('v', 'v'), B('o', 'v'), t);
   e.einsum("Pdb,Pja->jabd", R(-1), B('v', 'v'), B('o', 'v'), t);
   t = make("tb_LC", {o, v, o, o});  // (ka|jl) at [k][a][j][l]
   e.einsum("Pka,Pjl->kajl", ONE, B('o', 'v'), B('o', 'o'), t);
-  t = make("tb_LD", {o, o, v, o});  // 2(ia|jl) - (il|ja) at [i][j][a][l]
-  e.einsum("Pia,Pjl->ijal", R(2), B('o', 'v'), B('o', 'o'), t);
-  e.einsum("Pil,Pja->ijal", R(-1), B('o', 'o'), B('o', 'v'), t);
+  t = make("tb_LD", {o, v, o, o});  // -(2(ia|jl) - (il|ja)) at [i][a][j][l]
+  e.einsum("Pia,Pjl->iajl", R(-2), B('o', 'v'), B('o', 'o'), t);
+  e.einsum("Pil,Pja->iajl", ONE, B('o', 'o'), B('o', 'v'), t);
   t = make("tb_X2a", {o, v, v, v});  // (ac|ke) at [k][a][c][e]
   e.einsum("Pac,Pke->kace", ONE, B('v', 'v'), B('o', 'v'), t);
   t = make("tb_X2b", {o, o, o, v});  // (ki|mc) at [k][m][i][c]
@@ -309,7 +319,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const cplx* gLA = P("tb_LA", {o, v, v, v});
   const cplx* gLB = P("tb_LB", {o, v, v, v});
   const cplx* gLC = P("tb_LC", {o, v, o, o});
-  const cplx* gLD = P("tb_LD", {o, o, v, o});
+  const cplx* gLD = P("tb_LD", {o, v, o, o});
   const cplx* gX2a = P("tb_X2a", {o, v, v, v});
   const cplx* gX2b = P("tb_X2b", {o, o, o, v});
   const cplx* gY2a = P("tb_Y2a", {o, v, v, v});
@@ -326,7 +336,24 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int pr = prec_;
 
   // ---------------- t3 blocks
-  fill(W, (int64_t)nw * v3, cplx{0, 0}, s);
+  {  // W[n][(a,b)][c] = -sum_m t2[I][m][(a,b)] (mj|ck)~[J][K][m][c]   (store: initialises W)
+    GemmDesc g = base((int)v2, v, o, nw, bl, pr);
+    g.store = 1;
+    g.alpha = R(-1);
+    g.A = t2;
+    g.sAm0 = 1;
+    g.sAk0 = v2;
+    set4(g.cA, (int64_t)o * v2, 0, 0, 0);
+    g.B = gW2;
+    g.sBk0 = v;
+    g.sBn0 = 1;
+    set4(g.cB, 0, (int64_t)o * o * v, (int64_t)o * v, 0);
+    g.C = W;
+    g.sCm0 = v;
+    g.sCn0 = 1;
+    set4(g.cC, 0, 0, 0, v3);
+    checked_gemm(g, blh, t2len, lOOOV, winlen, s);
+  }
   {  // W[n][a][(b,c)] += sum_e t2[I][J][a][e] (ck|be)~[K][(b,c)][e]
     GemmDesc g = base(v, (int)v2, v, nw, bl, pr);
     g.A = t2;
@@ -343,76 +370,60 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, v3);
     checked_gemm(g, blh, t2len, lOVVV, winlen, s);
   }
-  {  // W[n][(a,b)][c] -= sum_m t2[I][m][(a,b)] (mj|ck)~[J][K][m][c]
-    GemmDesc g = base((int)v2, v, o, nw, bl, pr);
-    g.alpha = R(-1);
-    g.A = t2;
-    g.sAm0 = 1;
-    g.sAk0 = v2;
-    set4(g.cA, (int64_t)o * v2, 0, 0, 0);
-    g.B = gW2;
-    g.sBk0 = v;
-    g.sBn0 = 1;
-    set4(g.cB, 0, (int64_t)o * o * v, (int64_t)o * v, 0);
-    g.C = W;
-    g.sCm0 = v;
-    g.sCn0 = 1;
-    set4(g.cC, 0, 0, 0, v3);
-    checked_gemm(g, blh, t2len, lOOOV, winlen, s);
-  }
-  launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, s);
+  launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
 
   // ---------------- lambda3 blocks
-  fill(W, (int64_t)nw * v3, cplx{0, 0}, s);
-  {  // W[n][(a,b)][c] -= sum_d (ka|db)~[K][(a,b)][d] l2[I][J][c][d]
-    GemmDesc g = base((int)v2, v, v, nw, bl, pr);
-    g.alpha = R(-1);
-    g.A = gLA;
-    g.sAm0 = v;
-    g.sAk0 = 1;
-    set4(g.cA, 0, 0, v3, 0);
-    g.B = l2;
-    g.sBk0 = 1;
-    g.sBn0 = v;
-    set4(g.cB, (int64_t)o * v2, v2, 0, 0);
-    g.C = W;
-    g.sCm0 = v;
-    g.sCn0 = 1;
-    set4(g.cC, 0, 0, 0, v3);
-    checked_gemm(g, blh, lOVVV, l2len, winlen, s);
-    // W[n][(a,b)][c] += sum_d Lt_djab[J][(a,b)][d] l2[K][I][c][d]
-    g.alpha = ONE;
-    g.A = gLB;
-    set4(g.cA, 0, v3, 0, 0);
-    set4(g.cB, v2, 0, (int64_t)o * v2, 0);
-    checked_gemm(g, blh, lOVVV, l2len, winlen, s);
-  }
-  {  // W[n][a][(b,c)] += sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)]
-    GemmDesc g = base(v, (int)v2, o, nw, bl, pr);
+  {  // W[n][a][(b,c)] = sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)] - sum_l Lt_ijal[I][a][J][l] l2[l][K][(b,c)]
+    GemmDesc g = base(v, (int)v2, 2 * o, nw, bl, pr);
+    g.store = 1;
+    g.kseg = o;
+    g.K0 = o;
     g.A = gLC;
     g.sAm0 = (int64_t)o * o;
     g.sAk0 = 1;
     set4(g.cA, 0, o, (int64_t)v * o * o, 0);
+    g.A2 = gLD;
+    set4(g.cA2, (int64_t)v * o * o, o, 0, 0);
     g.B = l2;
     g.sBk0 = (int64_t)o * v2;
     g.sBn0 = 1;
     set4(g.cB, v2, 0, 0, 0);
+    g.B2 = l2;
+    set4(g.cB2, 0, 0, v2, 0);
     g.C = W;
     g.sCm0 = v2;
     g.sCn0 = 1;
     set4(g.cC, 0, 0, 0, v3);
-    checked_gemm(g, blh, (int64_t)o * v * o * o, l2len, winlen, s);
-    // W[n][a][(b,c)] -= sum_l Lt_ijal[I][J][a][l] l2[l][K][(b,c)]
-    g.alpha = R(-1);
-    g.A = gLD;
-    g.sAm0 = o;
-    set4(g.cA, (int64_t)o * v * o, (int64_t)v * o, 0, 0);
-    set4(g.cB, 0, 0, v2, 0);
-    checked_gemm(g, blh, (int64_t)o * o * v * o, l2len, winlen, s);
+    const int64_t lLC = (int64_t)o * v * o * o;
+    checked_gemm(g, blh, lLC, l2len, winlen, s, lLC, l2len);
   }
-  launch_lam_elem(W, bl, Lov, F, l1, l2, o, v, nw, s);
-  launch_sym_cube(W, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, s);
-  launches_ += 10;
+  {  // W[n][(a,b)][c] += sum_d -(ka|db)~[K][(a,b)][d] l2[I][J][c][d] + sum_d Lt_djab[J][(a,b)][d] l2[K][I][c][d]
+    GemmDesc g = base((int)v2, v, 2 * v, nw, bl, pr);
+    g.kseg = v;
+    g.K0 = v;
+    g.A = gLA;
+    g.sAm0 = v;
+    g.sAk0 = 1;
+    set4(g.cA, 0, 0, v3, 0);
+    g.A2 = gLB;
+    set4(g.cA2, 0, v3, 0, 0);
+    g.B = l2;
+    g.sBk0 = 1;
+    g.sBn0 = v;
+    set4(g.cB, (int64_t)o * v2, v2, 0, 0);
+    g.B2 = l2;
+    set4(g.cB2, v2, 0, (int64_t)o * v2, 0);
+    g.C = W;
+    g.sCm0 = v;
+    g.sCn0 = 1;
+    set4(g.cC, 0, 0, 0, v3);
+    checked_gemm(g, blh, lOVVV, l2len, winlen, s, lOVVV, l2len);
+  }
+  {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
+    LamElem le{Lov, F, l1, l2};
+    launch_sym_cube(W, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, &le, s);
+  }
+  launches_ += 5;
 
   if (rhs_terms) {
     // Contractions run over the blocks this window is responsible for: all of

@@ -7,14 +7,19 @@
 
 namespace rtcc3 {
 
-void launch_sym_div(const cplx* W, cplx* T, const int* part, const int* bl, const double* eps, int o, int v, int nb,
-                    hipStream_t s);
+// Inputs of the lambda3 bracket terms that carry no summation index.
+struct LamElem {
+  const cplx* Lov = nullptr;  // L_iajb = 2(ia|jb)~ - (ib|ja)~, [o][v][o][v]
+  const cplx* F = nullptr;    // dressed Fock, [n][n]
+  const cplx* l1 = nullptr;   // [o][v]
+  const cplx* l2 = nullptr;   // [o][o][v][v]
+};
 // Symmetrise and divide for the canonical triples of a window (canon: 4 ints
 // per entry, I <= J <= K and the slot of that ordering); writes all orderings.
+// le (may be null): add the lambda3 bracket terms without a summation index to
+// every source element first.
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
-                     int v, hipStream_t s);
-void launch_lam_elem(cplx* W, const int* bl, const cplx* Lov, const cplx* F, const cplx* l1, const cplx* l2, int o,
-                     int v, int nb, hipStream_t s);
+                     int v, const LamElem* le, hipStream_t s);
 void launch_comb(const cplx* T, cplx* Z, const int* bl, int v, int nb, int mode, hipStream_t s);
 void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, const cplx* F, const cplx* l2, cplx* X1,
                      cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s);

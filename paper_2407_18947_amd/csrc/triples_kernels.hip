@@ -17,49 +17,6 @@ __device__ __forceinline__ void catomic(cplx* p, cplx x) {
   unsafeAtomicAdd(&p->im, x.im);
 }
 
-// t_ijk^abc = P_ijk^abc W'_ijk^abc / D_ijk^abc with
-// P f_ijk^abc = f_ijk^abc + f_jik^bac + f_ikj^acb + f_kji^cba + f_kij^cab + f_jki^bca.
-__global__ void sym_div_kernel(const cplx* __restrict__ W, cplx* __restrict__ T, const int* __restrict__ part,
-                               const int* __restrict__ bl, const double* __restrict__ eps, int o, int v) {
-  const int q = blockIdx.y;
-  const int64_t v3 = (int64_t)v * v * v;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= v3) return;
-  const int a = (int)(e / ((int64_t)v * v)), b = (int)((e / v) % v), c = (int)(e % v);
-  const int* p = part + 6 * q;
-  const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
-  auto at = [&](int s, int x, int y, int z) { return W[(int64_t)p[s] * v3 + ((int64_t)x * v + y) * v + z]; };
-  cplx s = at(0, a, b, c);
-  s = cadd(s, at(1, b, a, c));
-  s = cadd(s, at(2, a, c, b));
-  s = cadd(s, at(3, c, b, a));
-  s = cadd(s, at(4, c, a, b));
-  s = cadd(s, at(5, b, c, a));
-  const double D = eps[I] + eps[J] + eps[K] - eps[o + a] - eps[o + b] - eps[o + c];
-  T[(int64_t)n * v3 + e] = cplx{s.re / D, s.im / D};
-}
-
-// Terms of the lambda3 bracket without a summation index:
-//   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik
-__global__ void lam_elem_kernel(cplx* __restrict__ W, const int* __restrict__ bl, const cplx* __restrict__ Lov,
-                                const cplx* __restrict__ F, const cplx* __restrict__ l1, const cplx* __restrict__ l2,
-                                int o, int v) {
-  const int q = blockIdx.y;
-  const int64_t v3 = (int64_t)v * v * v;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= v3) return;
-  const int a = (int)(e / ((int64_t)v * v)), b = (int)((e / v) % v), c = (int)(e % v);
-  const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
-  const int nn = o + v;
-  const cplx* Lij = Lov + (((int64_t)I * v + a) * o + J) * v;  // L[I,a,J,:]
-  cplx x = cmul(Lij[b], l1[(int64_t)K * v + c]);
-  x = csub(x, cmul(Lij[c], l1[(int64_t)K * v + b]));
-  x = cadd(x, cmul(F[(int64_t)I * nn + o + a], l2[(((int64_t)J * o + K) * v + b) * v + c]));
-  x = csub(x, cmul(F[(int64_t)J * nn + o + a], l2[(((int64_t)I * o + K) * v + b) * v + c]));
-  cplx* w = W + (int64_t)n * v3 + e;
-  *w = cadd(*w, x);
-}
-
 // mode 0: Z[n][b][c][e] = 2 t[c,b,e] - t[c,e,b] - t[e,b,c]
 // mode 1: Z[n][a][b][c] = 2 t[c,b,a] - t[b,c,a] - t[a,b,c]
 __global__ void comb_kernel(const cplx* __restrict__ T, cplx* __restrict__ Z, const int* __restrict__ bl, int v,
@@ -251,9 +208,14 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
 constexpr int CB = 8;
 __device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}};
 
+// With LAM, each source element first receives the terms of the lambda3 bracket
+// that carry no summation index,
+//   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik,
+// evaluated at that source's own occupied and virtual indices.
+template <bool LAM>
 __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ W, cplx* __restrict__ T,
                                                          const int* __restrict__ canon, const int* __restrict__ part,
-                                                         const double* __restrict__ eps, int o, int v) {
+                                                         const double* __restrict__ eps, int o, int v, LamElem le) {
   __shared__ cplx acc[CB * CB * CB];
   const int q = blockIdx.y;
   const int I = canon[4 * q], J = canon[4 * q + 1], K = canon[4 * q + 2], n0 = canon[4 * q + 3];
@@ -267,10 +229,13 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   const int64_t v3 = (int64_t)v * v * v;
   for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) acc[e] = cplx{0, 0};
   __syncthreads();
+  const int occ[3] = {I, J, K};
+  const int nn = o + v;
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
     const int x0 = t0[p0], x1 = t0[p1], x2 = t0[p2];
     const cplx* src = W + (int64_t)sl[s] * v3;
+    const int si = occ[p0], sj = occ[p1], sk = occ[p2];  // the source's occupied triple
     for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
       const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
@@ -279,7 +244,14 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
         tl[p0] = u0;
         tl[p1] = u1;
         tl[p2] = u2;
-        const cplx w = src[((int64_t)X0 * v + X1) * v + X2];
+        cplx w = src[((int64_t)X0 * v + X1) * v + X2];
+        if (LAM) {
+          const cplx* Lij = le.Lov + (((int64_t)si * v + X0) * o + sj) * v;  // L[si,X0,sj,:]
+          w = cadd(w, cmul(Lij[X1], le.l1[(int64_t)sk * v + X2]));
+          w = csub(w, cmul(Lij[X2], le.l1[(int64_t)sk * v + X1]));
+          w = cadd(w, cmul(le.F[(int64_t)si * nn + o + X0], le.l2[(((int64_t)sj * o + sk) * v + X1) * v + X2]));
+          w = csub(w, cmul(le.F[(int64_t)sj * nn + o + X0], le.l2[(((int64_t)si * o + sk) * v + X1) * v + X2]));
+        }
         cplx& r = acc[(tl[0] * CB + tl[1]) * CB + tl[2]];
         r.re += w.re;
         r.im += w.im;
@@ -322,26 +294,16 @@ inline dim3 blocks_v3(int v, int nb) {
 
 }  // namespace
 
-void launch_sym_div(const cplx* W, cplx* T, const int* part, const int* bl, const double* eps, int o, int v, int nb,
-                    hipStream_t s) {
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(sym_div_kernel, blocks_v3(v, nb), dim3(256), 0, s, W, T, part, bl, eps, o, v);
-  RTCC3_HIP(hipGetLastError());
-}
-
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
-                     int v, hipStream_t s) {
+                     int v, const LamElem* le, hipStream_t s) {
   if (ncanon <= 0) return;
   const int nc = (v + CB - 1) / CB;
-  hipLaunchKernelGGL(sym_cube_kernel, dim3((unsigned)(nc * nc * nc), (unsigned)ncanon), dim3(256), 0, s, W, T, canon,
-                     part, eps, o, v);
-  RTCC3_HIP(hipGetLastError());
-}
-
-void launch_lam_elem(cplx* W, const int* bl, const cplx* Lov, const cplx* F, const cplx* l1, const cplx* l2, int o,
-                     int v, int nb, hipStream_t s) {
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(lam_elem_kernel, blocks_v3(v, nb), dim3(256), 0, s, W, bl, Lov, F, l1, l2, o, v);
+  const dim3 grid((unsigned)(nc * nc * nc), (unsigned)ncanon);
+  if (le) {
+    hipLaunchKernelGGL(sym_cube_kernel<true>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, *le);
+  } else {
+    hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, LamElem{});
+  }
   RTCC3_HIP(hipGetLastError());
 }
 

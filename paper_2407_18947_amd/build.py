@@ -14,7 +14,10 @@ OUT = os.path.join(HERE, "librtcc3.so")
 BUILD = os.path.join(HERE, "_build")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{CSRC}", f"-I{os.path.join(os.path.dirname(HERE), 'include')}"]
-DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# MFMAs in their VGPR form: accumulators that live across a loop stay in
+# VGPRs instead of being copied to and from AGPRs around every use.
+DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _hipcc() -> str:

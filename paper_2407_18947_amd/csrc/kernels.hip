@@ -11,7 +11,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int BM = 64, BK = 16, NT = 256;
 
 template <typename T>
 struct Frag;
@@ -37,17 +37,40 @@ __device__ __forceinline__ void atomic_add_cplx(cplx* p, double re, double im) {
   unsafeAtomicAdd(&p->im, im);
 }
 
-// One workgroup computes a 64x64 tile of C for one batch entry.  Waves are
-// arranged 2x2, each owning a 32x32 sub-tile = 2x2 MFMA 16x16 blocks with a
-// real and an imaginary accumulator:
+// Split k = q*K0 + r for 0 <= k < 2^22 without an integer divide: the float
+// estimate of the quotient is off by at most one, corrected either way.
+__device__ __forceinline__ void split_k(int k, int K0, float inv, int& q, int& r) {
+  q = (int)((float)k * inv);
+  r = k - q * K0;
+  q = r < 0 ? q - 1 : q;
+  r = r < 0 ? r + K0 : r;
+  q = r >= K0 ? q + 1 : q;
+  r = r >= K0 ? r - K0 : r;
+}
+
+// One workgroup computes a 64 x BN tile of C for one batch entry.  BN = 64:
+// waves arranged 2x2, each owning a 32x32 sub-tile = 2x2 MFMA 16x16 blocks;
+// BN = 16 (narrow N, e.g. one occupied index): waves stacked 4x1, each owning
+// one 16x16 block.  Every block has a real and an imaginary accumulator:
 //   Cre += Are*Bre - Aim*Bim,  Cim += Are*Bim + Aim*Bre.
 // MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16].
 // Result layout: FP32 holds D[4*(l/16)+r][l%16] in register r, FP64 holds
 // D[4*r+l/16][l%16] (Frag<T>::row).
-template <typename T, bool ATOMIC>
+//
+// Tiles of A and B go through two LDS buffers: while the MFMAs consume one,
+// the next tile is loaded into registers and then stored into the other, so
+// each K step needs one barrier.  Loads carry no branches: an element outside
+// the operand reads the entry's first element and is replaced by zero.
+// KFA: A is read with k as the fast thread index (unit stride in k), else m;
+// NFB: B is read with n as the fast thread index, else k.
+template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN>
 __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
   typedef typename Frag<T>::acc acc_t;
-  __shared__ T sAr[BK][BM + 1], sAi[BK][BM + 1], sBr[BK][BN + 1], sBi[BK][BN + 1];
+  constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
+  constexpr int IB = WM / 16, JB = WN / 16;                         // MFMA blocks per wave
+  constexpr int NEB = BN * BK / NT;                                 // B elements per thread
+  __shared__ T sA[2][2][BK][BM + 1];  // [buffer][re, im][k][m]
+  __shared__ T sB[2][2][BK][BN + 1];  // [buffer][re, im][k][n]
 
   const int tilesN = (d.N + BN - 1) / BN;
   const int kz = blockIdx.x % ksplit;
@@ -58,11 +81,11 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   const int kbeg = kz * kchunk;
   const int kend = min(d.K, kbeg + kchunk);
   if (kbeg >= kend) return;
-  const cplx* __restrict__ A;
-  const cplx* __restrict__ B;
-  const cplx* __restrict__ A2 = nullptr;
-  const cplx* __restrict__ B2 = nullptr;
-  cplx* __restrict__ C;
+  const cplx* A;
+  const cplx* B;
+  const cplx* A2 = nullptr;
+  const cplx* B2 = nullptr;
+  cplx* C;
   if (d.bl) {
     const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
     A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
@@ -81,119 +104,164 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
       B2 = d.B2 + b * d.sBb;
     }
   }
+  if (!d.kseg) {
+    A2 = A;
+    B2 = B;
+  }
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+  const float invK0 = 1.0f / (float)d.K0;
 
-  // loader geometry: 4 elements of each tile per thread, the fast thread
-  // index along the operand's unit-stride dimension when there is one
-  const bool kfastA = (d.sAk0 == 1);
-  const bool nfastB = (d.sBn0 == 1);
-  int amm[4], akk[4], bnn[4], bkk[4];
-  int64_t aoff[4], boff[4];
-  bool aval[4], bval[4];
+  // Loader geometry: element r of a thread sits at (akk[r], amm[r]) of the A
+  // tile; with KFA all four share one k (one k slot), else one m.
+  constexpr int NKA = KFA ? 1 : 4, NMA = KFA ? 4 : 1;
+  constexpr int NKB = NFB ? NEB : 1, NNB = NFB ? 1 : NEB;
+  int akk[4], amm[4], bkk[NEB], bnn[NEB];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int e = tid + NT * r;
-    amm[r] = kfastA ? e / BK : e % BM;
-    akk[r] = kfastA ? e % BK : e / BM;
+    amm[r] = KFA ? e / BK : e % BM;
+    akk[r] = KFA ? e % BK : e / BM;
+  }
+#pragma unroll
+  for (int r = 0; r < NEB; ++r) {
+    const int e = tid + NT * r;
+    bnn[r] = NFB ? e % BN : e / BK;
+    bkk[r] = NFB ? e / BN : e % BK;
+  }
+  int64_t aoff[NMA], boff[NNB];
+  bool aval[NMA], bval[NNB];
+#pragma unroll
+  for (int r = 0; r < NMA; ++r) {
     const int m = tm * BM + amm[r];
     aval[r] = m < d.M;
     aoff[r] = aval[r] ? (int64_t)(m / d.M0) * d.sAm1 + (int64_t)(m % d.M0) * d.sAm0 : 0;
-    bnn[r] = nfastB ? e % BN : e / BK;
-    bkk[r] = nfastB ? e / BN : e % BK;
+  }
+#pragma unroll
+  for (int r = 0; r < NNB; ++r) {
     const int n = tn * BN + bnn[r];
     bval[r] = n < d.N;
     boff[r] = bval[r] ? (int64_t)(n / d.N0) * d.sBn1 + (int64_t)(n % d.N0) * d.sBn0 : 0;
   }
+  // K segments: k >= kseg reads A2/B2 at k - kseg (without segments kseg is
+  // out of reach and A2 = A, B2 = B).
+  const int kseg = d.kseg ? d.kseg : 0x7fffffff;
 
-  acc_t cre[2][2], cim[2][2];
+  // Every load is issued: an element outside the operand reads offset 0 of
+  // its entry (the empty asm keeps the compiler from turning the address
+  // select back into a branch around the load) and is then replaced by zero.
+  cplx av[4], bv[NEB];
+  auto fetch = [](const cplx* p, bool ok, int64_t off) {
+    int64_t o = ok ? off : 0;
+    asm volatile("" : "+v"(o));
+    const cplx x = p[o];
+    return cplx{ok ? x.re : 0.0, ok ? x.im : 0.0};
+  };
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int s = 0; s < NKA; ++s) {
+      const int k = k0 + akk[s];
+      const bool kin = k < kend, hi = k >= kseg;
+      int q, r;
+      split_k(hi ? k - kseg : k, d.K0, invK0, q, r);
+      const int64_t ko = (int64_t)q * d.sAk1 + (int64_t)r * d.sAk0;
+      const cplx* p = hi ? A2 : A;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+      for (int t = 0; t < NMA; ++t) {
+        const int e = KFA ? t : s;
+        av[e] = fetch(p, kin && aval[KFA ? t : 0], aoff[KFA ? t : 0] + ko);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NKB; ++s) {
+      const int k = k0 + bkk[s];
+      const bool kin = k < kend, hi = k >= kseg;
+      int q, r;
+      split_k(hi ? k - kseg : k, d.K0, invK0, q, r);
+      const int64_t ko = (int64_t)q * d.sBk1 + (int64_t)r * d.sBk0;
+      const cplx* p = hi ? B2 : B;
+#pragma unroll
+      for (int t = 0; t < NNB; ++t) {
+        const int e = NFB ? s : t;
+        bv[e] = fetch(p, kin && bval[NFB ? 0 : t], boff[NFB ? 0 : t] + ko);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      sA[buf][0][akk[r]][amm[r]] = (T)av[r].re;
+      sA[buf][1][akk[r]][amm[r]] = (T)av[r].im;
+    }
+#pragma unroll
+    for (int r = 0; r < NEB; ++r) {
+      sB[buf][0][bkk[r]][bnn[r]] = (T)bv[r].re;
+      sB[buf][1][bkk[r]][bnn[r]] = (T)bv[r].im;
+    }
+  };
+
+  acc_t cre[IB][JB], cim[IB][JB];
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
       cre[i][j] = acc_t{0, 0, 0, 0};
       cim[i][j] = acc_t{0, 0, 0, 0};
     }
 
-  cplx av[4], bv[4];
-  const int kseg = d.kseg;
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int ka = k0 + akk[r];
-      av[r] = cplx{0.0, 0.0};
-      if (aval[r] && ka < kend) {
-        const cplx* pa = A;
-        if (kseg && ka >= kseg) {
-          pa = A2;
-          ka -= kseg;
-        }
-        av[r] = pa[aoff[r] + (int64_t)(ka / d.K0) * d.sAk1 + (int64_t)(ka % d.K0) * d.sAk0];
-      }
-      int kb = k0 + bkk[r];
-      bv[r] = cplx{0.0, 0.0};
-      if (bval[r] && kb < kend) {
-        const cplx* pb = B;
-        if (kseg && kb >= kseg) {
-          pb = B2;
-          kb -= kseg;
-        }
-        bv[r] = pb[boff[r] + (int64_t)(kb / d.K0) * d.sBk1 + (int64_t)(kb % d.K0) * d.sBk0];
-      }
-    }
-  };
-
+  const int nsteps = (kend - kbeg + BK - 1) / BK;
   load(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      sAr[akk[r]][amm[r]] = (T)av[r].re;
-      sAi[akk[r]][amm[r]] = (T)av[r].im;
-      sBr[bkk[r]][bnn[r]] = (T)bv[r].re;
-      sBi[bkk[r]][bnn[r]] = (T)bv[r].im;
-    }
-    __syncthreads();
-    if (k0 + BK < kend) load(k0 + BK);  // next tile in flight during the MFMAs below
+  stash(0);
+  __syncthreads();
+  // The last step also loads and stores a (fully masked) next tile: the loop
+  // body then has no branch, and the buffer it overwrites is no longer read.
+  for (int it = 0; it < nsteps; ++it) {
+    const int cur = it & 1;
+    load(kbeg + (it + 1) * BK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
-      T ar[2], ai[2], nai[2], br[2], bi[2];
+      T ar[IB], ai[IB], nai[IB], br[JB], bi[JB];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = sAr[kr][wm + 16 * i + c16];
-        ai[i] = sAi[kr][wm + 16 * i + c16];
+      for (int i = 0; i < IB; ++i) {
+        ar[i] = sA[cur][0][kr][wm + 16 * i + c16];
+        ai[i] = sA[cur][1][kr][wm + 16 * i + c16];
         nai[i] = -ai[i];
-        br[i] = sBr[kr][wn + 16 * i + c16];
-        bi[i] = sBi[kr][wn + 16 * i + c16];
+      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        br[j] = sB[cur][0][kr][wn + 16 * j + c16];
+        bi[j] = sB[cur][1][kr][wn + 16 * j + c16];
       }
       // four independent MFMAs between two that update the same accumulator
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
+        for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
+        for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
+        for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
+        for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
     }
+    stash(cur ^ 1);
+    __syncthreads();
   }
 
   const double alr = d.alpha.re, ali = d.alpha.im;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = tm * BM + wm + 16 * i + Frag<T>::row(lane, r);
@@ -247,17 +315,91 @@ inline unsigned grid_for(int64_t n, int bs) {
   return (unsigned)g;
 }
 
+template <typename T, bool ATOMIC, int BN>
+void launch_zgemm_l(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb) {
+  if (kfa && nfb)
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else if (kfa)
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else if (nfb)
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, true, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, false, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+}
+
+template <typename T, bool ATOMIC>
+void launch_zgemm_t(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb,
+                    int bn) {
+  if (bn == 16)
+    launch_zgemm_l<T, ATOMIC, 16>(d, grid, s, ksplit, kchunk, kfa, nfb);
+  else
+    launch_zgemm_l<T, ATOMIC, 64>(d, grid, s, ksplit, kchunk, kfa, nfb);
+}
+
+void launch_zgemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool f32, bool atomic,
+                  bool kfa, bool nfb, int bn) {
+  if (f32) {
+    if (atomic)
+      launch_zgemm_t<float, true>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
+    else
+      launch_zgemm_t<float, false>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
+  } else {
+    if (atomic)
+      launch_zgemm_t<double, true>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
+    else
+      launch_zgemm_t<double, false>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
+  }
+}
+
+// The same product with the roles of A and B exchanged: C^T = B^T A^T.
+GemmDesc transposed(const GemmDesc& d) {
+  GemmDesc t = d;
+  t.M = d.N;
+  t.N = d.M;
+  t.M0 = d.N0;
+  t.N0 = d.M0;
+  t.A = d.B;
+  t.sAm1 = d.sBn1;
+  t.sAm0 = d.sBn0;
+  t.sAk1 = d.sBk1;
+  t.sAk0 = d.sBk0;
+  t.sAb = d.sBb;
+  t.B = d.A;
+  t.sBk1 = d.sAk1;
+  t.sBk0 = d.sAk0;
+  t.sBn1 = d.sAm1;
+  t.sBn0 = d.sAm0;
+  t.sBb = d.sAb;
+  t.sCm1 = d.sCn1;
+  t.sCm0 = d.sCn0;
+  t.sCn1 = d.sCm1;
+  t.sCn0 = d.sCm0;
+  std::copy(d.cB, d.cB + 4, t.cA);
+  std::copy(d.cA, d.cA + 4, t.cB);
+  t.A2 = d.B2;
+  t.B2 = d.A2;
+  std::copy(d.cB2, d.cB2 + 4, t.cA2);
+  std::copy(d.cA2, d.cA2 + 4, t.cB2);
+  return t;
+}
+
 }  // namespace
 
-void gemm(const GemmDesc& d, hipStream_t s) {
-  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
-  if (d.K <= 0) return;
-  RTCC3_CHECK(d.M0 >= 1 && d.N0 >= 1 && d.K0 >= 1, "gemm: inner extents must be >= 1");
-  const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+void gemm(const GemmDesc& d0, hipStream_t s) {
+  if (d0.M <= 0 || d0.N <= 0 || d0.batch <= 0) return;
+  if (d0.K <= 0) return;
+  RTCC3_CHECK(d0.M0 >= 1 && d0.N0 >= 1 && d0.K0 >= 1, "gemm: inner extents must be >= 1");
+  RTCC3_CHECK(!d0.kseg || (d0.K == 2 * d0.kseg && d0.A2 && d0.B2 && d0.K0 == d0.kseg), "gemm: bad K segments");
+  RTCC3_CHECK(d0.K < (1 << 22), "gemm: K too long");
+  RTCC3_CHECK(!d0.store || !d0.atomic, "gemm: store mode cannot be atomic");
+  // A narrow side (at most 16, e.g. one occupied index) goes on N with 64x16
+  // tiles; a narrow M is moved there by transposing the product.
+  const bool tr = d0.M <= 16 && d0.N > 16;
+  const GemmDesc d = tr ? transposed(d0) : d0;
+  const int bn = d.N <= 16 ? 16 : 64;
+  const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + bn - 1) / bn);
   // Split K across workgroups when the grid is too small to fill the chip and
   // K is long; the partial products are then added with atomics.
-  RTCC3_CHECK(!d.kseg || (d.K == 2 * d.kseg && d.A2 && d.B2), "gemm: bad K segments");
-  RTCC3_CHECK(!d.store || !d.atomic, "gemm: store mode cannot be atomic");
   int ksplit = 1;
   const int64_t wgs = tiles * d.batch;
   if (!d.store && wgs < 512 && d.K >= 8 * BK) {
@@ -274,17 +416,8 @@ void gemm(const GemmDesc& d, hipStream_t s) {
   }
   dim3 grid((unsigned)(tiles * ksplit), (unsigned)by, (unsigned)bz);
   const bool atomic = d.atomic || ksplit > 1;
-  if (d.prec == 0) {
-    if (atomic)
-      hipLaunchKernelGGL((zgemm_kernel<double, true>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-    else
-      hipLaunchKernelGGL((zgemm_kernel<double, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-  } else {
-    if (atomic)
-      hipLaunchKernelGGL((zgemm_kernel<float, true>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-    else
-      hipLaunchKernelGGL((zgemm_kernel<float, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-  }
+  const bool kfa = d.sAk0 == 1, nfb = d.sBn0 == 1;
+  launch_zgemm(d, grid, s, ksplit, kchunk, d.prec != 0, atomic, kfa, nfb, bn);
   RTCC3_HIP(hipGetLastError());
 }
 

@@ -53,7 +53,12 @@ def _close(name, a, b, tol=TOL):
     assert err <= tol * scale, f"{name}: max|diff| = {err:.3e} (scale {scale:.3e})"
 
 
-@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (64, 64, 16), (100, 70, 129), (3, 200, 40)])
+@pytest.mark.parametrize(
+    "M,N,K",
+    [(1, 1, 1), (17, 33, 5), (64, 64, 16), (100, 70, 129), (3, 200, 40),
+     # narrow N (64x16 tiles), narrow M (transposed onto N), long K (split K)
+     (70, 15, 300), (15, 70, 300), (16, 17, 64), (130, 3, 1000)],
+)
 @pytest.mark.parametrize("prec", [0, 1])
 def test_zgemm_selftest(M, N, K, prec):
     _say(f"zgemm {M}x{N}x{K} prec={prec}")

@@ -57,13 +57,22 @@ struct GemmDesc {
   cplx alpha;
   int atomic;
   int prec;
-  // Optional second K segment with the same strides: when kseg > 0 the
-  // contraction length is K = 2*kseg and k >= kseg reads A2/B2 at k - kseg
-  // (block-table offsets cA2/cB2).
-  int kseg;
-  const cplx* A2;
-  const cplx* B2;
-  int64_t cA2[4], cB2[4];
+  // K segments (nseg > 0, block table required): the contraction runs over
+  // consecutive segments, segment s covering k in [seg[s].k0, seg[s+1].k0)
+  // (the last one up to K) with its own operands
+  //   A_s[m][r] = seg[s].A[cA.(I,J,K,n) + m*sAm + r*sAk],
+  //   B_s[r][n] = seg[s].B[cB.(I,J,K,n) + r*sBk + n*sBn],   r = k - seg[s].k0,
+  // so one product sums terms whose operands live in different tensors.
+  // The plain A/B fields and M0/N0/K0 splits are then unused (M0 = M, N0 = N).
+  struct Seg {
+    int k0;
+    const cplx* A;
+    int64_t cA[4], sAm, sAk;
+    const cplx* B;
+    int64_t cB[4], sBk, sBn;
+  };
+  int nseg;
+  Seg seg[4];
   // store = 1: C = alpha*AB without reading C (no split-K, not atomic).
   int store;
 };

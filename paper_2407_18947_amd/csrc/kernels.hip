@@ -63,7 +63,9 @@ __device__ __forceinline__ void split_k(int k, int K0, float inv, int& q, int& r
 // the operand reads the entry's first element and is replaced by zero.
 // KFA: A is read with k as the fast thread index (unit stride in k), else m;
 // NFB: B is read with n as the fast thread index, else k.
-template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN>
+// SEG: the operands come from the K segments of the descriptor (A read with
+// k fast, B with n fast).
+template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG>
 __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
   typedef typename Frag<T>::acc acc_t;
   constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
@@ -81,32 +83,29 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   const int kbeg = kz * kchunk;
   const int kend = min(d.K, kbeg + kchunk);
   if (kbeg >= kend) return;
-  const cplx* A;
-  const cplx* B;
-  const cplx* A2 = nullptr;
-  const cplx* B2 = nullptr;
+  const cplx* A = nullptr;
+  const cplx* B = nullptr;
   cplx* C;
+  const cplx* Ap[4] = {nullptr, nullptr, nullptr, nullptr};  // K-segment bases of this entry
+  const cplx* Bp[4] = {nullptr, nullptr, nullptr, nullptr};
   if (d.bl) {
     const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
-    A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
-    B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
     C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
-    if (d.kseg) {
-      A2 = d.A2 + d.cA2[0] * I + d.cA2[1] * J + d.cA2[2] * K + d.cA2[3] * n;
-      B2 = d.B2 + d.cB2[0] * I + d.cB2[1] * J + d.cB2[2] * K + d.cB2[3] * n;
+    if (SEG) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const GemmDesc::Seg& g = d.seg[s < d.nseg ? s : 0];
+        Ap[s] = g.A + g.cA[0] * I + g.cA[1] * J + g.cA[2] * K + g.cA[3] * n;
+        Bp[s] = g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n;
+      }
+    } else {
+      A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
+      B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
     }
   } else {
     A = d.A + b * d.sAb;
     B = d.B + b * d.sBb;
     C = d.C + b * d.sCb;
-    if (d.kseg) {
-      A2 = d.A2 + b * d.sAb;
-      B2 = d.B2 + b * d.sBb;
-    }
-  }
-  if (!d.kseg) {
-    A2 = A;
-    B2 = B;
   }
 
   const int tid = threadIdx.x;
@@ -145,10 +144,6 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     bval[r] = n < d.N;
     boff[r] = bval[r] ? (int64_t)(n / d.N0) * d.sBn1 + (int64_t)(n % d.N0) * d.sBn0 : 0;
   }
-  // K segments: k >= kseg reads A2/B2 at k - kseg (without segments kseg is
-  // out of reach and A2 = A, B2 = B).
-  const int kseg = d.kseg ? d.kseg : 0x7fffffff;
-
   // Every load is issued: an element outside the operand reads offset 0 of
   // its entry (the empty asm keeps the compiler from turning the address
   // select back into a branch around the load) and is then replaced by zero.
@@ -159,33 +154,58 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     const cplx x = p[o];
     return cplx{ok ? x.re : 0.0, ok ? x.im : 0.0};
   };
+  // Segment of k (SEG): unused segments start at INT_MAX.
+  const int sk1 = d.nseg > 1 ? d.seg[1].k0 : 0x7fffffff;
+  const int sk2 = d.nseg > 2 ? d.seg[2].k0 : 0x7fffffff;
+  const int sk3 = d.nseg > 3 ? d.seg[3].k0 : 0x7fffffff;
+  auto segof = [&](int k) { return (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3); };
+  auto pick = [](int s, auto x0, auto x1, auto x2, auto x3) { return s == 0 ? x0 : s == 1 ? x1 : s == 2 ? x2 : x3; };
   auto load = [&](int k0) {
+    if (SEG) {
+      // A: one k per thread (k fast), four rows; B: one column, four k
+      const int k = k0 + akk[0];
+      const int s = segof(k);
+      const int r = k - pick(s, 0, sk1, sk2, sk3);
+      const cplx* p = pick(s, Ap[0], Ap[1], Ap[2], Ap[3]);
+      const int64_t sm = pick(s, d.seg[0].sAm, d.seg[1].sAm, d.seg[2].sAm, d.seg[3].sAm);
+      const int64_t kof = (int64_t)r * pick(s, d.seg[0].sAk, d.seg[1].sAk, d.seg[2].sAk, d.seg[3].sAk);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[t] = fetch(p, k < kend && aval[t], (int64_t)(tm * BM + amm[t]) * sm + kof);
+      const int64_t ncol = tn * BN + bnn[0];
+#pragma unroll
+      for (int t = 0; t < NEB; ++t) {
+        const int kb = k0 + bkk[t];
+        const int sb = segof(kb);
+        const int rb = kb - pick(sb, 0, sk1, sk2, sk3);
+        const cplx* pb = pick(sb, Bp[0], Bp[1], Bp[2], Bp[3]);
+        const int64_t off = (int64_t)rb * pick(sb, d.seg[0].sBk, d.seg[1].sBk, d.seg[2].sBk, d.seg[3].sBk) +
+                            ncol * pick(sb, d.seg[0].sBn, d.seg[1].sBn, d.seg[2].sBn, d.seg[3].sBn);
+        bv[t] = fetch(pb, kb < kend && bval[0], off);
+      }
+      return;
+    }
 #pragma unroll
     for (int s = 0; s < NKA; ++s) {
       const int k = k0 + akk[s];
-      const bool kin = k < kend, hi = k >= kseg;
       int q, r;
-      split_k(hi ? k - kseg : k, d.K0, invK0, q, r);
+      split_k(k, d.K0, invK0, q, r);
       const int64_t ko = (int64_t)q * d.sAk1 + (int64_t)r * d.sAk0;
-      const cplx* p = hi ? A2 : A;
 #pragma unroll
       for (int t = 0; t < NMA; ++t) {
         const int e = KFA ? t : s;
-        av[e] = fetch(p, kin && aval[KFA ? t : 0], aoff[KFA ? t : 0] + ko);
+        av[e] = fetch(A, k < kend && aval[KFA ? t : 0], aoff[KFA ? t : 0] + ko);
       }
     }
 #pragma unroll
     for (int s = 0; s < NKB; ++s) {
       const int k = k0 + bkk[s];
-      const bool kin = k < kend, hi = k >= kseg;
       int q, r;
-      split_k(hi ? k - kseg : k, d.K0, invK0, q, r);
+      split_k(k, d.K0, invK0, q, r);
       const int64_t ko = (int64_t)q * d.sBk1 + (int64_t)r * d.sBk0;
-      const cplx* p = hi ? B2 : B;
 #pragma unroll
       for (int t = 0; t < NNB; ++t) {
         const int e = NFB ? s : t;
-        bv[e] = fetch(p, kin && bval[NFB ? 0 : t], boff[NFB ? 0 : t] + ko);
+        bv[e] = fetch(B, k < kend && bval[NFB ? 0 : t], boff[NFB ? 0 : t] + ko);
       }
     }
   };
@@ -318,19 +338,21 @@ inline unsigned grid_for(int64_t n, int bs) {
 template <typename T, bool ATOMIC, int BN>
 void launch_zgemm_l(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb) {
   if (kfa && nfb)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   else if (kfa)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   else if (nfb)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, true, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, true, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   else
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, false, BN>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, false, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
 }
 
 template <typename T, bool ATOMIC>
 void launch_zgemm_t(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb,
                     int bn) {
-  if (bn == 16)
+  if (d.nseg > 0)
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, 64, true>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else if (bn == 16)
     launch_zgemm_l<T, ATOMIC, 16>(d, grid, s, ksplit, kchunk, kfa, nfb);
   else
     launch_zgemm_l<T, ATOMIC, 64>(d, grid, s, ksplit, kchunk, kfa, nfb);
@@ -376,10 +398,6 @@ GemmDesc transposed(const GemmDesc& d) {
   t.sCn0 = d.sCm0;
   std::copy(d.cB, d.cB + 4, t.cA);
   std::copy(d.cA, d.cA + 4, t.cB);
-  t.A2 = d.B2;
-  t.B2 = d.A2;
-  std::copy(d.cB2, d.cB2 + 4, t.cA2);
-  std::copy(d.cA2, d.cA2 + 4, t.cB2);
   return t;
 }
 
@@ -389,14 +407,21 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   if (d0.M <= 0 || d0.N <= 0 || d0.batch <= 0) return;
   if (d0.K <= 0) return;
   RTCC3_CHECK(d0.M0 >= 1 && d0.N0 >= 1 && d0.K0 >= 1, "gemm: inner extents must be >= 1");
-  RTCC3_CHECK(!d0.kseg || (d0.K == 2 * d0.kseg && d0.A2 && d0.B2 && d0.K0 == d0.kseg), "gemm: bad K segments");
+  if (d0.nseg > 0) {
+    RTCC3_CHECK(d0.nseg <= 4 && d0.bl && d0.seg[0].k0 == 0 && d0.M0 == d0.M && d0.N0 == d0.N,
+                "gemm: bad K segments");
+    for (int s = 0; s < d0.nseg; ++s) {
+      const int end = s + 1 < d0.nseg ? d0.seg[s + 1].k0 : d0.K;
+      RTCC3_CHECK(d0.seg[s].A && d0.seg[s].B && end > d0.seg[s].k0, "gemm: bad K segments");
+    }
+  }
   RTCC3_CHECK(d0.K < (1 << 22), "gemm: K too long");
   RTCC3_CHECK(!d0.store || !d0.atomic, "gemm: store mode cannot be atomic");
   // A narrow side (at most 16, e.g. one occupied index) goes on N with 64x16
   // tiles; a narrow M is moved there by transposing the product.
-  const bool tr = d0.M <= 16 && d0.N > 16;
+  const bool tr = d0.M <= 16 && d0.N > 16 && d0.nseg == 0;
   const GemmDesc d = tr ? transposed(d0) : d0;
-  const int bn = d.N <= 16 ? 16 : 64;
+  const int bn = d.N <= 16 && d.nseg == 0 ? 16 : 64;  // the segmented kernel has 64-wide tiles
   const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + bn - 1) / bn);
   // Split K across workgroups when the grid is too small to fill the chip and
   // K is long; the partial products are then added with atomics.

@@ -55,12 +55,10 @@ int64_t span(int64_t X, int64_t X0, int64_t s1, int64_t s0) {
 
 // Launch a GEMM after checking, on the host, that every batch entry stays
 // inside the operand buffers (lengths in elements).
-void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s,
-                  int64_t lenA2 = 0, int64_t lenB2 = 0) {
+void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
   if (g.batch <= 0) return;
-  const int kl = g.kseg ? g.kseg : g.K;  // contraction length per segment
-  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + span(kl, g.K0, g.sAk1, g.sAk0);
-  const int64_t eB = span(kl, g.K0, g.sBk1, g.sBk0) + span(g.N, g.N0, g.sBn1, g.sBn0);
+  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + span(g.K, g.K0, g.sAk1, g.sAk0);
+  const int64_t eB = span(g.K, g.K0, g.sBk1, g.sBk0) + span(g.N, g.N0, g.sBn1, g.sBn0);
   const int64_t eC = span(g.M, g.M0, g.sCm1, g.sCm0) + span(g.N, g.N0, g.sCn1, g.sCn0);
   for (int b = 0; b < g.batch; ++b) {
     int64_t oA, oB, oC;
@@ -77,13 +75,31 @@ void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t l
     RTCC3_CHECK(oA >= 0 && oA + eA < lenA, "triples: A operand out of bounds");
     RTCC3_CHECK(oB >= 0 && oB + eB < lenB, "triples: B operand out of bounds");
     RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
-    if (g.kseg) {
-      RTCC3_CHECK(g.bl, "triples: K segments need a block table");
-      const int* q = bl_host + 4 * b;
-      const int64_t oA2 = g.cA2[0] * q[0] + g.cA2[1] * q[1] + g.cA2[2] * q[2] + g.cA2[3] * q[3];
-      const int64_t oB2 = g.cB2[0] * q[0] + g.cB2[1] * q[1] + g.cB2[2] * q[2] + g.cB2[3] * q[3];
-      RTCC3_CHECK(oA2 >= 0 && oA2 + eA < lenA2, "triples: A2 operand out of bounds");
-      RTCC3_CHECK(oB2 >= 0 && oB2 + eB < lenB2, "triples: B2 operand out of bounds");
+  }
+  gemm(g, s);
+}
+
+// A K-segmented product (GemmDesc::seg) after the same check per segment;
+// lenA[s], lenB[s]: lengths of segment s's operand tensors.
+void checked_seg_gemm(const GemmDesc& g, const int* bl_host, const int64_t* lenA, const int64_t* lenB, int64_t lenC,
+                      hipStream_t s) {
+  if (g.batch <= 0) return;
+  RTCC3_CHECK(g.bl && g.nseg >= 1 && g.nseg <= 4, "triples: segmented product needs a block table");
+  const int64_t eC = span(g.M, g.M0, g.sCm1, g.sCm0) + span(g.N, g.N0, g.sCn1, g.sCn0);
+  for (int b = 0; b < g.batch; ++b) {
+    const int* q = bl_host + 4 * b;
+    const int64_t oC = g.cC[0] * q[0] + g.cC[1] * q[1] + g.cC[2] * q[2] + g.cC[3] * q[3];
+    RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
+    for (int t = 0; t < g.nseg; ++t) {
+      const GemmDesc::Seg& sg = g.seg[t];
+      const int len = (t + 1 < g.nseg ? g.seg[t + 1].k0 : g.K) - sg.k0;
+      RTCC3_CHECK(len >= 1 && sg.sAm >= 0 && sg.sAk >= 0 && sg.sBk >= 0 && sg.sBn >= 0, "triples: bad segment");
+      const int64_t oA = sg.cA[0] * q[0] + sg.cA[1] * q[1] + sg.cA[2] * q[2] + sg.cA[3] * q[3];
+      const int64_t oB = sg.cB[0] * q[0] + sg.cB[1] * q[1] + sg.cB[2] * q[2] + sg.cB[3] * q[3];
+      const int64_t eA = (int64_t)(g.M - 1) * sg.sAm + (int64_t)(len - 1) * sg.sAk;
+      const int64_t eB = (int64_t)(len - 1) * sg.sBk + (int64_t)(g.N - 1) * sg.sBn;
+      RTCC3_CHECK(oA >= 0 && oA + eA < lenA[t], "triples: A segment out of bounds");
+      RTCC3_CHECK(oB >= 0 && oB + eB < lenB[t], "triples: B segment out of bounds");
     }
   }
   gemm(g, s);
@@ -263,15 +279,15 @@ void Triples::blocks(Engine& e, const CCSDResult& r) {
     return t;
   };
   View t;
-  t = make("tb_W1", {o, v, v, v});  // (ck|be) at [k][b][c][e]
-  e.einsum("Pck,Pbe->kbce", ONE, B('v', 'o'), B('v', 'v'), t);
-  t = make("tb_W2", {o, o, o, v});  // (mj|ck) at [j][k][m][c]
-  e.einsum("Pmj,Pck->jkmc", ONE, B('o', 'o'), B('v', 'o'), t);
-  t = make("tb_LA", {o, v, v, v});  // -(ka|db) at [k][a][b][d]
-  e.einsum("Pka,Pdb->kabd", R(-1), B('o', 'v'), B('v', 'v'), t);
-  t = make("tb_LB", {o, v, v, v});  // 2(da|jb) - (db|ja) at [j][a][b][d]
-  e.einsum("Pda,Pjb->jabd", R(2), B('v', 'v'), B('o', 'v'), t);
-  e.einsum("Pdb,Pja->jabd", R(-1), B('v', 'v'), B('o', 'v'), t);
+  t = make("tb_W1", {o, v, v, v});  // (ck|be) at [k][e][b][c]
+  e.einsum("Pck,Pbe->kebc", ONE, B('v', 'o'), B('v', 'v'), t);
+  t = make("tb_W2", {o, o, v, o});  // -(mk|ai) at [k][i][a][m]
+  e.einsum("Pmk,Pai->kiam", R(-1), B('o', 'o'), B('v', 'o'), t);
+  t = make("tb_LA", {o, v, v, v});  // -(ib|dc) at [i][d][b][c]
+  e.einsum("Pib,Pdc->idbc", R(-1), B('o', 'v'), B('v', 'v'), t);
+  t = make("tb_LB", {o, v, v, v});  // 2(db|kc) - (dc|kb) at [k][d][b][c]
+  e.einsum("Pdb,Pkc->kdbc", R(2), B('v', 'v'), B('o', 'v'), t);
+  e.einsum("Pdc,Pkb->kdbc", R(-1), B('v', 'v'), B('o', 'v'), t);
   t = make("tb_LC", {o, v, o, o});  // (ka|jl) at [k][a][j][l]
   e.einsum("Pka,Pjl->kajl", ONE, B('o', 'v'), B('o', 'o'), t);
   t = make("tb_LD", {o, v, o, o});  // -(2(ia|jl) - (il|ja)) at [i][a][j][l]
@@ -315,7 +331,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
   auto P = [&](const char* name, std::vector<int64_t> shape) { return e.tensor(name, shape).p; };
   const cplx* gW1 = P("tb_W1", {o, v, v, v});
-  const cplx* gW2 = P("tb_W2", {o, o, o, v});
+  const cplx* gW2 = P("tb_W2", {o, o, v, o});
   const cplx* gLA = P("tb_LA", {o, v, v, v});
   const cplx* gLB = P("tb_LB", {o, v, v, v});
   const cplx* gLC = P("tb_LC", {o, v, o, o});
@@ -335,95 +351,68 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int* blh = w.bl.data();
   const int pr = prec_;
 
+  // Both builds produce W[n][a][(b,c)] in one store-mode product.  A term X
+  // whose natural layout is [(a,b)][c] is taken at the cyclically relabelled
+  // block instead, Y_ijk^abc = X_jki^bca, which has the layout [a][(b,c)]:
+  // P_ijk^abc sums over all simultaneous permutations of (ijk) and (abc), so
+  // P Y = P X.
+  const int64_t lT2 = t2len, lOVVV_ = lOVVV;
+  auto seg = [](GemmDesc::Seg& sg, int k0, const cplx* A, std::initializer_list<int64_t> cA, int64_t sAm,
+                int64_t sAk, const cplx* B, std::initializer_list<int64_t> cB, int64_t sBk) {
+    sg.k0 = k0;
+    sg.A = A;
+    std::copy(cA.begin(), cA.end(), sg.cA);
+    sg.sAm = sAm;
+    sg.sAk = sAk;
+    sg.B = B;
+    std::copy(cB.begin(), cB.end(), sg.cB);
+    sg.sBk = sBk;
+    sg.sBn = 1;
+  };
+
   // ---------------- t3 blocks
-  {  // W[n][(a,b)][c] = -sum_m t2[I][m][(a,b)] (mj|ck)~[J][K][m][c]   (store: initialises W)
-    GemmDesc g = base((int)v2, v, o, nw, bl, pr);
+  {  // W[n][a][(b,c)] = sum_e t2[I][J][a][e] (ck|be)~[K][e][(b,c)]
+     //              + sum_m -(mk|ai)~[K][I][a][m] t2[J][m][(b,c)]   (term 2 relabelled)
+    GemmDesc g = base(v, (int)v2, v + o, nw, bl, pr);
     g.store = 1;
-    g.alpha = R(-1);
-    g.A = t2;
-    g.sAm0 = 1;
-    g.sAk0 = v2;
-    set4(g.cA, (int64_t)o * v2, 0, 0, 0);
-    g.B = gW2;
-    g.sBk0 = v;
-    g.sBn0 = 1;
-    set4(g.cB, 0, (int64_t)o * o * v, (int64_t)o * v, 0);
-    g.C = W;
-    g.sCm0 = v;
-    g.sCn0 = 1;
-    set4(g.cC, 0, 0, 0, v3);
-    checked_gemm(g, blh, t2len, lOOOV, winlen, s);
-  }
-  {  // W[n][a][(b,c)] += sum_e t2[I][J][a][e] (ck|be)~[K][(b,c)][e]
-    GemmDesc g = base(v, (int)v2, v, nw, bl, pr);
-    g.A = t2;
-    g.sAm0 = v;
-    g.sAk0 = 1;
-    set4(g.cA, (int64_t)o * v2, v2, 0, 0);
-    g.B = gW1;
-    g.sBk0 = 1;
-    g.sBn0 = v;
-    set4(g.cB, 0, 0, v3, 0);
+    g.nseg = 2;
+    seg(g.seg[0], 0, t2, {(int64_t)o * v2, v2, 0, 0}, v, 1, gW1, {0, 0, v3, 0}, v2);
+    seg(g.seg[1], v, gW2, {(int64_t)v * o, 0, (int64_t)o * v * o, 0}, o, 1, t2, {0, (int64_t)o * v2, 0, 0}, v2);
     g.C = W;
     g.sCm0 = v2;
     g.sCn0 = 1;
     set4(g.cC, 0, 0, 0, v3);
-    checked_gemm(g, blh, t2len, lOVVV, winlen, s);
+    const int64_t lA[2] = {lT2, lOOOV}, lB[2] = {lOVVV_, lT2};
+    checked_seg_gemm(g, blh, lA, lB, winlen, s);
   }
   launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
 
   // ---------------- lambda3 blocks
-  {  // W[n][a][(b,c)] = sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)] - sum_l Lt_ijal[I][a][J][l] l2[l][K][(b,c)]
-    GemmDesc g = base(v, (int)v2, 2 * o, nw, bl, pr);
+  {  // W[n][a][(b,c)] = sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)]
+     //              - sum_l Lt_ijal[I][a][J][l] l2[l][K][(b,c)]
+     //              + sum_d l2[J][K][a][d] -(ib|dc)~[I][d][(b,c)]                (relabelled)
+     //              + sum_d l2[I][J][a][d] (2(db|kc) - (dc|kb))~[K][d][(b,c)]    (relabelled)
+    GemmDesc g = base(v, (int)v2, 2 * o + 2 * v, nw, bl, pr);
     g.store = 1;
-    g.kseg = o;
-    g.K0 = o;
-    g.A = gLC;
-    g.sAm0 = (int64_t)o * o;
-    g.sAk0 = 1;
-    set4(g.cA, 0, o, (int64_t)v * o * o, 0);
-    g.A2 = gLD;
-    set4(g.cA2, (int64_t)v * o * o, o, 0, 0);
-    g.B = l2;
-    g.sBk0 = (int64_t)o * v2;
-    g.sBn0 = 1;
-    set4(g.cB, v2, 0, 0, 0);
-    g.B2 = l2;
-    set4(g.cB2, 0, 0, v2, 0);
+    g.nseg = 4;
+    const int64_t oo = (int64_t)o * o, ov2 = (int64_t)o * v2;
+    seg(g.seg[0], 0, gLC, {0, o, (int64_t)v * oo, 0}, oo, 1, l2, {v2, 0, 0, 0}, ov2);
+    seg(g.seg[1], o, gLD, {(int64_t)v * oo, o, 0, 0}, oo, 1, l2, {0, 0, v2, 0}, ov2);
+    seg(g.seg[2], 2 * o, l2, {0, ov2, v2, 0}, v, 1, gLA, {v3, 0, 0, 0}, v2);
+    seg(g.seg[3], 2 * o + v, l2, {ov2, v2, 0, 0}, v, 1, gLB, {0, 0, v3, 0}, v2);
     g.C = W;
     g.sCm0 = v2;
     g.sCn0 = 1;
     set4(g.cC, 0, 0, 0, v3);
     const int64_t lLC = (int64_t)o * v * o * o;
-    checked_gemm(g, blh, lLC, l2len, winlen, s, lLC, l2len);
-  }
-  {  // W[n][(a,b)][c] += sum_d -(ka|db)~[K][(a,b)][d] l2[I][J][c][d] + sum_d Lt_djab[J][(a,b)][d] l2[K][I][c][d]
-    GemmDesc g = base((int)v2, v, 2 * v, nw, bl, pr);
-    g.kseg = v;
-    g.K0 = v;
-    g.A = gLA;
-    g.sAm0 = v;
-    g.sAk0 = 1;
-    set4(g.cA, 0, 0, v3, 0);
-    g.A2 = gLB;
-    set4(g.cA2, 0, v3, 0, 0);
-    g.B = l2;
-    g.sBk0 = 1;
-    g.sBn0 = v;
-    set4(g.cB, (int64_t)o * v2, v2, 0, 0);
-    g.B2 = l2;
-    set4(g.cB2, v2, 0, (int64_t)o * v2, 0);
-    g.C = W;
-    g.sCm0 = v;
-    g.sCn0 = 1;
-    set4(g.cC, 0, 0, 0, v3);
-    checked_gemm(g, blh, lOVVV, l2len, winlen, s, lOVVV, l2len);
+    const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
+    checked_seg_gemm(g, blh, lA, lB, winlen, s);
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
     launch_sym_cube(W, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, &le, s);
   }
-  launches_ += 5;
+  launches_ += 4;
 
   if (rhs_terms) {
     // Contractions run over the blocks this window is responsible for: all of

@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RK4 steps/sec (T+Λ RT-CC3) at o=15,v=57; FP32-split vs FP64 at dipole err"
 PAPER_GPU_DP_TRIMER_STEPS_PER_S = 1.0 / 806.52  # Table 1, GPU-dp, water trimer (P100)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
+PRECISIONS = ("fp64", "fp32", "bf16x3", "bf16x2")
+# real bf16 products per complex multiply-add: 4 real products times the kept slice pairs
+SLICE_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
 
 
 def triples_flops_per_step(o: int, v: int) -> float:
@@ -81,7 +84,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=PRECISIONS, default="fp64")
+    ap.add_argument("--split", choices=PRECISIONS, default="bf16x3",
+                    help="reduced-precision triples path timed beside the main run (dipole error against it)")
+    ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--o", type=int, default=15)
     ap.add_argument("--v", type=int, default=57)
     ap.add_argument("--seed", type=int, default=3)
@@ -102,27 +108,33 @@ def main():
     dt, amp = 0.05, 0.002
     s = make_system(o, v, seed=args.seed)
     y0 = initial_state(s)
-    prec = _lib.RTCC3_FP64 if args.precision == "fp64" else _lib.RTCC3_FP32
+    codes = {"fp64": _lib.RTCC3_FP64, "fp32": _lib.RTCC3_FP32, "bf16x3": _lib.RTCC3_BF16X3,
+             "bf16x2": _lib.RTCC3_BF16X2}
     K, W = args.steps, args.warmup
     field = field_delta_kick(W + K, dt, amp, "z")
     torch.cuda.set_device(0)
-    ctx = _lib.Context(s, prec)
-    ctx.set_state(y0)
-    if W > 0:
-        ctx.propagate(W, dt, field[: 2 * W + 1])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.propagate(K, dt, field[2 * W: 2 * (W + K) + 1])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timing = _lib.rtcc3_last_timing(ctx.ctx)  # HIP events on the context's stream
-    ctx.close()
-    secs = t1 - t0
+
+    def run(precision):
+        """W warm-up steps, then K timed steps; returns (s, dipole series, timing)."""
+        ctx = _lib.Context(s, codes[precision])
+        ctx.set_state(y0)
+        mu_w = ctx.propagate(W, dt, field[: 2 * W + 1]) if W > 0 else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu = ctx.propagate(K, dt, field[2 * W: 2 * (W + K) + 1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        timing = _lib.rtcc3_last_timing(ctx.ctx)  # HIP events on the context's stream
+        ctx.close()
+        series = np.concatenate([np.asarray(mu_w), np.asarray(mu)]) if mu_w is not None else np.asarray(mu)
+        return t1 - t0, series, timing
+
+    secs, mu_main, timing = run(args.precision)
     steps_per_s = K / secs
     tri_ms_per_step = timing[1] / K
     alg = triples_flops_per_step(o, v)
     achieved = alg / (tri_ms_per_step * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    peak = PEAK_TFLOPS[args.precision] / SLICE_PRODUCTS[args.precision]
     out = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -134,7 +146,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": steps_per_s / PAPER_GPU_DP_TRIMER_STEPS_PER_S,
-        "dtype": "f64" if args.precision == "fp64" else "f32 triples GEMMs, f64 elsewhere",
+        "dtype": {"fp64": "f64", "fp32": "f32 triples GEMMs, f64 elsewhere",
+                  "bf16x3": "bf16x3-split triples GEMMs (f32 accumulate), f64 elsewhere",
+                  "bf16x2": "bf16x2-split triples GEMMs (f32 accumulate), f64 elsewhere"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"RT-CC3 T+Lambda, o={o}, v={v}, naux={s.naux}, seeded synthetic water-trimer-sized "
@@ -153,6 +167,19 @@ def main():
             "algorithmic_flop_per_step": alg,
         },
     }
+    if not args.no_split and args.split != args.precision:
+        secs_s, mu_s, timing_s = run(args.split)
+        tri_s = timing_s[1] / K
+        out["split"] = {
+            "precision": args.split,
+            "value": K / secs_s,
+            "unit": "RK4 steps/s",
+            "ms_per_step": 1e3 * secs_s / K,
+            "ratio_vs_main": (K / secs_s) / steps_per_s,
+            "max_dipole_err_vs_main": float(np.abs(mu_s - mu_main).max()),
+            "triples_ms_per_step": tri_s,
+            "triples_tflops_effective": alg / (tri_s * 1e-3) / 1e12,
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, y0, field[0], args.cpu_blocks)
     print(json.dumps(out), flush=True)

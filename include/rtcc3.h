@@ -52,9 +52,16 @@ enum {
   RTCC3_EDIVERGED = -5  /* the propagated state became non-finite */
 };
 
-/* Precision of the triples contractions.  Denominators, residual accumulation,
- * RK4 and the dipole always stay in FP64. */
-enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1 };
+/* Precision of the triples contractions (the paper's single- versus
+ * double-precision comparison, Section 3 and Table 1).  Denominators, residual
+ * accumulation, RK4 and the dipole always stay in FP64.
+ *   RTCC3_FP64    FP64 matrix cores
+ *   RTCC3_FP32    operands rounded to FP32, FP32 matrix cores and accumulation
+ *   RTCC3_BF16X3  each real operand split into three bf16 slices (about FP32's
+ *                 24 significand bits), six slice products on the bf16 matrix
+ *                 cores, FP32 accumulation
+ *   RTCC3_BF16X2  two bf16 slices (16 bits), three slice products */
+enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1, RTCC3_BF16X3 = 2, RTCC3_BF16X2 = 3 };
 
 /* Create a context.
  *   o, v     numbers of occupied / virtual orbitals (o >= 1, v >= 1)
@@ -62,7 +69,7 @@ enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1 };
  *   naux, B  [naux*n*n] host, density-fitting factors, (pq|rs) = sum_P B[P][p][q] B[P][r][s];
  *            each B[P] symmetric (<= 1e-12)
  *   dipole   [3*n*n] host, electric dipole matrices mu^x, mu^y, mu^z, symmetric
- *   precision RTCC3_FP64 or RTCC3_FP32
+ *   precision one of RTCC3_FP64, RTCC3_FP32, RTCC3_BF16X3, RTCC3_BF16X2
  *   hip_stream a hipStream_t to order work on, or NULL for a stream owned by the context
  *   out      receives the context
  * Returns EINVAL, ENOMEM or EDEVICE on failure (message via rtcc3_last_error(NULL)). */
@@ -109,7 +116,7 @@ int rtcc3_last_timing(rtcc3_ctx *ctx, double kernel_ms[3]);
 
 /* Library self-test of the complex GEMM the contractions run on:
  * C[m][n] = sum_k A[m][k] B[k][n] for host row-major complex arrays, computed
- * on the device with FP64 (precision 0) or FP32 (1) matrix-core arithmetic.
+ * on the device with the matrix-core arithmetic of the given precision.
  * Returns EINVAL for non-positive sizes or NULL pointers. */
 int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rtcc3_c64 *A, const rtcc3_c64 *B, rtcc3_c64 *C);
 

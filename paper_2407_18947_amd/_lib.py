@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "librtcc3.so")
 
 RTCC3_OK, RTCC3_EINVAL, RTCC3_ENOMEM, RTCC3_EDEVICE, RTCC3_ESTATE, RTCC3_EDIVERGED = 0, -1, -2, -3, -4, -5
-RTCC3_FP64, RTCC3_FP32 = 0, 1
+RTCC3_FP64, RTCC3_FP32, RTCC3_BF16X3, RTCC3_BF16X2 = 0, 1, 2, 3
 RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION = 1, 2
 
 EXPORTS = [

@@ -42,7 +42,10 @@ struct Error : std::runtime_error {
 // or, when a block table bl is given (4 ints per entry: I, J, K, n), at
 //   A + cA[0]*I + cA[1]*J + cA[2]*K + cA[3]*n   (same for B and C).
 // atomic: accumulate with atomics (several batch entries may share C).
-// prec 0: FP64 MFMA; 1: operands rounded to FP32, FP32 MFMA and accumulate.
+// prec: RTCC3_PREC_FP64: FP64 MFMA; RTCC3_PREC_FP32: operands rounded to FP32,
+// FP32 MFMA and accumulate; RTCC3_PREC_BF16X3 / BF16X2: operands split into
+// three / two bf16 slices, bf16 MFMA with FP32 accumulate.
+enum { RTCC3_PREC_FP64 = 0, RTCC3_PREC_FP32 = 1, RTCC3_PREC_BF16X3 = 2, RTCC3_PREC_BF16X2 = 3 };
 struct GemmDesc {
   int M, N, K, batch;
   int M0, N0, K0;

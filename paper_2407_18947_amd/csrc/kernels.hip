@@ -11,7 +11,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 64, BK = 16, NT = 256;
+constexpr int BM = 64, NT = 256;
 
 template <typename T>
 struct Frag;
@@ -48,121 +48,108 @@ __device__ __forceinline__ void split_k(int k, int K0, float inv, int& q, int& r
   r = r >= K0 ? r - K0 : r;
 }
 
-// One workgroup computes a 64 x BN tile of C for one batch entry.  BN = 64:
-// waves arranged 2x2, each owning a 32x32 sub-tile = 2x2 MFMA 16x16 blocks;
-// BN = 16 (narrow N, e.g. one occupied index): waves stacked 4x1, each owning
-// one 16x16 block.  Every block has a real and an imaginary accumulator:
-//   Cre += Are*Bre - Aim*Bim,  Cim += Are*Bim + Aim*Bre.
-// MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16].
-// Result layout: FP32 holds D[4*(l/16)+r][l%16] in register r, FP64 holds
-// D[4*r+l/16][l%16] (Frag<T>::row).
-//
-// Tiles of A and B go through two LDS buffers: while the MFMAs consume one,
-// the next tile is loaded into registers and then stored into the other, so
-// each K step needs one barrier.  Loads carry no branches: an element outside
-// the operand reads the entry's first element and is replaced by zero.
-// KFA: A is read with k as the fast thread index (unit stride in k), else m;
-// NFB: B is read with n as the fast thread index, else k.
-// SEG: the operands come from the K segments of the descriptor (A read with
-// k fast, B with n fast).
-template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG>
-__global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
-  typedef typename Frag<T>::acc acc_t;
-  constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
-  constexpr int IB = WM / 16, JB = WN / 16;                         // MFMA blocks per wave
-  constexpr int NEB = BN * BK / NT;                                 // B elements per thread
-  __shared__ T sA[2][2][BK][BM + 1];  // [buffer][re, im][k][m]
-  __shared__ T sB[2][2][BK][BN + 1];  // [buffer][re, im][k][n]
-
-  const int tilesN = (d.N + BN - 1) / BN;
-  const int kz = blockIdx.x % ksplit;
-  const int tile = blockIdx.x / ksplit;
-  const int tm = tile / tilesN, tn = tile % tilesN;
-  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
-  if (b >= d.batch) return;
-  const int kbeg = kz * kchunk;
-  const int kend = min(d.K, kbeg + kchunk);
-  if (kbeg >= kend) return;
-  const cplx* A = nullptr;
-  const cplx* B = nullptr;
-  cplx* C;
-  const cplx* Ap[4] = {nullptr, nullptr, nullptr, nullptr};  // K-segment bases of this entry
-  const cplx* Bp[4] = {nullptr, nullptr, nullptr, nullptr};
-  if (d.bl) {
-    const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
-    C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
-    if (SEG) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const GemmDesc::Seg& g = d.seg[s < d.nseg ? s : 0];
-        Ap[s] = g.A + g.cA[0] * I + g.cA[1] * J + g.cA[2] * K + g.cA[3] * n;
-        Bp[s] = g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n;
-      }
-    } else {
-      A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
-      B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
-    }
-  } else {
-    A = d.A + b * d.sAb;
-    B = d.B + b * d.sBb;
-    C = d.C + b * d.sCb;
-  }
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
-  const float invK0 = 1.0f / (float)d.K0;
-
-  // Loader geometry: element r of a thread sits at (akk[r], amm[r]) of the A
-  // tile; with KFA all four share one k (one k slot), else one m.
-  constexpr int NKA = KFA ? 1 : 4, NMA = KFA ? 4 : 1;
-  constexpr int NKB = NFB ? NEB : 1, NNB = NFB ? 1 : NEB;
-  int akk[4], amm[4], bkk[NEB], bnn[NEB];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int e = tid + NT * r;
-    amm[r] = KFA ? e / BK : e % BM;
-    akk[r] = KFA ? e % BK : e / BM;
-  }
-#pragma unroll
-  for (int r = 0; r < NEB; ++r) {
-    const int e = tid + NT * r;
-    bnn[r] = NFB ? e % BN : e / BK;
-    bkk[r] = NFB ? e / BN : e % BK;
-  }
+// Operands of one 64 x BN tile of C for one batch entry, brought into
+// registers BK values of k at a time.  Element r of a thread sits at
+// (akk[r], amm[r]) of the A tile and (bkk[r], bnn[r]) of the B tile.
+// KFA: A is read with k as the fast thread index (unit stride in k), so all
+// of a thread's A elements share one k; else they share one m.  NFB: B is read
+// with n as the fast thread index, else k.  SEG: the operands come from the K
+// segments of the descriptor (read with A k-fast, B n-fast).
+// Every load is issued: an element outside the operand reads offset 0 of its
+// entry (the empty asm keeps the compiler from turning the address select
+// back into a branch around the load) and is then replaced by zero.
+template <bool KFA, bool NFB, int BN, int BK, bool SEG>
+struct TileLoader {
+  static constexpr int NEA = BM * BK / NT, NEB = BN * BK / NT;
+  static constexpr int NKA = KFA ? 1 : NEA, NMA = KFA ? NEA : 1;
+  static constexpr int NKB = NFB ? NEB : 1, NNB = NFB ? 1 : NEB;
+  int akk[NEA], amm[NEA], bkk[NEB], bnn[NEB];
   int64_t aoff[NMA], boff[NNB];
   bool aval[NMA], bval[NNB];
+  const cplx* A;
+  const cplx* B;
+  const cplx* Ap[4];  // K-segment bases of this entry
+  const cplx* Bp[4];
+  int kend, sk1, sk2, sk3, m0, n0;
+  float invK0;
+  cplx av[NEA], bv[NEB];
+
+  // Returns the entry's C base.
+  __device__ __forceinline__ cplx* init(const GemmDesc& d, int64_t b, int tm, int tn, int kend_) {
+    kend = kend_;
+    m0 = tm * BM;
+    n0 = tn * BN;
+    invK0 = 1.0f / (float)d.K0;
+    cplx* C;
+    A = B = nullptr;
 #pragma unroll
-  for (int r = 0; r < NMA; ++r) {
-    const int m = tm * BM + amm[r];
-    aval[r] = m < d.M;
-    aoff[r] = aval[r] ? (int64_t)(m / d.M0) * d.sAm1 + (int64_t)(m % d.M0) * d.sAm0 : 0;
-  }
+    for (int s = 0; s < 4; ++s) Ap[s] = Bp[s] = nullptr;
+    if (d.bl) {
+      const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
+      C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
+      if (SEG) {
 #pragma unroll
-  for (int r = 0; r < NNB; ++r) {
-    const int n = tn * BN + bnn[r];
-    bval[r] = n < d.N;
-    boff[r] = bval[r] ? (int64_t)(n / d.N0) * d.sBn1 + (int64_t)(n % d.N0) * d.sBn0 : 0;
+        for (int s = 0; s < 4; ++s) {
+          const GemmDesc::Seg& g = d.seg[s < d.nseg ? s : 0];
+          Ap[s] = g.A + g.cA[0] * I + g.cA[1] * J + g.cA[2] * K + g.cA[3] * n;
+          Bp[s] = g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n;
+        }
+      } else {
+        A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
+        B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
+      }
+    } else {
+      A = d.A + b * d.sAb;
+      B = d.B + b * d.sBb;
+      C = d.C + b * d.sCb;
+    }
+    // segment starts; unused segments start at INT_MAX
+    sk1 = d.nseg > 1 ? d.seg[1].k0 : 0x7fffffff;
+    sk2 = d.nseg > 2 ? d.seg[2].k0 : 0x7fffffff;
+    sk3 = d.nseg > 3 ? d.seg[3].k0 : 0x7fffffff;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < NEA; ++r) {
+      const int e = tid + NT * r;
+      amm[r] = KFA ? e / BK : e % BM;
+      akk[r] = KFA ? e % BK : e / BM;
+    }
+#pragma unroll
+    for (int r = 0; r < NEB; ++r) {
+      const int e = tid + NT * r;
+      bnn[r] = NFB ? e % BN : e / BK;
+      bkk[r] = NFB ? e / BN : e % BK;
+    }
+#pragma unroll
+    for (int r = 0; r < NMA; ++r) {
+      const int m = m0 + amm[r];
+      aval[r] = m < d.M;
+      aoff[r] = aval[r] ? (int64_t)(m / d.M0) * d.sAm1 + (int64_t)(m % d.M0) * d.sAm0 : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < NNB; ++r) {
+      const int n = n0 + bnn[r];
+      bval[r] = n < d.N;
+      boff[r] = bval[r] ? (int64_t)(n / d.N0) * d.sBn1 + (int64_t)(n % d.N0) * d.sBn0 : 0;
+    }
+    return C;
   }
-  // Every load is issued: an element outside the operand reads offset 0 of
-  // its entry (the empty asm keeps the compiler from turning the address
-  // select back into a branch around the load) and is then replaced by zero.
-  cplx av[4], bv[NEB];
-  auto fetch = [](const cplx* p, bool ok, int64_t off) {
+
+  static __device__ __forceinline__ cplx fetch(const cplx* p, bool ok, int64_t off) {
     int64_t o = ok ? off : 0;
     asm volatile("" : "+v"(o));
     const cplx x = p[o];
     return cplx{ok ? x.re : 0.0, ok ? x.im : 0.0};
-  };
-  // Segment of k (SEG): unused segments start at INT_MAX.
-  const int sk1 = d.nseg > 1 ? d.seg[1].k0 : 0x7fffffff;
-  const int sk2 = d.nseg > 2 ? d.seg[2].k0 : 0x7fffffff;
-  const int sk3 = d.nseg > 3 ? d.seg[3].k0 : 0x7fffffff;
-  auto segof = [&](int k) { return (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3); };
-  auto pick = [](int s, auto x0, auto x1, auto x2, auto x3) { return s == 0 ? x0 : s == 1 ? x1 : s == 2 ? x2 : x3; };
-  auto load = [&](int k0) {
+  }
+  __device__ __forceinline__ int segof(int k) const { return (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3); }
+  template <typename X>
+  static __device__ __forceinline__ X pick(int s, X x0, X x1, X x2, X x3) {
+    return s == 0 ? x0 : s == 1 ? x1 : s == 2 ? x2 : x3;
+  }
+
+  __device__ __forceinline__ void load(const GemmDesc& d, int k0) {
     if (SEG) {
-      // A: one k per thread (k fast), four rows; B: one column, four k
+      static_assert(!SEG || (KFA && NFB), "segments are read with A k-fast and B n-fast");
       const int k = k0 + akk[0];
       const int s = segof(k);
       const int r = k - pick(s, 0, sk1, sk2, sk3);
@@ -170,8 +157,8 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
       const int64_t sm = pick(s, d.seg[0].sAm, d.seg[1].sAm, d.seg[2].sAm, d.seg[3].sAm);
       const int64_t kof = (int64_t)r * pick(s, d.seg[0].sAk, d.seg[1].sAk, d.seg[2].sAk, d.seg[3].sAk);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) av[t] = fetch(p, k < kend && aval[t], (int64_t)(tm * BM + amm[t]) * sm + kof);
-      const int64_t ncol = tn * BN + bnn[0];
+      for (int t = 0; t < NEA; ++t) av[t] = fetch(p, k < kend && aval[t], (int64_t)(m0 + amm[t]) * sm + kof);
+      const int64_t ncol = n0 + bnn[0];
 #pragma unroll
       for (int t = 0; t < NEB; ++t) {
         const int kb = k0 + bkk[t];
@@ -208,17 +195,76 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
         bv[e] = fetch(B, k < kend && bval[NFB ? 0 : t], boff[NFB ? 0 : t] + ko);
       }
     }
-  };
+  }
+};
+
+// C[m][n] (+)= alpha * x for one element of the tile.
+template <bool ATOMIC>
+__device__ __forceinline__ void put(const GemmDesc& d, cplx* C, int m, int n, double xr, double xi) {
+  if (m >= d.M || n >= d.N) return;
+  const double alr = d.alpha.re, ali = d.alpha.im;
+  const double vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
+  cplx* p = C + (int64_t)(m / d.M0) * d.sCm1 + (int64_t)(m % d.M0) * d.sCm0 + (int64_t)(n / d.N0) * d.sCn1 +
+            (int64_t)(n % d.N0) * d.sCn0;
+  if (ATOMIC) {
+    atomic_add_cplx(p, vr, vi);
+  } else if (d.store) {
+    *p = cplx{vr, vi};
+  } else {
+    cplx c = *p;
+    c.re += vr;
+    c.im += vi;
+    *p = c;
+  }
+}
+
+// One workgroup computes a 64 x BN tile of C for one batch entry.  BN = 64:
+// waves arranged 2x2, each owning a 32x32 sub-tile = 2x2 MFMA 16x16 blocks;
+// BN = 16 (narrow N, e.g. one occupied index): waves stacked 4x1, each owning
+// one 16x16 block.  Every block has a real and an imaginary accumulator:
+//   Cre += Are*Bre - Aim*Bim,  Cim += Are*Bim + Aim*Bre.
+// MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16].
+// Result layout: FP32 holds D[4*(l/16)+r][l%16] in register r, FP64 holds
+// D[4*r+l/16][l%16] (Frag<T>::row).
+// Tiles of A and B go through two LDS buffers: while the MFMAs consume one,
+// the next tile is loaded into registers and then stored into the other, so
+// each K step needs one barrier.
+template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG>
+__global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
+  typedef typename Frag<T>::acc acc_t;
+  constexpr int BK = 16;
+  constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
+  constexpr int IB = WM / 16, JB = WN / 16;                         // MFMA blocks per wave
+  typedef TileLoader<KFA, NFB, BN, BK, SEG> Loader;
+  __shared__ T sA[2][2][BK][BM + 1];  // [buffer][re, im][k][m]
+  __shared__ T sB[2][2][BK][BN + 1];  // [buffer][re, im][k][n]
+
+  const int tilesN = (d.N + BN - 1) / BN;
+  const int kz = blockIdx.x % ksplit;
+  const int tile = blockIdx.x / ksplit;
+  const int tm = tile / tilesN, tn = tile % tilesN;
+  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (b >= d.batch) return;
+  const int kbeg = kz * kchunk;
+  const int kend = min(d.K, kbeg + kchunk);
+  if (kbeg >= kend) return;
+
+  Loader ld;
+  cplx* C = ld.init(d, b, tm, tn, kend);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      sA[buf][0][akk[r]][amm[r]] = (T)av[r].re;
-      sA[buf][1][akk[r]][amm[r]] = (T)av[r].im;
+    for (int r = 0; r < Loader::NEA; ++r) {
+      sA[buf][0][ld.akk[r]][ld.amm[r]] = (T)ld.av[r].re;
+      sA[buf][1][ld.akk[r]][ld.amm[r]] = (T)ld.av[r].im;
     }
 #pragma unroll
-    for (int r = 0; r < NEB; ++r) {
-      sB[buf][0][bkk[r]][bnn[r]] = (T)bv[r].re;
-      sB[buf][1][bkk[r]][bnn[r]] = (T)bv[r].im;
+    for (int r = 0; r < Loader::NEB; ++r) {
+      sB[buf][0][ld.bkk[r]][ld.bnn[r]] = (T)ld.bv[r].re;
+      sB[buf][1][ld.bkk[r]][ld.bnn[r]] = (T)ld.bv[r].im;
     }
   };
 
@@ -232,14 +278,14 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     }
 
   const int nsteps = (kend - kbeg + BK - 1) / BK;
-  load(kbeg);
+  ld.load(d, kbeg);
   stash(0);
   __syncthreads();
   // The last step also loads and stores a (fully masked) next tile: the loop
   // body then has no branch, and the buffer it overwrites is no longer read.
   for (int it = 0; it < nsteps; ++it) {
     const int cur = it & 1;
-    load(kbeg + (it + 1) * BK);  // in flight during the MFMAs below
+    ld.load(d, kbeg + (it + 1) * BK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
@@ -277,32 +323,258 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     __syncthreads();
   }
 
-  const double alr = d.alpha.re, ali = d.alpha.im;
 #pragma unroll
   for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int j = 0; j < JB; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = tm * BM + wm + 16 * i + Frag<T>::row(lane, r);
-        const int n = tn * BN + wn + 16 * j + (lane & 15);
-        if (m < d.M && n < d.N) {
-          const double xr = (double)cre[i][j][r], xi = (double)cim[i][j][r];
-          const double vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
-          cplx* p = C + (int64_t)(m / d.M0) * d.sCm1 + (int64_t)(m % d.M0) * d.sCm0 +
-                    (int64_t)(n / d.N0) * d.sCn1 + (int64_t)(n % d.N0) * d.sCn0;
-          if (ATOMIC) {
-            atomic_add_cplx(p, vr, vi);
-          } else if (d.store) {
-            *p = cplx{vr, vi};
-          } else {
-            cplx c = *p;
-            c.re += vr;
-            c.im += vi;
-            *p = c;
-          }
+      for (int r = 0; r < 4; ++r)
+        put<ATOMIC>(d, C, tm * BM + wm + 16 * i + Frag<T>::row(lane, r), tn * BN + wn + 16 * j + (lane & 15),
+                    (double)cre[i][j][r], (double)cim[i][j][r]);
+}
+
+// Split bf16 operands: x = s_0 + s_1 + ... + s_{NSL-1} + O(2^-8NSL |x|) with
+// each s_p the bf16 rounding of what the earlier slices leave (every
+// remainder is exact in FP32).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+template <int NSL>
+__device__ __forceinline__ void bf16_slices8(const double* v, bf16x8* s) {
+  float x[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) x[e] = (float)v[e];
+#pragma unroll
+  for (int p = 0; p < NSL; ++p)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 h = (__bf16)x[e];
+      s[p][e] = h;
+      x[e] -= (float)h;
+    }
+}
+
+// Operand rows of the split kernel: thread t owns row t % R of its tile and
+// the eight consecutive k of chunk (t / R) % 4 (R = 64 rows, or 16 for a
+// narrow B tile, where only the first 64 threads load).  m- or n-fast
+// operands are then read by a wave as 64 consecutive rows per instruction.
+template <int R, bool SEG, bool ISA>
+struct SplitRows {
+  int row, chunk;
+  bool act, val;
+  int64_t roff;  // offset of the row (not SEG)
+  const cplx* P;  // entry base (not SEG)
+  const cplx* Ps[4];
+  __device__ __forceinline__ void init(const GemmDesc& d, int tid, int base, int ext, const cplx* p,
+                                       const cplx* const* ps) {
+    row = tid % R;
+    chunk = (tid / R) % 4;
+    act = tid < 4 * R;
+    const int x = base + row;
+    val = act && x < ext;
+    const int64_t s1 = ISA ? d.sAm1 : d.sBn1, s0 = ISA ? d.sAm0 : d.sBn0;
+    const int X0 = ISA ? d.M0 : d.N0;
+    roff = SEG ? 0 : (val ? (int64_t)(x / X0) * s1 + (int64_t)(x % X0) * s0 : 0);
+    P = p;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) Ps[s] = ps[s];
+  }
+  // Loads the eight elements k0 + 8*chunk + e (re and im parts).
+  __device__ __forceinline__ void load(const GemmDesc& d, int k0, int kend, int sk1, int sk2, int sk3, float invK0,
+                                       int xabs, double* re, double* im) const {
+    const int kb = k0 + 8 * chunk;
+    if (SEG) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;
+        const int s = (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3);
+        const int r = k - (s == 0 ? 0 : s == 1 ? sk1 : s == 2 ? sk2 : sk3);
+        const GemmDesc::Seg& g0 = d.seg[0];
+        const GemmDesc::Seg& g1 = d.seg[1];
+        const GemmDesc::Seg& g2 = d.seg[2];
+        const GemmDesc::Seg& g3 = d.seg[3];
+        const cplx* p = s == 0 ? Ps[0] : s == 1 ? Ps[1] : s == 2 ? Ps[2] : Ps[3];
+        int64_t sx, sk;
+        if (ISA) {
+          sx = s == 0 ? g0.sAm : s == 1 ? g1.sAm : s == 2 ? g2.sAm : g3.sAm;
+          sk = s == 0 ? g0.sAk : s == 1 ? g1.sAk : s == 2 ? g2.sAk : g3.sAk;
+        } else {
+          sx = s == 0 ? g0.sBn : s == 1 ? g1.sBn : s == 2 ? g2.sBn : g3.sBn;
+          sk = s == 0 ? g0.sBk : s == 1 ? g1.sBk : s == 2 ? g2.sBk : g3.sBk;
         }
+        const bool ok = val && k < kend;
+        int64_t o = ok ? (int64_t)xabs * sx + (int64_t)r * sk : 0;
+        asm volatile("" : "+v"(o));
+        const cplx v = p[o];
+        re[e] = ok ? v.re : 0.0;
+        im[e] = ok ? v.im : 0.0;
       }
+      return;
+    }
+    const int64_t k1 = ISA ? d.sAk1 : d.sBk1, k0s = ISA ? d.sAk0 : d.sBk0;
+    int q, r;
+    split_k(kb, d.K0, invK0, q, r);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool ok = val && kb + e < kend;
+      int64_t o = ok ? roff + (int64_t)q * k1 + (int64_t)r * k0s : 0;
+      asm volatile("" : "+v"(o));
+      const cplx v = P[o];
+      re[e] = ok ? v.re : 0.0;
+      im[e] = ok ? v.im : 0.0;
+      // next k
+      ++r;
+      q = r == d.K0 ? q + 1 : q;
+      r = r == d.K0 ? 0 : r;
+    }
+  }
+};
+
+// The same tile product on the bf16 matrix cores (16x16x32 MFMA, FP32
+// accumulate) with each real operand split into NSL bf16 slices; the real
+// products keep the slice pairs (p, q) with p + q < NSL (3 pairs for two
+// slices, 6 for three), dropping terms of relative size 2^-8NSL.  The real
+// part accumulates Re*Re and Im*Im separately and subtracts at the end.
+// MFMA 16x16x32 bf16 operand layout: lane l holds A[l%16][8*(l/16) + 0..7] and
+// B[8*(l/16) + 0..7][l%16]; the result layout is that of the FP32 MFMAs.
+// LDS holds each slice as [row][k] (A rows m, B rows n) in rows of 32 bf16 =
+// four 16-byte chunks, chunk index xor (row/4)%4, so that the 16 rows of one
+// fragment read cover all banks once.  One buffer and two barriers per K
+// step; several workgroups per CU overlap one's loads with another's MFMAs.
+template <bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG, int NSL>
+__global__ __launch_bounds__(NT) void zgemm_split_kernel(GemmDesc d, int ksplit, int kchunk) {
+  constexpr int BK = 32;
+  constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;
+  constexpr int IB = WM / 16, JB = WN / 16;
+  __shared__ __attribute__((aligned(16))) bf16x8 sA[2][NSL][BM][BK / 8];  // [re, im][slice][m][k chunk]
+  __shared__ __attribute__((aligned(16))) bf16x8 sB[2][NSL][BN][BK / 8];  // [re, im][slice][n][k chunk]
+
+  const int tilesN = (d.N + BN - 1) / BN;
+  const int kz = blockIdx.x % ksplit;
+  const int tile = blockIdx.x / ksplit;
+  const int tm = tile / tilesN, tn = tile % tilesN;
+  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (b >= d.batch) return;
+  const int kbeg = kz * kchunk;
+  const int kend = min(d.K, kbeg + kchunk);
+  if (kbeg >= kend) return;
+
+  // entry bases
+  const cplx* A = nullptr;
+  const cplx* B = nullptr;
+  const cplx* Ap[4] = {nullptr, nullptr, nullptr, nullptr};
+  const cplx* Bp[4] = {nullptr, nullptr, nullptr, nullptr};
+  cplx* C;
+  if (d.bl) {
+    const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
+    C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
+    if (SEG) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const GemmDesc::Seg& g = d.seg[s < d.nseg ? s : 0];
+        Ap[s] = g.A + g.cA[0] * I + g.cA[1] * J + g.cA[2] * K + g.cA[3] * n;
+        Bp[s] = g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n;
+      }
+    } else {
+      A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
+      B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
+    }
+  } else {
+    A = d.A + b * d.sAb;
+    B = d.B + b * d.sBb;
+    C = d.C + b * d.sCb;
+  }
+  const int sk1 = d.nseg > 1 ? d.seg[1].k0 : 0x7fffffff;
+  const int sk2 = d.nseg > 2 ? d.seg[2].k0 : 0x7fffffff;
+  const int sk3 = d.nseg > 3 ? d.seg[3].k0 : 0x7fffffff;
+  const float invK0 = 1.0f / (float)d.K0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+  SplitRows<BM, SEG, true> ra;
+  SplitRows<BN, SEG, false> rb;
+  ra.init(d, tid, tm * BM, d.M, A, Ap);
+  rb.init(d, tid, tn * BN, d.N, B, Bp);
+  auto cswz = [](int row, int c) { return (c ^ (row >> 2)) & 3; };
+
+  f4 crr[IB][JB], cii[IB][JB], cim[IB][JB];
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      crr[i][j] = f4{0, 0, 0, 0};
+      cii[i][j] = f4{0, 0, 0, 0};
+      cim[i][j] = f4{0, 0, 0, 0};
+    }
+
+  const int nsteps = (kend - kbeg + BK - 1) / BK;
+  const int c16 = lane & 15, kc = lane >> 4;
+  for (int it = 0; it < nsteps; ++it) {
+    const int k0 = kbeg + it * BK;
+    double xr[8], xi[8];
+    bf16x8 sr[NSL], si[NSL];
+    ra.load(d, k0, kend, sk1, sk2, sk3, invK0, tm * BM + ra.row, xr, xi);
+    bf16_slices8<NSL>(xr, sr);
+    bf16_slices8<NSL>(xi, si);
+    double yr[8], yi[8];
+    bf16x8 tr[NSL], ti[NSL];
+    if (rb.act) {
+      rb.load(d, k0, kend, sk1, sk2, sk3, invK0, tn * BN + rb.row, yr, yi);
+      bf16_slices8<NSL>(yr, tr);
+      bf16_slices8<NSL>(yi, ti);
+    }
+    __syncthreads();  // the previous step's fragment reads are done
+#pragma unroll
+    for (int p = 0; p < NSL; ++p) {
+      sA[0][p][ra.row][cswz(ra.row, ra.chunk)] = sr[p];
+      sA[1][p][ra.row][cswz(ra.row, ra.chunk)] = si[p];
+    }
+    if (rb.act) {
+#pragma unroll
+      for (int p = 0; p < NSL; ++p) {
+        sB[0][p][rb.row][cswz(rb.row, rb.chunk)] = tr[p];
+        sB[1][p][rb.row][cswz(rb.row, rb.chunk)] = ti[p];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NSL; ++p) {
+      bf16x8 ar[IB], ai[IB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        const int row = wm + 16 * i + c16;
+        ar[i] = sA[0][p][row][cswz(row, kc)];
+        ai[i] = sA[1][p][row][cswz(row, kc)];
+      }
+#pragma unroll
+      for (int q = 0; q + p < NSL; ++q) {
+        bf16x8 br[JB], bi[JB];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          const int row = wn + 16 * j + c16;
+          br[j] = sB[0][q][row][cswz(row, kc)];
+          bi[j] = sB[1][q][row][cswz(row, kc)];
+        }
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) {
+            crr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[i], br[j], crr[i][j], 0, 0, 0);
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[i], bi[j], cim[i][j], 0, 0, 0);
+            cii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[i], bi[j], cii[i][j], 0, 0, 0);
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[i], br[j], cim[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        put<ATOMIC>(d, C, tm * BM + wm + 16 * i + Frag<float>::row(lane, r), tn * BN + wn + 16 * j + (lane & 15),
+                    (double)crr[i][j][r] - (double)cii[i][j][r], (double)cim[i][j][r]);
 }
 
 __global__ void axpy_kernel(AxpyDesc d, int64_t total) {
@@ -335,42 +607,52 @@ inline unsigned grid_for(int64_t n, int bs) {
   return (unsigned)g;
 }
 
-template <typename T, bool ATOMIC, int BN>
-void launch_zgemm_l(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb) {
-  if (kfa && nfb)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-  else if (kfa)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-  else if (nfb)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, true, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+// Kernel choice: precision (FP64, FP32, bf16 split with 3 or 2 slices),
+// atomic epilogue, operand layouts, tile width and K segments.
+template <int MODE, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG>
+void launch_one(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk) {
+  if (MODE == RTCC3_PREC_FP64)
+    hipLaunchKernelGGL((zgemm_kernel<double, ATOMIC, KFA, NFB, BN, SEG>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else if (MODE == RTCC3_PREC_FP32)
+    hipLaunchKernelGGL((zgemm_kernel<float, ATOMIC, KFA, NFB, BN, SEG>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else if (MODE == RTCC3_PREC_BF16X3)
+    hipLaunchKernelGGL((zgemm_split_kernel<ATOMIC, KFA, NFB, BN, SEG, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   else
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, false, BN, false>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    hipLaunchKernelGGL((zgemm_split_kernel<ATOMIC, KFA, NFB, BN, SEG, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
 }
 
-template <typename T, bool ATOMIC>
-void launch_zgemm_t(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb,
-                    int bn) {
+template <int MODE, bool ATOMIC>
+void launch_layout(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb, int bn) {
   if (d.nseg > 0)
-    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, 64, true>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
-  else if (bn == 16)
-    launch_zgemm_l<T, ATOMIC, 16>(d, grid, s, ksplit, kchunk, kfa, nfb);
-  else
-    launch_zgemm_l<T, ATOMIC, 64>(d, grid, s, ksplit, kchunk, kfa, nfb);
+    launch_one<MODE, ATOMIC, true, true, 64, true>(d, grid, s, ksplit, kchunk);
+  else if (bn == 16) {
+    if (kfa && nfb)
+      launch_one<MODE, ATOMIC, true, true, 16, false>(d, grid, s, ksplit, kchunk);
+    else if (kfa)
+      launch_one<MODE, ATOMIC, true, false, 16, false>(d, grid, s, ksplit, kchunk);
+    else if (nfb)
+      launch_one<MODE, ATOMIC, false, true, 16, false>(d, grid, s, ksplit, kchunk);
+    else
+      launch_one<MODE, ATOMIC, false, false, 16, false>(d, grid, s, ksplit, kchunk);
+  } else {
+    if (kfa && nfb)
+      launch_one<MODE, ATOMIC, true, true, 64, false>(d, grid, s, ksplit, kchunk);
+    else if (kfa)
+      launch_one<MODE, ATOMIC, true, false, 64, false>(d, grid, s, ksplit, kchunk);
+    else if (nfb)
+      launch_one<MODE, ATOMIC, false, true, 64, false>(d, grid, s, ksplit, kchunk);
+    else
+      launch_one<MODE, ATOMIC, false, false, 64, false>(d, grid, s, ksplit, kchunk);
+  }
 }
 
-void launch_zgemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool f32, bool atomic,
-                  bool kfa, bool nfb, int bn) {
-  if (f32) {
-    if (atomic)
-      launch_zgemm_t<float, true>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
-    else
-      launch_zgemm_t<float, false>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
-  } else {
-    if (atomic)
-      launch_zgemm_t<double, true>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
-    else
-      launch_zgemm_t<double, false>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
-  }
+template <int MODE>
+void launch_mode(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool atomic, bool kfa, bool nfb,
+                 int bn) {
+  if (atomic)
+    launch_layout<MODE, true>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
+  else
+    launch_layout<MODE, false>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
 }
 
 // The same product with the roles of A and B exchanged: C^T = B^T A^T.
@@ -427,12 +709,13 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   // K is long; the partial products are then added with atomics.
   int ksplit = 1;
   const int64_t wgs = tiles * d.batch;
-  if (!d.store && wgs < 512 && d.K >= 8 * BK) {
+  constexpr int BKMAX = 32;  // K chunks are multiples of every kernel's K step
+  if (!d.store && wgs < 512 && d.K >= 4 * BKMAX) {
     const int64_t want = (1024 + wgs - 1) / wgs;
-    const int64_t maxs = d.K / (4 * BK);
+    const int64_t maxs = d.K / (2 * BKMAX);
     ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
   }
-  const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BK - 1) / BK * BK);
+  const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BKMAX - 1) / BKMAX * BKMAX);
   RTCC3_CHECK(tiles * ksplit < (1LL << 31), "gemm: too many tiles");
   int64_t by = d.batch, bz = 1;
   while (by > 65535) {
@@ -442,7 +725,22 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   dim3 grid((unsigned)(tiles * ksplit), (unsigned)by, (unsigned)bz);
   const bool atomic = d.atomic || ksplit > 1;
   const bool kfa = d.sAk0 == 1, nfb = d.sBn0 == 1;
-  launch_zgemm(d, grid, s, ksplit, kchunk, d.prec != 0, atomic, kfa, nfb, bn);
+  switch (d.prec) {
+    case RTCC3_PREC_FP64:
+      launch_mode<RTCC3_PREC_FP64>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
+      break;
+    case RTCC3_PREC_FP32:
+      launch_mode<RTCC3_PREC_FP32>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
+      break;
+    case RTCC3_PREC_BF16X3:
+      launch_mode<RTCC3_PREC_BF16X3>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
+      break;
+    case RTCC3_PREC_BF16X2:
+      launch_mode<RTCC3_PREC_BF16X2>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
+      break;
+    default:
+      RTCC3_CHECK(false, "gemm: unknown precision");
+  }
   RTCC3_HIP(hipGetLastError());
 }
 

@@ -168,6 +168,10 @@ bool finite(const double* p, int64_t n) {
 
 // =============================================================================
 
+static_assert(RTCC3_FP64 == RTCC3_PREC_FP64 && RTCC3_FP32 == RTCC3_PREC_FP32 && RTCC3_BF16X3 == RTCC3_PREC_BF16X3 &&
+                  RTCC3_BF16X2 == RTCC3_PREC_BF16X2,
+              "precision codes of the C interface and the kernels differ");
+
 extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const double* B, const double* dipole,
                             int precision, void* hip_stream, rtcc3_ctx** out) {
   if (!out) return fail(nullptr, RTCC3_EINVAL, "out is NULL");
@@ -175,7 +179,7 @@ extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const do
   if (o < 1 || v < 1) return fail(nullptr, RTCC3_EINVAL, "need o >= 1 and v >= 1");
   if (naux < 1) return fail(nullptr, RTCC3_EINVAL, "need naux >= 1");
   if (!fock || !B || !dipole) return fail(nullptr, RTCC3_EINVAL, "NULL input array");
-  if (precision != RTCC3_FP64 && precision != RTCC3_FP32) return fail(nullptr, RTCC3_EINVAL, "unknown precision");
+  if (precision < RTCC3_FP64 || precision > RTCC3_BF16X2) return fail(nullptr, RTCC3_EINVAL, "unknown precision");
   const int64_t n = (int64_t)o + v;
   if (n > 4096 || (int64_t)naux * n * n > (int64_t)1 << 34)
     return fail(nullptr, RTCC3_ENOMEM, "system too large");
@@ -412,7 +416,7 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
     return RTCC3_OK;
   }
   if (option == RTCC3_OPT_PRECISION) {
-    if (value != RTCC3_FP64 && value != RTCC3_FP32) return fail(c, RTCC3_EINVAL, "unknown precision");
+    if (value < RTCC3_FP64 || value > RTCC3_BF16X2) return fail(c, RTCC3_EINVAL, "unknown precision");
     c->precision = value;
     c->tri->set_precision(value);
     return RTCC3_OK;
@@ -443,7 +447,7 @@ extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
 extern "C" int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rtcc3_c64* A, const rtcc3_c64* B,
                                     rtcc3_c64* Cout) {
   if (M < 1 || N < 1 || K < 1 || !A || !B || !Cout) return fail(nullptr, RTCC3_EINVAL, "bad gemm arguments");
-  if (precision != RTCC3_FP64 && precision != RTCC3_FP32) return fail(nullptr, RTCC3_EINVAL, "unknown precision");
+  if (precision < RTCC3_FP64 || precision > RTCC3_BF16X2) return fail(nullptr, RTCC3_EINVAL, "unknown precision");
   if ((int64_t)M * K > (1LL << 28) || (int64_t)K * N > (1LL << 28) || (int64_t)M * N > (1LL << 28))
     return fail(nullptr, RTCC3_EINVAL, "gemm self-test too large");
   cplx *dA = nullptr, *dB = nullptr, *dC = nullptr;

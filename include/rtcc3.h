@@ -60,7 +60,9 @@ enum {
  *   RTCC3_BF16X3  each real operand split into three bf16 slices (about FP32's
  *                 24 significand bits), six slice products on the bf16 matrix
  *                 cores, FP32 accumulation
- *   RTCC3_BF16X2  two bf16 slices (16 bits), three slice products */
+ *   RTCC3_BF16X2  two bf16 slices (16 bits), three slice products
+ * The bf16 splits apply to the products that build t3 and lambda3; the other
+ * triples products of such a run use FP32. */
 enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1, RTCC3_BF16X3 = 2, RTCC3_BF16X2 = 3 };
 
 /* Create a context.

@@ -78,6 +78,9 @@ struct GemmDesc {
   Seg seg[4];
   // store = 1: C = alpha*AB without reading C (no split-K, not atomic).
   int store;
+  // A bf16-split precision runs unsegmented products in FP32 unless
+  // force_prec is set (self-tests of the split kernel).
+  int force_prec;
 };
 void gemm(const GemmDesc& d, hipStream_t s);
 

@@ -725,7 +725,12 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   dim3 grid((unsigned)(tiles * ksplit), (unsigned)by, (unsigned)bz);
   const bool atomic = d.atomic || ksplit > 1;
   const bool kfa = d.sAk0 == 1, nfb = d.sBn0 == 1;
-  switch (d.prec) {
+  // The bf16 split pays off only where the matrix cores bound the product (the
+  // long segmented builds); the other products of a split-precision run use
+  // FP32, which is at least as accurate.
+  const bool split = d.prec == RTCC3_PREC_BF16X3 || d.prec == RTCC3_PREC_BF16X2;
+  const int prec = split && d.nseg == 0 && !d.force_prec ? RTCC3_PREC_FP32 : d.prec;
+  switch (prec) {
     case RTCC3_PREC_FP64:
       launch_mode<RTCC3_PREC_FP64>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
       break;

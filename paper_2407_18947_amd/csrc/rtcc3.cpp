@@ -478,6 +478,7 @@ extern "C" int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rt
     g.sCn0 = 1;
     g.alpha = cplx{1, 0};
     g.prec = precision;
+    g.force_prec = 1;
     gemm(g, nullptr);
     RTCC3_HIP(hipDeviceSynchronize());
     RTCC3_HIP(hipMemcpy(Cout, dC, sizeof(cplx) * M * N, hipMemcpyDeviceToHost));

@@ -29,6 +29,27 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
 PRECISIONS = ("fp64", "fp32", "bf16x3", "bf16x2")
 # real bf16 products per complex multiply-add: 4 real products times the kept slice pairs
 SLICE_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
+# HBM bytes per launch of the build product, from the two counter passes in
+# profiles/build_product_trimer_o15_v57_fp64_traffic.md (FETCH_SIZE, WRITE_SIZE,
+# scaled by a 1 GiB copy).  Valid only for the sources they were measured on.
+MEASURED_TRAFFIC = {
+    "fingerprint": {"kernels.hip": "e827d91d0ac49e79", "triples.cpp": "47342cb115d45f72"},
+    "config": (15, 57, "fp64"),
+    "bytes_per_launch": 1.957e9 + 0.900e9,
+}
+
+
+def _traffic(o: int, v: int, precision: str):
+    """The measured traffic if it applies to this build and workload, else None."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2407_18947_amd", "csrc")
+    for name, want in MEASURED_TRAFFIC["fingerprint"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != want:
+                return None
+    if MEASURED_TRAFFIC["config"] != (o, v, precision):
+        return None
+    return MEASURED_TRAFFIC["bytes_per_launch"]
 
 
 def triples_flops_per_step(o: int, v: int) -> float:
@@ -93,6 +114,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-blocks", type=int, default=60, help="oracle blocks timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -129,12 +152,23 @@ def main():
         series = np.concatenate([np.asarray(mu_w), np.asarray(mu)]) if mu_w is not None else np.asarray(mu)
         return t1 - t0, series, timing
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     secs, mu_main, timing = run(args.precision)
     steps_per_s = K / secs
     tri_ms_per_step = timing[1] / K
     alg = triples_flops_per_step(o, v)
     achieved = alg / (tri_ms_per_step * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision] / SLICE_PRODUCTS[args.precision]
+    b_ms, b_launches, b_flop = timing[3], timing[4], timing[5]
+    b_achieved = b_flop / (b_ms * 1e-3) / 1e12 if b_ms > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -147,22 +181,34 @@ def main():
         "scaling": "weak",
         "vs_baseline": steps_per_s / PAPER_GPU_DP_TRIMER_STEPS_PER_S,
         "dtype": {"fp64": "f64", "fp32": "f32 triples GEMMs, f64 elsewhere",
-                  "bf16x3": "bf16x3-split triples GEMMs (f32 accumulate), f64 elsewhere",
-                  "bf16x2": "bf16x2-split triples GEMMs (f32 accumulate), f64 elsewhere"}[args.precision],
+                  "bf16x3": "bf16x3-split triples build GEMMs, f32 other triples GEMMs, f64 elsewhere",
+                  "bf16x2": "bf16x2-split triples build GEMMs, f32 other triples GEMMs, f64 elsewhere"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"RT-CC3 T+Lambda, o={o}, v={v}, naux={s.naux}, seeded synthetic water-trimer-sized "
                          f"integrals (seed {args.seed}), delta kick {amp} a.u. along z, dt={dt}"),
             "o": o, "v": v, "naux": s.naux, "precision": args.precision,
         },
+        # Dominant kernel: the segmented product that builds a window's t3 (and,
+        # in a second launch, lambda3) blocks before symmetrisation.
         "roofline": {
             "bound": "mfma",
-            "kernel": "triples engine (all triples kernels of a step: 4 RHS passes + density pass)",
-            "achieved": achieved,
+            "kernel": "zgemm_kernel<double, false, true, true, 64, true> (t3 and lambda3 build products)"
+            if args.precision == "fp64" else "segmented build products",
+            "achieved": b_achieved,
             "peak": peak,
             "unit": "TFLOP/s",
+            "frac": b_achieved / peak,
+            "traffic": _traffic(o, v, args.precision),
+            "launches": int(b_launches),
+            "avg_launch_ms": b_ms / max(b_launches, 1),
+            "algorithmic_flop_per_launch": b_flop / max(b_launches, 1),
+        },
+        # All triples kernels of a step together, against the same peak.
+        "triples_engine": {
+            "achieved": achieved,
+            "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
             "triples_ms_per_step": tri_ms_per_step,
             "algorithmic_flop_per_step": alg,
         },

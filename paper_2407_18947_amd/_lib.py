@@ -142,7 +142,7 @@ def rtcc3_set_option(ctx, option, value):
 
 
 def rtcc3_last_timing(ctx):
-    out = np.zeros(3)
+    out = np.zeros(6)
     _check(load().rtcc3_last_timing(ctx, _ptr(out)), ctx)
     return out
 

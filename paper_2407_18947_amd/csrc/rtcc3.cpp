@@ -24,7 +24,7 @@ struct rtcc3_ctx {
   int64_t ylen = 0;
   View B, mu, h0, I, ones_o, h;
   cplx *y = nullptr, *ytmp = nullptr, *k = nullptr, *acc = nullptr;
-  double last_ms[3] = {0, 0, 0};
+  double last_ms[6] = {0, 0, 0, 0, 0, 0};
   cplx* mus = nullptr;  // dipole series of the last propagation (grows on demand)
   int64_t mus_n = 0;
   std::string err;
@@ -400,6 +400,7 @@ extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double*
     RTCC3_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->last_ms[0] = ms;
     c->tri->timing(c->last_ms[1], c->last_ms[2]);
+    c->tri->build_timing(c->last_ms[3], c->last_ms[4], c->last_ms[5]);
     std::vector<cplx> mh((size_t)(steps + 1) * 3);
     RTCC3_HIP(hipMemcpy(mh.data(), mus.p, sizeof(cplx) * mh.size(), hipMemcpyDeviceToHost));
     if (dipole_out) std::memcpy(dipole_out, mh.data(), sizeof(cplx) * mh.size());
@@ -424,9 +425,9 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
   return fail(c, RTCC3_EINVAL, "unknown option");
 }
 
-extern "C" int rtcc3_last_timing(rtcc3_ctx* c, double kernel_ms[3]) {
+extern "C" int rtcc3_last_timing(rtcc3_ctx* c, double kernel_ms[6]) {
   if (!c || !kernel_ms) return RTCC3_EINVAL;
-  for (int i = 0; i < 3; ++i) kernel_ms[i] = c->last_ms[i];
+  for (int i = 0; i < 6; ++i) kernel_ms[i] = c->last_ms[i];
   return RTCC3_OK;
 }
 

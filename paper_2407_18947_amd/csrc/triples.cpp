@@ -133,6 +133,9 @@ Triples::~Triples() {
       if (w.d_slabs) (void)hipFree(w.d_slabs);
     }
   if (eps_) (void)hipFree(eps_);
+  if (t0_) (void)hipEventDestroy(t0_);
+  if (t1_) (void)hipEventDestroy(t1_);
+  for (hipEvent_t ev : bev_) (void)hipEventDestroy(ev);
 }
 
 namespace {
@@ -383,7 +386,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     g.sCn0 = 1;
     set4(g.cC, 0, 0, 0, v3);
     const int64_t lA[2] = {lT2, lOOOV}, lB[2] = {lOVVV_, lT2};
+    build_event(s);
     checked_seg_gemm(g, blh, lA, lB, winlen, s);
+    build_event(s);
+    build_flop_ += 8.0 * nw * v * v2 * (v + o);
   }
   launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
 
@@ -406,7 +412,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, v3);
     const int64_t lLC = (int64_t)o * v * o * o;
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
+    build_event(s);
     checked_seg_gemm(g, blh, lA, lB, winlen, s);
+    build_event(s);
+    build_flop_ += 8.0 * nw * v * v2 * (2 * o + 2 * v);
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
@@ -704,6 +713,15 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   }
 }
 
+void Triples::build_event(hipStream_t s) {
+  if (nbev_ == (int)bev_.size()) {
+    hipEvent_t ev;
+    RTCC3_HIP(hipEventCreate(&ev));
+    bev_.push_back(ev);
+  }
+  RTCC3_HIP(hipEventRecord(bev_[nbev_++], s));
+}
+
 TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density) {
   const int64_t o = d.o, v = d.v;
   const int64_t ov = o * v, oovv = o * o * v * v;
@@ -713,6 +731,7 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
     RTCC3_HIP(hipEventCreate(&t1_));
   }
   RTCC3_HIP(hipEventRecord(t0_, s));
+  nbev_ = 0;
   blocks(e, r);
   // accumulators
   const char* names[] = {"tr_X1", "tr_X2p", "tr_Y1", "tr_Y2p", "tr_Z34", "tr_R15",
@@ -784,6 +803,12 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   float ms = 0;
   RTCC3_HIP(hipEventElapsedTime(&ms, t0_, t1_));
   ms_ += ms;
+  for (int i = 0; i + 1 < nbev_; i += 2) {
+    float b = 0;
+    RTCC3_HIP(hipEventElapsedTime(&b, bev_[i], bev_[i + 1]));
+    build_ms_ += b;
+    ++build_launches_;
+  }
   return out;
 }
 

@@ -40,8 +40,24 @@ class Triples {
   // the blocks each window owns.
   TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density);
   void set_precision(int p) { prec_ = p; }
-  void reset_timing() { ms_ = 0; launches_ = 0; }
-  void timing(double& ms, double& launches) const { ms = ms_; launches = (double)launches_; }
+  void reset_timing() {
+    ms_ = 0;
+    launches_ = 0;
+    build_ms_ = 0;
+    build_launches_ = 0;
+    build_flop_ = 0;
+  }
+  void timing(double& ms, double& launches) const {
+    ms = ms_;
+    launches = (double)launches_;
+  }
+  // The segmented build products (t3 and lambda3): event-timed milliseconds,
+  // launches and algorithmic flops (8 per complex multiply-add).
+  void build_timing(double& ms, double& launches, double& flop) const {
+    ms = build_ms_;
+    launches = (double)build_launches_;
+    flop = build_flop_;
+  }
 
  private:
   Dims d_;
@@ -52,6 +68,11 @@ class Triples {
   double ms_ = 0;
   long launches_ = 0;
   hipEvent_t t0_ = nullptr, t1_ = nullptr;
+  double build_ms_ = 0, build_flop_ = 0;
+  long build_launches_ = 0;
+  std::vector<hipEvent_t> bev_;  // event pairs around the build products of one run
+  int nbev_ = 0;                 // pairs recorded in the current run
+  void build_event(hipStream_t s);
 
   void build_windows();
   void upload(Window& w);

@@ -81,6 +81,16 @@ struct GemmDesc {
   // A bf16-split precision runs unsegmented products in FP32 unless
   // force_prec is set (self-tests of the split kernel).
   int force_prec;
+  // Combined operand (comb_n = 3, block table required, A read k-fast and B
+  // k-fast): operand A (comb_on = 0) or B (comb_on = 1) of batch entry b is
+  //   sum_s comb_w[s] * X[part[6*n + comb_perm[s]]*comb_stride + offset],  n = bl[4*b + 3],
+  // in place of its block-table offset; e.g. a linear combination of a block
+  // and blocks of permuted occupied triples read at the same element offset.
+  int comb_n, comb_on;
+  const int* part;
+  int comb_perm[3];
+  double comb_w[3];
+  int64_t comb_stride;
 };
 void gemm(const GemmDesc& d, hipStream_t s);
 

@@ -1,6 +1,7 @@
 // Generic kernels: batched complex GEMM on the matrix cores (FP64 or FP32
 // MFMA, complex product as four real products), strided axpy/permute, fill.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -58,7 +59,8 @@ __device__ __forceinline__ void split_k(int k, int K0, float inv, int& q, int& r
 // Every load is issued: an element outside the operand reads offset 0 of its
 // entry (the empty asm keeps the compiler from turning the address select
 // back into a branch around the load) and is then replaced by zero.
-template <bool KFA, bool NFB, int BN, int BK, bool SEG>
+// CMB = 1 / 2: operand A / B is a combination of three blocks (GemmDesc::comb_*).
+template <bool KFA, bool NFB, int BN, int BK, bool SEG, int CMB = 0>
 struct TileLoader {
   static constexpr int NEA = BM * BK / NT, NEB = BN * BK / NT;
   static constexpr int NKA = KFA ? 1 : NEA, NMA = KFA ? NEA : 1;
@@ -70,6 +72,8 @@ struct TileLoader {
   const cplx* B;
   const cplx* Ap[4];  // K-segment bases of this entry
   const cplx* Bp[4];
+  const cplx* Xc[3];  // bases of the combined operand's blocks
+  double wc[3];
   int kend, sk1, sk2, sk3, m0, n0;
   float invK0;
   cplx av[NEA], bv[NEB];
@@ -97,6 +101,15 @@ struct TileLoader {
       } else {
         A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
         B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
+      }
+      if (CMB) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          Xc[s] = (CMB == 1 ? d.A : d.B) + (int64_t)d.part[6 * n + d.comb_perm[s]] * d.comb_stride;
+          wc[s] = d.comb_w[s];
+        }
+        if (CMB == 1) A = Xc[0];
+        if (CMB == 2) B = Xc[0];
       }
     } else {
       A = d.A + b * d.sAb;
@@ -141,6 +154,14 @@ struct TileLoader {
     const cplx x = p[o];
     return cplx{ok ? x.re : 0.0, ok ? x.im : 0.0};
   }
+  __device__ __forceinline__ cplx fetch3(bool ok, int64_t off) const {
+    int64_t o = ok ? off : 0;
+    asm volatile("" : "+v"(o));
+    const cplx x0 = Xc[0][o], x1 = Xc[1][o], x2 = Xc[2][o];
+    const double re = wc[0] * x0.re + wc[1] * x1.re + wc[2] * x2.re;
+    const double im = wc[0] * x0.im + wc[1] * x1.im + wc[2] * x2.im;
+    return cplx{ok ? re : 0.0, ok ? im : 0.0};
+  }
   __device__ __forceinline__ int segof(int k) const { return (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3); }
   template <typename X>
   static __device__ __forceinline__ X pick(int s, X x0, X x1, X x2, X x3) {
@@ -180,7 +201,8 @@ struct TileLoader {
 #pragma unroll
       for (int t = 0; t < NMA; ++t) {
         const int e = KFA ? t : s;
-        av[e] = fetch(A, k < kend && aval[KFA ? t : 0], aoff[KFA ? t : 0] + ko);
+        const bool ok = k < kend && aval[KFA ? t : 0];
+        av[e] = CMB == 1 ? fetch3(ok, aoff[KFA ? t : 0] + ko) : fetch(A, ok, aoff[KFA ? t : 0] + ko);
       }
     }
 #pragma unroll
@@ -192,7 +214,8 @@ struct TileLoader {
 #pragma unroll
       for (int t = 0; t < NNB; ++t) {
         const int e = NFB ? s : t;
-        bv[e] = fetch(B, k < kend && bval[NFB ? 0 : t], boff[NFB ? 0 : t] + ko);
+        const bool ok = k < kend && bval[NFB ? 0 : t];
+        bv[e] = CMB == 2 ? fetch3(ok, boff[NFB ? 0 : t] + ko) : fetch(B, ok, boff[NFB ? 0 : t] + ko);
       }
     }
   }
@@ -229,13 +252,13 @@ __device__ __forceinline__ void put(const GemmDesc& d, cplx* C, int m, int n, do
 // Tiles of A and B go through two LDS buffers: while the MFMAs consume one,
 // the next tile is loaded into registers and then stored into the other, so
 // each K step needs one barrier.
-template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG>
+template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG, int CMB = 0>
 __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
   typedef typename Frag<T>::acc acc_t;
   constexpr int BK = 16;
   constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
   constexpr int IB = WM / 16, JB = WN / 16;                         // MFMA blocks per wave
-  typedef TileLoader<KFA, NFB, BN, BK, SEG> Loader;
+  typedef TileLoader<KFA, NFB, BN, BK, SEG, CMB> Loader;
   __shared__ T sA[2][2][BK][BM + 1];  // [buffer][re, im][k][m]
   __shared__ T sB[2][2][BK][BN + 1];  // [buffer][re, im][k][n]
 
@@ -621,9 +644,26 @@ void launch_one(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kch
     hipLaunchKernelGGL((zgemm_split_kernel<ATOMIC, KFA, NFB, BN, SEG, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
 }
 
+// Combined-operand products (A k-fast, B k-fast), FP64 or FP32.
+template <int MODE, bool ATOMIC, int BN>
+void launch_comb_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk) {
+  typedef typename std::conditional<MODE == RTCC3_PREC_FP64, double, float>::type T;
+  if (d.comb_on == 0)
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false, 1>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+}
+
 template <int MODE, bool ATOMIC>
 void launch_layout(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb, int bn) {
-  if (d.nseg > 0)
+  if (d.comb_n > 0) {
+    if (MODE == RTCC3_PREC_FP64 || MODE == RTCC3_PREC_FP32) {
+      if (bn == 16)
+        launch_comb_gemm<MODE, ATOMIC, 16>(d, grid, s, ksplit, kchunk);
+      else
+        launch_comb_gemm<MODE, ATOMIC, 64>(d, grid, s, ksplit, kchunk);
+    }
+  } else if (d.nseg > 0)
     launch_one<MODE, ATOMIC, true, true, 64, true>(d, grid, s, ksplit, kchunk);
   else if (bn == 16) {
     if (kfa && nfb)
@@ -678,6 +718,7 @@ GemmDesc transposed(const GemmDesc& d) {
   t.sCm0 = d.sCn0;
   t.sCn1 = d.sCm1;
   t.sCn0 = d.sCm0;
+  t.comb_on = 1 - d.comb_on;
   std::copy(d.cB, d.cB + 4, t.cA);
   std::copy(d.cA, d.cA + 4, t.cB);
   return t;
@@ -689,6 +730,10 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   if (d0.M <= 0 || d0.N <= 0 || d0.batch <= 0) return;
   if (d0.K <= 0) return;
   RTCC3_CHECK(d0.M0 >= 1 && d0.N0 >= 1 && d0.K0 >= 1, "gemm: inner extents must be >= 1");
+  if (d0.comb_n > 0) {
+    RTCC3_CHECK(d0.comb_n == 3 && d0.bl && d0.part && d0.nseg == 0 && (d0.comb_on == 0 || d0.comb_on == 1),
+                "gemm: bad combined operand");
+  }
   if (d0.nseg > 0) {
     RTCC3_CHECK(d0.nseg <= 4 && d0.bl && d0.seg[0].k0 == 0 && d0.M0 == d0.M && d0.N0 == d0.N,
                 "gemm: bad K segments");
@@ -725,11 +770,12 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   dim3 grid((unsigned)(tiles * ksplit), (unsigned)by, (unsigned)bz);
   const bool atomic = d.atomic || ksplit > 1;
   const bool kfa = d.sAk0 == 1, nfb = d.sBn0 == 1;
+  RTCC3_CHECK(!d.comb_n || (kfa && !nfb), "gemm: a combined operand needs A and B read k-fast");
   // The bf16 split pays off only where the matrix cores bound the product (the
   // long segmented builds); the other products of a split-precision run use
   // FP32, which is at least as accurate.
   const bool split = d.prec == RTCC3_PREC_BF16X3 || d.prec == RTCC3_PREC_BF16X2;
-  const int prec = split && d.nseg == 0 && !d.force_prec ? RTCC3_PREC_FP32 : d.prec;
+  const int prec = split && ((d.nseg == 0 && !d.force_prec) || d.comb_n) ? RTCC3_PREC_FP32 : d.prec;
   switch (prec) {
     case RTCC3_PREC_FP64:
       launch_mode<RTCC3_PREC_FP64>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);

@@ -330,7 +330,6 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, v}).p;
   cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, v}).p;
   cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, v}).p;
-  cplx* Z = e.tensor("tw_Z", {(int64_t)max_nw_, v, v, v}).p;
   cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
   auto P = [&](const char* name, std::vector<int64_t> shape) { return e.tensor(name, shape).p; };
   const cplx* gW1 = P("tb_W1", {o, v, v, v});
@@ -443,35 +442,53 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     cplx* R12 = P("tr_R12", {o, o, o, v});
     const int64_t lR = (int64_t)o * o * v * o;
 
-    // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ with Z1 = 2t[c,b,e] - t[c,e,b] - t[e,b,c]
-    launch_comb(T, Z, cbl, v, cn, 0, s);
-    {
+    // The combinations of X2 are read straight from the window: with
+    // t_{sigma(ijk)}^{sigma(abc)} = t_ijk^abc, for the block (I,J,K)
+    //   Z1[b][c][e] = 2t[c,b,e] - t[c,e,b] - t[e,b,c] = (2 T_IJK - T_IKJ - T_KJI)[c][b][e]
+    //   Zh[a][b][c] = 2t[c,b,a] - t[b,c,a] - t[a,b,c] = (2 T_KJI - T_KIJ - T_IJK)[a][b][c]
+    // (window orderings: 0 IJK, 1 JIK, 2 IKJ, 3 KJI, 4 KIJ, 5 JKI).
+    auto combine = [&](GemmDesc& g, int on, int p0, int p1, int p2) {
+      g.comb_n = 3;
+      g.comb_on = on;
+      g.part = w.d_part;
+      g.comb_perm[0] = p0;
+      g.comb_perm[1] = p1;
+      g.comb_perm[2] = p2;
+      g.comb_w[0] = 2.0;
+      g.comb_w[1] = -1.0;
+      g.comb_w[2] = -1.0;
+      g.comb_stride = v3;
+    };
+    {  // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ into X2p[I][J][a][b]
       GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
+      g.K0 = v;
       g.A = gX2a;
       g.sAm0 = v2;
+      g.sAk1 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, v3, 0);
-      g.B = Z;
+      g.B = T;  // B[(c,e)][b] = Z1[b][c][e]
+      g.sBk1 = v2;
       g.sBk0 = 1;
-      g.sBn0 = v2;
+      g.sBn0 = v;
       set4(g.cB, 0, 0, 0, v3);
+      combine(g, 1, 0, 2, 3);
       g.C = X2p;
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
       checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
     }
-    // X2: -sum_c Zh[(a,b)][c] (Ki|Ic)~ into X2p[x][J] with Zh = 2t[c,b,a] - t[b,c,a] - t[a,b,c]
-    launch_comb(T, Z, cbl, v, cn, 1, s);
-    {
+    {  // X2: -sum_c Zh[(a,b)][c] (Ki|Ic)~ into X2p[x][J]
       GemmDesc g = base((int)v2, o, v, cn, cbl, pr);
       g.atomic = 1;
       g.alpha = R(-1);
-      g.A = Z;
+      g.A = T;  // A[(a,b)][c] = Zh[a][b][c]
       g.sAm0 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, 0, v3);
+      combine(g, 0, 3, 4, 0);
       g.B = gX2b;
       g.sBk0 = 1;
       g.sBn0 = v;

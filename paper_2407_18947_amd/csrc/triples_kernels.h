@@ -20,7 +20,6 @@ struct LamElem {
 // every source element first.
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
                      int v, const LamElem* le, hipStream_t s);
-void launch_comb(const cplx* T, cplx* Z, const int* bl, int v, int nb, int mode, hipStream_t s);
 void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, const cplx* F, const cplx* l2, cplx* X1,
                      cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s);
 

@@ -17,27 +17,6 @@ __device__ __forceinline__ void catomic(cplx* p, cplx x) {
   unsafeAtomicAdd(&p->im, x.im);
 }
 
-// mode 0: Z[n][b][c][e] = 2 t[c,b,e] - t[c,e,b] - t[e,b,c]
-// mode 1: Z[n][a][b][c] = 2 t[c,b,a] - t[b,c,a] - t[a,b,c]
-__global__ void comb_kernel(const cplx* __restrict__ T, cplx* __restrict__ Z, const int* __restrict__ bl, int v,
-                            int mode) {
-  const int q = blockIdx.y;
-  const int64_t v3 = (int64_t)v * v * v;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= v3) return;
-  const int n = bl[4 * q + 3];
-  const int x = (int)(e / ((int64_t)v * v)), y = (int)((e / v) % v), z = (int)(e % v);
-  const cplx* t = T + (int64_t)n * v3;
-  auto at = [&](int i, int j, int k) { return t[((int64_t)i * v + j) * v + k]; };
-  cplx r;
-  if (mode == 0) {  // x=b, y=c, z=e
-    r = csub(csub(cscale(2.0, at(y, x, z)), at(y, z, x)), at(z, x, y));
-  } else {  // x=a, y=b, z=c
-    r = csub(csub(cscale(2.0, at(z, y, x)), at(y, z, x)), at(x, y, z));
-  }
-  Z[(int64_t)n * v3 + e] = r;
-}
-
 // Contractions with one free virtual index per block (I,J,K), all from one
 // coalesced sweep over t[x][y][z] (z fastest), slab by slab in x:
 //   flags&1: X1[I][a]      += sum_bc t[a,b,c] L[J,b,K,c]  - sum_bc t[c,b,a] L[J,b,K,c]
@@ -287,11 +266,6 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   }
 }
 
-inline dim3 blocks_v3(int v, int nb) {
-  const int64_t v3 = (int64_t)v * v * v;
-  return dim3((unsigned)((v3 + 255) / 256), (unsigned)nb);
-}
-
 }  // namespace
 
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
@@ -304,12 +278,6 @@ void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const
   } else {
     hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, LamElem{});
   }
-  RTCC3_HIP(hipGetLastError());
-}
-
-void launch_comb(const cplx* T, cplx* Z, const int* bl, int v, int nb, int mode, hipStream_t s) {
-  if (nb <= 0) return;
-  hipLaunchKernelGGL(comb_kernel, blocks_v3(v, nb), dim3(256), 0, s, T, Z, bl, v, mode);
   RTCC3_HIP(hipGetLastError());
 }
 

@@ -91,6 +91,14 @@ struct GemmDesc {
   int comb_perm[3];
   double comb_w[3];
   int64_t comb_stride;
+  // Gathered K (gk_start set, block table required): batch entry b sums over
+  // the blocks q = gk_bl[4p..4p+3], p in [gk_start[b], gk_start[b+1]), each
+  // a K0-long stretch of the contraction whose A and B start at A + cA.q and
+  // B + cB.q (the k strides are sAk0, sBk0); C starts at C + cC.bl[4b..4b+3].
+  // K is K0 times the largest count.  Entries thus reduce over blocks that
+  // share an output without atomics.
+  const int* gk_start;
+  const int* gk_bl;
 };
 void gemm(const GemmDesc& d, hipStream_t s);
 

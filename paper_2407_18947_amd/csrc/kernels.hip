@@ -59,7 +59,8 @@ __device__ __forceinline__ void split_k(int k, int K0, float inv, int& q, int& r
 // Every load is issued: an element outside the operand reads offset 0 of its
 // entry (the empty asm keeps the compiler from turning the address select
 // back into a branch around the load) and is then replaced by zero.
-// CMB = 1 / 2: operand A / B is a combination of three blocks (GemmDesc::comb_*).
+// CMB = 1 / 2: operand A / B is a combination of three blocks (GemmDesc::comb_*);
+// CMB = 3: gathered K (GemmDesc::gk_*).
 template <bool KFA, bool NFB, int BN, int BK, bool SEG, int CMB = 0>
 struct TileLoader {
   static constexpr int NEA = BM * BK / NT, NEB = BN * BK / NT;
@@ -74,6 +75,7 @@ struct TileLoader {
   const cplx* Bp[4];
   const cplx* Xc[3];  // bases of the combined operand's blocks
   double wc[3];
+  int gs;  // first gathered block of the entry
   int kend, sk1, sk2, sk3, m0, n0;
   float invK0;
   cplx av[NEA], bv[NEB];
@@ -102,7 +104,12 @@ struct TileLoader {
         A = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
         B = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
       }
-      if (CMB) {
+      if (CMB == 3) {
+        A = d.A;
+        B = d.B;
+        gs = d.gk_start[b];
+      }
+      if (CMB == 1 || CMB == 2) {
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
           Xc[s] = (CMB == 1 ? d.A : d.B) + (int64_t)d.part[6 * n + d.comb_perm[s]] * d.comb_stride;
@@ -162,6 +169,11 @@ struct TileLoader {
     const double im = wc[0] * x0.im + wc[1] * x1.im + wc[2] * x2.im;
     return cplx{ok ? re : 0.0, ok ? im : 0.0};
   }
+  // Offset of the q-th gathered block of the entry under coefficients c.
+  __device__ __forceinline__ int64_t gather_off(const int* gbl, const int64_t* c, int q) const {
+    const int* e = gbl + 4 * (gs + q);
+    return c[0] * e[0] + c[1] * e[1] + c[2] * e[2] + c[3] * e[3];
+  }
   __device__ __forceinline__ int segof(int k) const { return (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3); }
   template <typename X>
   static __device__ __forceinline__ X pick(int s, X x0, X x1, X x2, X x3) {
@@ -197,7 +209,8 @@ struct TileLoader {
       const int k = k0 + akk[s];
       int q, r;
       split_k(k, d.K0, invK0, q, r);
-      const int64_t ko = (int64_t)q * d.sAk1 + (int64_t)r * d.sAk0;
+      const int64_t ko = CMB == 3 ? gather_off(d.gk_bl, d.cA, k < kend ? q : 0) + (int64_t)r * d.sAk0
+                                  : (int64_t)q * d.sAk1 + (int64_t)r * d.sAk0;
 #pragma unroll
       for (int t = 0; t < NMA; ++t) {
         const int e = KFA ? t : s;
@@ -210,7 +223,8 @@ struct TileLoader {
       const int k = k0 + bkk[s];
       int q, r;
       split_k(k, d.K0, invK0, q, r);
-      const int64_t ko = (int64_t)q * d.sBk1 + (int64_t)r * d.sBk0;
+      const int64_t ko = CMB == 3 ? gather_off(d.gk_bl, d.cB, k < kend ? q : 0) + (int64_t)r * d.sBk0
+                                  : (int64_t)q * d.sBk1 + (int64_t)r * d.sBk0;
 #pragma unroll
       for (int t = 0; t < NNB; ++t) {
         const int e = NFB ? s : t;
@@ -269,7 +283,8 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
   if (b >= d.batch) return;
   const int kbeg = kz * kchunk;
-  const int kend = min(d.K, kbeg + kchunk);
+  const int Kb = CMB == 3 ? (d.gk_start[b + 1] - d.gk_start[b]) * d.K0 : d.K;  // this entry's contraction length
+  const int kend = min(Kb, kbeg + kchunk);
   if (kbeg >= kend) return;
 
   Loader ld;
@@ -654,9 +669,30 @@ void launch_comb_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, i
     hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
 }
 
+// Gathered-K products, FP64 or FP32, for the layouts they are used with.
+template <int MODE, bool ATOMIC>
+void launch_gather_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb,
+                        int bn) {
+  typedef typename std::conditional<MODE == RTCC3_PREC_FP64, double, float>::type T;
+  RTCC3_CHECK(!nfb, "gemm: no gathered-K kernel for this operand layout");
+  if (kfa) {
+    if (bn == 16)
+      hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, 16, false, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    else
+      hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, 64, false, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  } else {
+    if (bn == 16)
+      hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, false, 16, false, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    else
+      hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, false, false, 64, false, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  }
+}
+
 template <int MODE, bool ATOMIC>
 void launch_layout(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb, int bn) {
-  if (d.comb_n > 0) {
+  if (d.gk_start) {
+    if (MODE == RTCC3_PREC_FP64 || MODE == RTCC3_PREC_FP32) launch_gather_gemm<MODE, ATOMIC>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
+  } else if (d.comb_n > 0) {
     if (MODE == RTCC3_PREC_FP64 || MODE == RTCC3_PREC_FP32) {
       if (bn == 16)
         launch_comb_gemm<MODE, ATOMIC, 16>(d, grid, s, ksplit, kchunk);
@@ -734,6 +770,11 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
     RTCC3_CHECK(d0.comb_n == 3 && d0.bl && d0.part && d0.nseg == 0 && (d0.comb_on == 0 || d0.comb_on == 1),
                 "gemm: bad combined operand");
   }
+  if (d0.gk_start) {
+    RTCC3_CHECK(d0.gk_bl && d0.bl && d0.nseg == 0 && d0.comb_n == 0 && d0.K % d0.K0 == 0 && d0.sAk1 == 0 &&
+                    d0.sBk1 == 0,
+                "gemm: bad gathered K");
+  }
   if (d0.nseg > 0) {
     RTCC3_CHECK(d0.nseg <= 4 && d0.bl && d0.seg[0].k0 == 0 && d0.M0 == d0.M && d0.N0 == d0.N,
                 "gemm: bad K segments");
@@ -746,7 +787,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   RTCC3_CHECK(!d0.store || !d0.atomic, "gemm: store mode cannot be atomic");
   // A narrow side (at most 16, e.g. one occupied index) goes on N with 64x16
   // tiles; a narrow M is moved there by transposing the product.
-  const bool tr = d0.M <= 16 && d0.N > 16 && d0.nseg == 0;
+  const bool tr = d0.M <= 16 && d0.N > 16 && d0.nseg == 0 && !d0.gk_start;
   const GemmDesc d = tr ? transposed(d0) : d0;
   const int bn = d.N <= 16 && d.nseg == 0 ? 16 : 64;  // the segmented kernel has 64-wide tiles
   const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + bn - 1) / bn);
@@ -775,7 +816,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   // long segmented builds); the other products of a split-precision run use
   // FP32, which is at least as accurate.
   const bool split = d.prec == RTCC3_PREC_BF16X3 || d.prec == RTCC3_PREC_BF16X2;
-  const int prec = split && ((d.nseg == 0 && !d.force_prec) || d.comb_n) ? RTCC3_PREC_FP32 : d.prec;
+  const int prec = split && ((d.nseg == 0 && !d.force_prec) || d.comb_n || d.gk_start) ? RTCC3_PREC_FP32 : d.prec;
   switch (prec) {
     case RTCC3_PREC_FP64:
       launch_mode<RTCC3_PREC_FP64>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);

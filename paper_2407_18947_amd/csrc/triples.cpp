@@ -79,6 +79,32 @@ void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t l
   gemm(g, s);
 }
 
+// A gathered-K product (GemmDesc::gk_*) over a window's J groups after the
+// same check for every gathered block and every group's output.
+void checked_gather_gemm(GemmDesc& g, const Window& w, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
+  const int ng = (int)w.gkey.size() / 4;
+  if (ng == 0) return;
+  g.batch = ng;
+  g.bl = w.d_gkey;
+  g.gk_start = w.d_gstart;
+  g.gk_bl = w.d_gbl;
+  RTCC3_CHECK(g.K == g.K0 * w.gmax && g.sAk1 == 0 && g.sBk1 == 0, "triples: bad gathered product");
+  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + (int64_t)(g.K0 - 1) * g.sAk0;
+  const int64_t eB = (int64_t)(g.K0 - 1) * g.sBk0 + span(g.N, g.N0, g.sBn1, g.sBn0);
+  const int64_t eC = span(g.M, g.M0, g.sCm1, g.sCm0) + span(g.N, g.N0, g.sCn1, g.sCn0);
+  auto dot = [](const int64_t* c, const int* q) { return c[0] * q[0] + c[1] * q[1] + c[2] * q[2] + c[3] * q[3]; };
+  for (int b = 0; b < ng; ++b) {
+    const int64_t oC = dot(g.cC, &w.gkey[4 * b]);
+    RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
+    for (int p = w.gstart[b]; p < w.gstart[b + 1]; ++p) {
+      const int64_t oA = dot(g.cA, &w.gbl[4 * p]), oB = dot(g.cB, &w.gbl[4 * p]);
+      RTCC3_CHECK(oA >= 0 && oA + eA < lenA, "triples: A operand out of bounds");
+      RTCC3_CHECK(oB >= 0 && oB + eB < lenB, "triples: B operand out of bounds");
+    }
+  }
+  gemm(g, s);
+}
+
 // A K-segmented product (GemmDesc::seg) after the same check per segment;
 // lenA[s], lenB[s]: lengths of segment s's operand tensors.
 void checked_seg_gemm(const GemmDesc& g, const int* bl_host, const int64_t* lenA, const int64_t* lenB, int64_t lenC,
@@ -131,6 +157,9 @@ Triples::~Triples() {
       if (w.d_owned) (void)hipFree(w.d_owned);
       if (w.d_canon) (void)hipFree(w.d_canon);
       if (w.d_slabs) (void)hipFree(w.d_slabs);
+      if (w.d_gkey) (void)hipFree(w.d_gkey);
+      if (w.d_gstart) (void)hipFree(w.d_gstart);
+      if (w.d_gbl) (void)hipFree(w.d_gbl);
     }
   if (eps_) (void)hipFree(eps_);
   if (t0_) (void)hipEventDestroy(t0_);
@@ -253,6 +282,28 @@ void Triples::build_windows() {
 }
 
 void Triples::upload(Window& w) {
+  {  // group the contraction blocks by J
+    const std::vector<int>& cb = w.owned.empty() ? w.bl : w.owned;
+    std::map<int, std::vector<int>> by;
+    for (size_t e = 0; e < cb.size(); e += 4) by[cb[e + 1]].push_back((int)e);
+    w.gkey.clear();
+    w.gstart.assign(1, 0);
+    w.gbl.clear();
+    w.gmax = 0;
+    for (auto& kv : by) {
+      w.gkey.insert(w.gkey.end(), {0, kv.first, 0, 0});
+      for (int e : kv.second) w.gbl.insert(w.gbl.end(), cb.begin() + e, cb.begin() + e + 4);
+      w.gstart.push_back((int)w.gbl.size() / 4);
+      w.gmax = std::max(w.gmax, (int)kv.second.size());
+    }
+    auto put = [](int** d, const std::vector<int>& h) {
+      RTCC3_HIP(hipMalloc(d, sizeof(int) * h.size()));
+      RTCC3_HIP(hipMemcpy(*d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
+    };
+    put(&w.d_gkey, w.gkey);
+    put(&w.d_gstart, w.gstart);
+    put(&w.d_gbl, w.gbl);
+  }
   RTCC3_HIP(hipMalloc(&w.d_bl, sizeof(int) * w.bl.size()));
   RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
   RTCC3_HIP(hipMalloc(&w.d_part, sizeof(int) * w.part.size()));
@@ -521,9 +572,9 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
       checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
     }
-    {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J]
-      GemmDesc g = base((int)v2, o, v, cn, cbl, pr);
-      g.atomic = 1;
+    {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J], summed over the blocks of each J
+      GemmDesc g = base((int)v2, o, v * w.gmax, 0, nullptr, pr);
+      g.K0 = v;
       g.alpha = R(-1);
       g.A = L;
       g.sAm0 = v;
@@ -537,7 +588,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
-      checked_gemm(g, cblh, winlen, lOOOV, oovv, s);
+      checked_gather_gemm(g, w, winlen, lOOOV, oovv, s);
     }
     // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates over (b,x)
     auto tl = [&](const cplx* Bp, int64_t lenB, int64_t sbk, int64_t sbn, const int64_t* cb, cplx* Cp,
@@ -629,9 +680,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       h.sCn0 = 1;
       checked_gemm(h, cblh, lS, winlen, ov, s);
     }
-    {  // term 11: Zi[J][(d,e)][b] += sum_c lambda[c][(d,e)] t2[K][I][b][c]   (block (k,i,j) = (I,J,K))
-      GemmDesc g = base((int)v2, v, v, cn, cbl, pr);
-      g.atomic = 1;
+    {  // term 11: Zi[J][(d,e)][b] += sum_c lambda[c][(d,e)] t2[K][I][b][c]   (block (k,i,j) = (I,J,K)),
+       // summed over the blocks of each J
+      GemmDesc g = base((int)v2, v, v * w.gmax, 0, nullptr, pr);
+      g.K0 = v;
       g.A = L;
       g.sAm0 = 1;
       g.sAk0 = v2;
@@ -644,7 +696,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
-      checked_gemm(g, cblh, winlen, t2len, lOVVV, s);
+      checked_gather_gemm(g, w, winlen, t2len, lOVVV, s);
     }
     {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
       GemmDesc g = base(o, v, (int)v2, cn, cbl, pr);

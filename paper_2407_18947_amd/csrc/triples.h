@@ -23,6 +23,15 @@ struct Window {
   std::vector<int> canon;     // [*][4]: I <= J <= K and the slot of that ordering, one per distinct triple
   std::vector<int> slabs;     // density windows: [*][4] = (0, 0, 0, slot of block (0,l,k)); the o blocks
                               // (i,l,k) of a slab occupy consecutive slots in i
+  // The blocks the right-hand-side contractions run over (all blocks, or the
+  // owned ones of a pair window) grouped by their second index J:
+  std::vector<int> gkey;    // [ng][4]: (0, J, 0, 0)
+  std::vector<int> gstart;  // [ng + 1]: group g is gbl entries [gstart[g], gstart[g+1])
+  std::vector<int> gbl;     // [*][4]: (I, J, K, n) in group order
+  int gmax = 0;             // largest group
+  int* d_gkey = nullptr;
+  int* d_gstart = nullptr;
+  int* d_gbl = nullptr;
   int* d_bl = nullptr;
   int* d_part = nullptr;
   int* d_owned = nullptr;

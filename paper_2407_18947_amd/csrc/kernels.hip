@@ -13,6 +13,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 64, NT = 256;
+constexpr int GK_MAXSEG = 256;  // gathered blocks one workgroup's K range may touch
 
 template <typename T>
 struct Frag;
@@ -75,7 +76,9 @@ struct TileLoader {
   const cplx* Bp[4];
   const cplx* Xc[3];  // bases of the combined operand's blocks
   double wc[3];
-  int gs;  // first gathered block of the entry
+  int gs;                // first gathered block of the entry
+  int gq0;               // first gathered block of this workgroup's K range
+  const int64_t* gofs;   // LDS: A and B offsets of the gathered blocks from gq0 on
   int kend, sk1, sk2, sk3, m0, n0;
   float invK0;
   cplx av[NEA], bv[NEB];
@@ -169,11 +172,8 @@ struct TileLoader {
     const double im = wc[0] * x0.im + wc[1] * x1.im + wc[2] * x2.im;
     return cplx{ok ? re : 0.0, ok ? im : 0.0};
   }
-  // Offset of the q-th gathered block of the entry under coefficients c.
-  __device__ __forceinline__ int64_t gather_off(const int* gbl, const int64_t* c, int q) const {
-    const int* e = gbl + 4 * (gs + q);
-    return c[0] * e[0] + c[1] * e[1] + c[2] * e[2] + c[3] * e[3];
-  }
+  // Offset of the q-th gathered block of the entry in operand x (0 = A, 1 = B).
+  __device__ __forceinline__ int64_t gather_off(int x, int q) const { return gofs[2 * (q - gq0) + x]; }
   __device__ __forceinline__ int segof(int k) const { return (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3); }
   template <typename X>
   static __device__ __forceinline__ X pick(int s, X x0, X x1, X x2, X x3) {
@@ -209,7 +209,7 @@ struct TileLoader {
       const int k = k0 + akk[s];
       int q, r;
       split_k(k, d.K0, invK0, q, r);
-      const int64_t ko = CMB == 3 ? gather_off(d.gk_bl, d.cA, k < kend ? q : 0) + (int64_t)r * d.sAk0
+      const int64_t ko = CMB == 3 ? gather_off(0, k < kend ? q : gq0) + (int64_t)r * d.sAk0
                                   : (int64_t)q * d.sAk1 + (int64_t)r * d.sAk0;
 #pragma unroll
       for (int t = 0; t < NMA; ++t) {
@@ -223,7 +223,7 @@ struct TileLoader {
       const int k = k0 + bkk[s];
       int q, r;
       split_k(k, d.K0, invK0, q, r);
-      const int64_t ko = CMB == 3 ? gather_off(d.gk_bl, d.cB, k < kend ? q : 0) + (int64_t)r * d.sBk0
+      const int64_t ko = CMB == 3 ? gather_off(1, k < kend ? q : gq0) + (int64_t)r * d.sBk0
                                   : (int64_t)q * d.sBk1 + (int64_t)r * d.sBk0;
 #pragma unroll
       for (int t = 0; t < NNB; ++t) {
@@ -292,6 +292,19 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+  if (CMB == 3) {
+    // operand offsets of the gathered blocks this workgroup's K range touches
+    __shared__ int64_t gofs[2 * GK_MAXSEG];
+    const int q0 = kbeg / d.K0, q1 = (kend - 1) / d.K0;
+    for (int q = q0 + tid; q <= q1; q += NT) {
+      const int* e = d.gk_bl + 4 * (ld.gs + q);
+      gofs[2 * (q - q0)] = d.cA[0] * e[0] + d.cA[1] * e[1] + d.cA[2] * e[2] + d.cA[3] * e[3];
+      gofs[2 * (q - q0) + 1] = d.cB[0] * e[0] + d.cB[1] * e[1] + d.cB[2] * e[2] + d.cB[3] * e[3];
+    }
+    ld.gq0 = q0;
+    ld.gofs = gofs;
+    __syncthreads();
+  }
 
   auto stash = [&](int buf) {
 #pragma unroll
@@ -674,6 +687,13 @@ template <int MODE, bool ATOMIC>
 void launch_gather_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb,
                         int bn) {
   typedef typename std::conditional<MODE == RTCC3_PREC_FP64, double, float>::type T;
+  if (kfa && nfb) {
+    if (bn == 16)
+      hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, 16, false, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    else
+      hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, true, 64, false, 3>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    return;
+  }
   RTCC3_CHECK(!nfb, "gemm: no gathered-K kernel for this operand layout");
   if (kfa) {
     if (bn == 16)
@@ -796,13 +816,20 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   int ksplit = 1;
   const int64_t wgs = tiles * d.batch;
   constexpr int BKMAX = 32;  // K chunks are multiples of every kernel's K step
-  if (!d.store && wgs < 512 && d.K >= 4 * BKMAX) {
-    const int64_t want = (1024 + wgs - 1) / wgs;
+  // A gathered product has few entries with long K: aim at a fuller chip.
+  const int64_t below = d.gk_start ? 2048 : 512, target = d.gk_start ? 2048 : 1024;
+  if (!d.store && wgs < below && d.K >= 4 * BKMAX) {
+    const int64_t want = (target + wgs - 1) / wgs;
     const int64_t maxs = d.K / (2 * BKMAX);
     ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
   }
+  if (d.gk_start) {  // a workgroup's K range spans at most GK_MAXSEG - 4 gathered blocks
+    const int64_t span_k = (int64_t)(GK_MAXSEG - 4) * d.K0 / BKMAX * BKMAX;
+    ksplit = (int)std::max<int64_t>(ksplit, (d.K + span_k - 1) / span_k);
+  }
   const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BKMAX - 1) / BKMAX * BKMAX);
   RTCC3_CHECK(tiles * ksplit < (1LL << 31), "gemm: too many tiles");
+  RTCC3_CHECK(!d.gk_start || kchunk / d.K0 + 2 <= GK_MAXSEG, "gemm: gathered K range too long for one workgroup");
   int64_t by = d.batch, bz = 1;
   while (by > 65535) {
     by = (by + 1) / 2;

@@ -680,23 +680,23 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       h.sCn0 = 1;
       checked_gemm(h, cblh, lS, winlen, ov, s);
     }
-    {  // term 11: Zi[J][(d,e)][b] += sum_c lambda[c][(d,e)] t2[K][I][b][c]   (block (k,i,j) = (I,J,K)),
+    {  // term 11: Zi[J][b][(d,e)] += sum_c t2[K][I][b][c] lambda[c][(d,e)]   (block (k,i,j) = (I,J,K)),
        // summed over the blocks of each J
-      GemmDesc g = base((int)v2, v, v * w.gmax, 0, nullptr, pr);
+      GemmDesc g = base(v, (int)v2, v * w.gmax, 0, nullptr, pr);
       g.K0 = v;
-      g.A = L;
-      g.sAm0 = 1;
-      g.sAk0 = v2;
-      set4(g.cA, 0, 0, 0, v3);
-      g.B = t2;
-      g.sBk0 = 1;
-      g.sBn0 = v;
-      set4(g.cB, v2, 0, (int64_t)o * v2, 0);
+      g.A = t2;
+      g.sAm0 = v;
+      g.sAk0 = 1;
+      set4(g.cA, v2, 0, (int64_t)o * v2, 0);
+      g.B = L;
+      g.sBk0 = v2;
+      g.sBn0 = 1;
+      set4(g.cB, 0, 0, 0, v3);
       g.C = Zi;
-      g.sCm0 = v;
+      g.sCm0 = v2;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
-      checked_gather_gemm(g, w, winlen, t2len, lOVVV, s);
+      checked_gather_gemm(g, w, t2len, winlen, lOVVV, s);
     }
     {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
       GemmDesc g = base(o, v, (int)v2, cn, cbl, pr);
@@ -835,7 +835,7 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   e.einsum("xajb,jb->xa", ONE, Lov, e.tensor("tr_Z34", {o, v}), Y1);
   e.einsum("lidj,jlda->ia", R(-1), e.tensor("tr_R8", {o, o, v, o}), g_oovv, Y1);
   e.einsum("ildj,dlja->ia", R(-1), e.tensor("tr_R8", {o, o, v, o}), g_voov, Y1);
-  e.einsum("ideb,daeb->ia", ONE, e.tensor("tr_Zi", {o, v, v, v}), g_vvvv, Y1);
+  e.einsum("ibde,daeb->ia", ONE, e.tensor("tr_Zi", {o, v, v, v}), g_vvvv, Y1);
   e.einsum("xljm,ljma->xa", ONE, g_oooo, e.tensor("tr_R12", {o, o, o, v}), Y1);
 
   TriplesOut out;

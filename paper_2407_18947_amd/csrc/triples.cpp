@@ -360,10 +360,10 @@ void Triples::blocks(Engine& e, const CCSDResult& r) {
   t = make("tb_G5", {o, o, v, v});  // L_jbxc = 2(jb|xc) - (jc|xb) at [j][x][b][c]
   e.einsum("Pjb,Pxc->jxbc", R(2), B('o', 'v'), B('o', 'v'), t);
   e.einsum("Pjc,Pxb->jxbc", R(-1), B('o', 'v'), B('o', 'v'), t);
-  t = make("tb_G9", {o, o, v, v});  // (xl|db) at [l][x][d][b]
-  e.einsum("Pxl,Pdb->lxdb", ONE, B('o', 'o'), B('v', 'v'), t);
-  t = make("tb_G10", {o, o, v, v});  // (dl|xb) at [l][x][d][b]
-  e.einsum("Pdl,Pxb->lxdb", ONE, B('v', 'o'), B('o', 'v'), t);
+  t = make("tb_G9", {o, v, v, o});  // (xl|db) at [l][b][d][x]
+  e.einsum("Pxl,Pdb->lbdx", ONE, B('o', 'o'), B('v', 'v'), t);
+  t = make("tb_G10", {o, v, v, o});  // (dl|xb) at [l][b][d][x]
+  e.einsum("Pdl,Pxb->lbdx", ONE, B('v', 'o'), B('o', 'v'), t);
 }
 
 void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_terms, bool density_terms) {
@@ -395,8 +395,8 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const cplx* gY2b = P("tb_Y2b", {o, o, o, v});
   const cplx* gG1 = P("tb_G1", {o, o, v, v});
   const cplx* gG5 = P("tb_G5", {o, o, v, v});
-  const cplx* gG9 = P("tb_G9", {o, o, v, v});
-  const cplx* gG10 = P("tb_G10", {o, o, v, v});
+  const cplx* gG9 = P("tb_G9", {o, v, v, o});
+  const cplx* gG10 = P("tb_G10", {o, v, v, o});
   const cplx* Lov = P("Lov", {o, v, o, v});
   const cplx* F = P("F", {(int64_t)d_.n, (int64_t)d_.n});
   const int64_t lOVVV = (int64_t)o * v3, lOOOV = (int64_t)o * o * o * v, lOOVV = oovv;
@@ -639,30 +639,21 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, (int64_t)o * v * o, 0, (int64_t)v * o, 0);
       checked_gemm(g, cblh, winlen, t2len, lR, s);
     }
-    {  // terms 9, 10: S[n][c][d][x] = sum_b t2[K][J][b][c] (xI|db)~ + sum_b t2[I][J][b][c] (dK|xb)~
-      fill(S, (int64_t)nw * v2 * o, cplx{0, 0}, s);
-      GemmDesc g = base(v, (int)(o * v), v, cn, cbl, pr);
-      g.N0 = v;
-      g.A = t2;
-      g.sAm0 = 1;
-      g.sAk0 = v;
-      set4(g.cA, 0, v2, (int64_t)o * v2, 0);
-      g.B = gG9;
-      g.sBk0 = 1;
-      g.sBn1 = v2;
-      g.sBn0 = v;
-      set4(g.cB, (int64_t)o * v2, 0, 0, 0);
+    {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
+       //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
+      GemmDesc g = base(v, (int)(o * v), 2 * v, cn, cbl, pr);
+      g.store = 1;
+      g.nseg = 2;
+      const int64_t ov2 = (int64_t)o * v2, v2o = v2 * o;
+      seg(g.seg[0], 0, t2, {0, ov2, v2, 0}, v, 1, gG9, {v2o, 0, 0, 0}, (int64_t)v * o);
+      seg(g.seg[1], v, t2, {v2, ov2, 0, 0}, v, 1, gG10, {0, 0, v2o, 0}, (int64_t)v * o);
       g.C = S;
       g.sCm0 = (int64_t)v * o;
-      g.sCn1 = 1;
-      g.sCn0 = o;
-      set4(g.cC, 0, 0, 0, v2 * o);
+      g.sCn0 = 1;
+      set4(g.cC, 0, 0, 0, v2o);
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
-      checked_gemm(g, cblh, t2len, lOOVV, lS, s);
-      set4(g.cA, (int64_t)o * v2, v2, 0, 0);
-      g.B = gG10;
-      set4(g.cB, 0, 0, (int64_t)o * v2, 0);
-      checked_gemm(g, cblh, t2len, lOOVV, lS, s);
+      const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
+      checked_seg_gemm(g, cblh, lA, lB, lS, s);
       // Y1[x][a] -= sum_(c,d) S[n][(c,d)][x] lambda[n][a][(c,d)] for every block of the table
       GemmDesc h = base(o, v, (int)v2, cn, cbl, pr);
       h.atomic = 1;

@@ -146,6 +146,10 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
   build_windows();
   for (auto& w : rhs_windows_) upload(w);
   for (auto& w : den_windows_) upload(w);
+  RTCC3_HIP(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
+  RTCC3_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+  RTCC3_HIP(hipEventCreateWithFlags(&ev_l_, hipEventDisableTiming));
+  RTCC3_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
   (void)e;
 }
 
@@ -162,6 +166,10 @@ Triples::~Triples() {
       if (w.d_gbl) (void)hipFree(w.d_gbl);
     }
   if (eps_) (void)hipFree(eps_);
+  if (s2_) (void)hipStreamSynchronize(s2_);
+  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_})
+    if (ev) (void)hipEventDestroy(ev);
+  if (s2_) (void)hipStreamDestroy(s2_);
   if (t0_) (void)hipEventDestroy(t0_);
   if (t1_) (void)hipEventDestroy(t1_);
   for (hipEvent_t ev : bev_) (void)hipEventDestroy(ev);
@@ -371,7 +379,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int64_t v2 = (int64_t)v * v, v3 = v2 * v, ov = (int64_t)o * v, oovv = (int64_t)o * o * v2;
   const int64_t ylen = 2 * (ov + oovv);
   const int nw = w.nw;
-  hipStream_t s = e.stream;
+  hipStream_t s = e.stream;  // t3 side
+  hipStream_t s2 = s2_;      // lambda3 side
+  RTCC3_HIP(hipEventRecord(ev_fork_, s));
+  RTCC3_HIP(hipStreamWaitEvent(s2, ev_fork_, 0));
   const cplx* t2 = y + ov;
   const cplx* l1 = y + ov + oovv;
   const cplx* l2 = y + 2 * ov + oovv;
@@ -379,6 +390,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   (void)ylen;
   const int64_t winlen = (int64_t)max_nw_ * v3;
   cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, v}).p;
+  cplx* Wl = e.tensor("tw_Wl", {(int64_t)max_nw_, v, v, v}).p;
   cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, v}).p;
   cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, v}).p;
   cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
@@ -456,21 +468,22 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     seg(g.seg[1], o, gLD, {(int64_t)v * oo, o, 0, 0}, oo, 1, l2, {0, 0, v2, 0}, ov2);
     seg(g.seg[2], 2 * o, l2, {0, ov2, v2, 0}, v, 1, gLA, {v3, 0, 0, 0}, v2);
     seg(g.seg[3], 2 * o + v, l2, {ov2, v2, 0, 0}, v, 1, gLB, {0, 0, v3, 0}, v2);
-    g.C = W;
+    g.C = Wl;
     g.sCm0 = v2;
     g.sCn0 = 1;
     set4(g.cC, 0, 0, 0, v3);
     const int64_t lLC = (int64_t)o * v * o * o;
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
-    build_event(s);
-    checked_seg_gemm(g, blh, lA, lB, winlen, s);
-    build_event(s);
+    build_event(s2);
+    checked_seg_gemm(g, blh, lA, lB, winlen, s2);
+    build_event(s2);
     build_flop_ += 8.0 * nw * v * v2 * (2 * o + 2 * v);
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
-    launch_sym_cube(W, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, &le, s);
+    launch_sym_cube(Wl, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, &le, s2);
   }
+  RTCC3_HIP(hipEventRecord(ev_l_, s2));  // lambda3 blocks ready
   launches_ += 4;
 
   if (rhs_terms) {
@@ -570,7 +583,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
-      checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
+      checked_gemm(g, cblh, lOVVV, winlen, oovv, s2);
     }
     {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J], summed over the blocks of each J
       GemmDesc g = base((int)v2, o, v * w.gmax, 0, nullptr, pr);
@@ -588,7 +601,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
-      checked_gather_gemm(g, w, winlen, lOOOV, oovv, s);
+      checked_gather_gemm(g, w, winlen, lOOOV, oovv, s2);
     }
     // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates over (b,x)
     auto tl = [&](const cplx* Bp, int64_t lenB, int64_t sbk, int64_t sbn, const int64_t* cb, cplx* Cp,
@@ -637,7 +650,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = o;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v * o, 0, (int64_t)v * o, 0);
-      checked_gemm(g, cblh, winlen, t2len, lR, s);
+      checked_gemm(g, cblh, winlen, t2len, lR, s2);
     }
     {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
        //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
@@ -653,7 +666,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, 0, 0, 0, v2o);
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
       const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
-      checked_seg_gemm(g, cblh, lA, lB, lS, s);
+      checked_seg_gemm(g, cblh, lA, lB, lS, s2);
       // Y1[x][a] -= sum_(c,d) S[n][(c,d)][x] lambda[n][a][(c,d)] for every block of the table
       GemmDesc h = base(o, v, (int)v2, cn, cbl, pr);
       h.atomic = 1;
@@ -669,7 +682,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       h.C = Y1;
       h.sCm0 = v;
       h.sCn0 = 1;
-      checked_gemm(h, cblh, lS, winlen, ov, s);
+      checked_gemm(h, cblh, lS, winlen, ov, s2);
     }
     {  // term 11: Zi[J][b][(d,e)] += sum_c t2[K][I][b][c] lambda[c][(d,e)]   (block (k,i,j) = (I,J,K)),
        // summed over the blocks of each J
@@ -687,7 +700,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v2;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
-      checked_gather_gemm(g, w, t2len, winlen, lOVVV, s);
+      checked_gather_gemm(g, w, t2len, winlen, lOVVV, s2);
     }
     {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
       GemmDesc g = base(o, v, (int)v2, cn, cbl, pr);
@@ -704,11 +717,13 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = (int64_t)o * v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * o * v, v, 0, 0);
-      checked_gemm(g, cblh, t2len, winlen, (int64_t)o * o * o * v, s);
+      checked_gemm(g, cblh, t2len, winlen, (int64_t)o * o * o * v, s2);
     }
     launches_ += 18;
   }
 
+  // the density terms read t3 and lambda3: join the lambda3 side's blocks
+  if (density_terms) RTCC3_HIP(hipStreamWaitEvent(s, ev_l_, 0));
   if (density_terms && !w.owned.empty()) {
     const int no = (int)w.owned.size() / 4;
     cplx* Dab = P("td_Dab", {v, v});
@@ -771,6 +786,9 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     g.sCn0 = 1;
     checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s);
   }
+  // the next window reuses every window buffer: join the lambda3 side
+  RTCC3_HIP(hipEventRecord(ev_join_, s2));
+  RTCC3_HIP(hipStreamWaitEvent(s, ev_join_, 0));
 }
 
 void Triples::build_event(hipStream_t s) {

@@ -80,6 +80,11 @@ class Triples {
   double build_ms_ = 0, build_flop_ = 0;
   long build_launches_ = 0;
   std::vector<hipEvent_t> bev_;  // event pairs around the build products of one run
+  // A window's lambda3 side (build, symmetrisation, the contractions that read
+  // lambda3 only) runs on a second stream beside the t3 side; ev_fork_ /
+  // ev_l_ / ev_join_ order the two.
+  hipStream_t s2_ = nullptr;
+  hipEvent_t ev_fork_ = nullptr, ev_l_ = nullptr, ev_join_ = nullptr;
   int nbev_ = 0;                 // pairs recorded in the current run
   void build_event(hipStream_t s);
 

@@ -273,8 +273,11 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
   constexpr int IB = WM / 16, JB = WN / 16;                         // MFMA blocks per wave
   typedef TileLoader<KFA, NFB, BN, BK, SEG, CMB> Loader;
-  __shared__ T sA[2][2][BK][BM + 1];  // [buffer][re, im][k][m]
-  __shared__ T sB[2][2][BK][BN + 1];  // [buffer][re, im][k][n]
+  // Segmented products keep one LDS buffer (two barriers per K step) so that
+  // three workgroups fit on a CU; the others double-buffer.
+  constexpr int NBUF = SEG ? 1 : 2;
+  __shared__ T sA[NBUF][2][BK][BM + 1];  // [buffer][re, im][k][m]
+  __shared__ T sB[NBUF][2][BK][BN + 1];  // [buffer][re, im][k][n]
 
   const int tilesN = (d.N + BN - 1) / BN;
   const int kz = blockIdx.x % ksplit;
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
   // The last step also loads and stores a (fully masked) next tile: the loop
   // body then has no branch, and the buffer it overwrites is no longer read.
   for (int it = 0; it < nsteps; ++it) {
-    const int cur = it & 1;
+    const int cur = NBUF == 2 ? it & 1 : 0;
     ld.load(d, kbeg + (it + 1) * BK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
@@ -370,7 +373,8 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
 #pragma unroll
         for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
     }
-    stash(cur ^ 1);
+    if (NBUF == 1) __syncthreads();  // every wave is done with the buffer
+    stash(NBUF == 2 ? cur ^ 1 : 0);
     __syncthreads();
   }
 

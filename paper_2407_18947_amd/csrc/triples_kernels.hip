@@ -72,11 +72,13 @@ __global__ void small_t3_simple_kernel(const cplx* __restrict__ T, const int* __
   }
 }
 
-// One workgroup of SW_NW waves per block; lane = z (unit stride), wave w owns
-// the rows y = w, w+SW_NW, ... (v <= 64).  Sums over z are wave reductions,
-// sums over x stay in registers, sums over y go through LDS once at the end.
+// One workgroup of SW_NW waves per block and chunk of x (blockIdx.y); lane = z
+// (unit stride), wave w owns the rows y = w, w+SW_NW, ... (v <= 64).  Sums
+// over z are wave reductions, sums over x stay in registers (a chunk's
+// partial sums are added atomically), sums over y go through LDS at the end.
 constexpr int SW_NW = 8;
 constexpr int SW_MAXY = 8;
+constexpr int SW_XCHUNK = 16;  // x values per workgroup
 
 __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* __restrict__ T, const int* __restrict__ bl,
                                                               const cplx* __restrict__ Lov, const cplx* __restrict__ F,
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
   __shared__ cplx sx[2][SW_NW][64];  // per-wave partials of X1a[x], Za[x]
   __shared__ cplx sz[SW_NW][64];     // per-wave partials of X1b[z]
   const int q = blockIdx.x;
+  const int xb = blockIdx.y * SW_XCHUNK, xe = min(v, xb + SW_XCHUNK);  // this workgroup's x
   const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
   const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
   const int nn = o + v;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
   }
   cplx a4{0, 0};
   const cplx fz = zin ? fK[z] : cplx{0, 0};
-  for (int x = 0; x < v; ++x) {
+  for (int x = xb; x < xe; ++x) {
     const cplx fx = fK[x];
     const cplx* tx = t + (int64_t)x * v2;
     cplx p1{0, 0}, p2{0, 0};
@@ -166,14 +169,17 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
   __syncthreads();
   if (threadIdx.x < v) {
     const int a = threadIdx.x;
+    const bool own = a >= xb && a < xe;  // X1a[a] and Za[a] belong to this chunk
     cplx s1{0, 0}, s2{0, 0}, s4{0, 0};
     for (int ww = 0; ww < SW_NW; ++ww) {
-      s1 = cadd(s1, sx[0][ww][a]);
-      s2 = cadd(s2, sx[1][ww][a]);
+      if (own) {
+        s1 = cadd(s1, sx[0][ww][a]);
+        s2 = cadd(s2, sx[1][ww][a]);
+      }
       s4 = cadd(s4, sz[ww][a]);
     }
     if (doX) catomic(&X1[(int64_t)I * v + a], csub(s1, s4));
-    if (doZ) catomic(&Z[(int64_t)I * v + a], s2);
+    if (doZ && own) catomic(&Z[(int64_t)I * v + a], s2);
   }
 }
 
@@ -285,8 +291,9 @@ void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, cons
                      cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s) {
   if (nb <= 0) return;
   if (v <= 64) {
-    hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p, Z, o,
-                       v, flags);
+    const unsigned nxc = (unsigned)((v + SW_XCHUNK - 1) / SW_XCHUNK);
+    hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb, nxc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p,
+                       Z, o, v, flags);
   } else {
     hipLaunchKernelGGL(small_t3_simple_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1,
                        X2p, Z, o, v, flags);

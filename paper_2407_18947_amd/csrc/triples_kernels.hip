@@ -72,114 +72,114 @@ __global__ void small_t3_simple_kernel(const cplx* __restrict__ T, const int* __
   }
 }
 
-// One workgroup of SW_NW waves per block and chunk of x (blockIdx.y); lane = z
-// (unit stride), wave w owns the rows y = w, w+SW_NW, ... (v <= 64).  Sums
-// over z are wave reductions, sums over x stay in registers (a chunk's
-// partial sums are added atomically), sums over y go through LDS at the end.
+// Sum of eight values over the 64 lanes of a wave: on return lane l holds in
+// v[0] the total of v[l >> 3] (reduce-scatter by halving, then the last three
+// lane bits), ten complex exchanges instead of eight full reductions.
+__device__ __forceinline__ void wave_sum8(cplx* v, int lane) {
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  auto xch = [](cplx x, int m) { return cplx{__shfl_xor(x.re, m), __shfl_xor(x.im, m)}; };
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const cplx mine = h5 ? v[4 + j] : v[j], other = h5 ? v[j] : v[4 + j];
+    v[j] = cadd(mine, xch(other, 32));
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const cplx mine = h4 ? v[2 + j] : v[j], other = h4 ? v[j] : v[2 + j];
+    v[j] = cadd(mine, xch(other, 16));
+  }
+  {
+    const cplx mine = h3 ? v[1] : v[0], other = h3 ? v[0] : v[1];
+    v[0] = cadd(mine, xch(other, 8));
+  }
+  v[0] = cadd(v[0], xch(v[0], 4));
+  v[0] = cadd(v[0], xch(v[0], 2));
+  v[0] = cadd(v[0], xch(v[0], 1));
+}
+
+// One workgroup of SW_NW waves per block and chunk of SW_NW rows y
+// (blockIdx.y); wave w owns the row y = SW_NW*chunk + w, lane = z (unit
+// stride, v <= 64), and the wave walks x eight at a time.  Sums over z use
+// wave_sum8 on eight x at once; sums over x stay in registers, so X2b and Zb
+// are complete per workgroup; X1a, Za, X1b (sums over y) go through LDS and
+// are added per chunk.
 constexpr int SW_NW = 8;
-constexpr int SW_MAXY = 8;
-constexpr int SW_XCHUNK = 16;  // x values per workgroup
 
 __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* __restrict__ T, const int* __restrict__ bl,
                                                               const cplx* __restrict__ Lov, const cplx* __restrict__ F,
                                                               const cplx* __restrict__ l2, cplx* __restrict__ X1,
                                                               cplx* __restrict__ X2p, cplx* __restrict__ Z, int o,
                                                               int v, int flags) {
-  __shared__ cplx sx[2][SW_NW][64];  // per-wave partials of X1a[x], Za[x]
-  __shared__ cplx sz[SW_NW][64];     // per-wave partials of X1b[z]
+  __shared__ cplx sP[2][SW_NW][64];  // per-wave X1a[x], Za[x]
+  __shared__ cplx sz[SW_NW][64];     // per-wave X1b[z]
   const int q = blockIdx.x;
-  const int xb = blockIdx.y * SW_XCHUNK, xe = min(v, xb + SW_XCHUNK);  // this workgroup's x
   const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
   const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
   const int nn = o + v;
   const cplx* t = T + (int64_t)n * v3;
   const cplx* fK = F + (int64_t)K * nn + o;
   const cplx* l2JK = l2 + ((int64_t)J * o + K) * v2;
-  const cplx* LJ = Lov + (int64_t)J * v * o * v + (int64_t)K * v;  // L[J,y,K,z] = LJ[y*o*v + z]
   const int64_t Ly = (int64_t)o * v;
   const bool doX = flags & 1, doZ = flags & 2;
-  const int z = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const bool zin = z < v;
-  const int ny = (v - w + SW_NW - 1) / SW_NW;  // rows of this wave
-  cplx a3[SW_MAXY], a5[SW_MAXY];
-#pragma unroll
-  for (int k = 0; k < SW_MAXY; ++k) {
-    a3[k] = cplx{0, 0};
-    a5[k] = cplx{0, 0};
-  }
-  cplx a4{0, 0};
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, z = lane;
+  const int y = blockIdx.y * SW_NW + w;
+  const bool yin = y < v, zin = z < v, ok = yin && zin;
+  const cplx* LJy = Lov + (int64_t)J * v * o * v + (int64_t)K * v + (yin ? y * Ly : 0);  // L[J,y,K,.]
+  const cplx Lyz = ok ? LJy[z] : cplx{0, 0};
+  const cplx lyz = ok ? l2JK[(int64_t)y * v + z] : cplx{0, 0};
   const cplx fz = zin ? fK[z] : cplx{0, 0};
-  for (int x = xb; x < xe; ++x) {
-    const cplx fx = fK[x];
-    const cplx* tx = t + (int64_t)x * v2;
-    cplx p1{0, 0}, p2{0, 0};
+  cplx a3{0, 0}, a4{0, 0}, a5{0, 0};
+  for (int xg = 0; xg < v; xg += 8) {
+    cplx r[8], p1[8], p2[8];
 #pragma unroll
-    for (int k = 0; k < SW_MAXY; ++k) {
-      if (k < ny) {
-        const int y = w + SW_NW * k;
-        const cplx tv = zin ? tx[(int64_t)y * v + z] : cplx{0, 0};
-        if (doX) {
-          if (zin) {
-            p1 = cadd(p1, cmul(tv, LJ[y * Ly + z]));
-            a3[k] = cadd(a3[k], cmul(tv, fx));
-            a4 = cadd(a4, cmul(tv, LJ[y * Ly + x]));
-          }
-          // X2a[x][y] = sum_z t[x,y,z] f[z]: wave reduction over the lanes
-          cplx r = cmul(tv, fz);
-          for (int off = 32; off > 0; off >>= 1) {
-            r.re += __shfl_xor(r.re, off);
-            r.im += __shfl_xor(r.im, off);
-          }
-          if (z == 0) catomic(&X2p[(((int64_t)I * o + J) * v + x) * v + y], r);
-        }
-        if (doZ && zin) {
-          p2 = cadd(p2, cmul(tv, l2JK[(int64_t)y * v + z]));
-          a5[k] = cadd(a5[k], cmul(tv, l2JK[(int64_t)x * v + z]));
-        }
+    for (int xl = 0; xl < 8; ++xl) {
+      const int x = xg + xl;
+      const bool xin = x < v;
+      const cplx tv = ok && xin ? t[(int64_t)x * v2 + (int64_t)y * v + z] : cplx{0, 0};
+      r[xl] = cmul(tv, fz);
+      p1[xl] = cmul(tv, Lyz);
+      p2[xl] = cmul(tv, lyz);
+      if (xin) {
+        a3 = cadd(a3, cmul(tv, fK[x]));
+        a4 = cadd(a4, cmul(tv, yin ? LJy[x] : cplx{0, 0}));
+        a5 = cadd(a5, cmul(tv, zin ? l2JK[(int64_t)x * v + z] : cplx{0, 0}));
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      p1.re += __shfl_xor(p1.re, off);
-      p1.im += __shfl_xor(p1.im, off);
-      p2.re += __shfl_xor(p2.re, off);
-      p2.im += __shfl_xor(p2.im, off);
+    const int xs = xg + (lane >> 3);  // the x a lane's reduced value belongs to
+    if (doX) {
+      // X2a[x][y] = sum_z t[x,y,z] f[z]
+      wave_sum8(r, lane);
+      if ((lane & 7) == 0 && xs < v && yin) catomic(&X2p[(((int64_t)I * o + J) * v + xs) * v + y], r[0]);
+      wave_sum8(p1, lane);
+      if ((lane & 7) == 0 && xs < v) sP[0][w][xs] = p1[0];
     }
-    if (z == 0) {
-      sx[0][w][x] = p1;
-      sx[1][w][x] = p2;
+    if (doZ) {
+      wave_sum8(p2, lane);
+      if ((lane & 7) == 0 && xs < v) sP[1][w][xs] = p2[0];
     }
   }
   // X2b[z][y] = sum_x t[x,y,z] f[x] (subtracted); Zb[y] = sum_xz t l2[x][z] (subtracted)
-#pragma unroll
-  for (int k = 0; k < SW_MAXY; ++k) {
-    if (k < ny) {
-      const int y = w + SW_NW * k;
-      if (doX && zin) catomic(&X2p[(((int64_t)I * o + J) * v + z) * v + y], cplx{-a3[k].re, -a3[k].im});
-      if (doZ) {
-        cplx r = a5[k];
-        for (int off = 32; off > 0; off >>= 1) {
-          r.re += __shfl_xor(r.re, off);
-          r.im += __shfl_xor(r.im, off);
-        }
-        if (z == 0) catomic(&Z[(int64_t)I * v + y], cplx{-r.re, -r.im});
-      }
+  if (doX && ok) catomic(&X2p[(((int64_t)I * o + J) * v + z) * v + y], cplx{-a3.re, -a3.im});
+  if (doZ) {
+    for (int off = 32; off > 0; off >>= 1) {
+      a5.re += __shfl_xor(a5.re, off);
+      a5.im += __shfl_xor(a5.im, off);
     }
+    if (lane == 0 && yin) catomic(&Z[(int64_t)I * v + y], cplx{-a5.re, -a5.im});
   }
   sz[w][z] = a4;
   __syncthreads();
   if (threadIdx.x < v) {
     const int a = threadIdx.x;
-    const bool own = a >= xb && a < xe;  // X1a[a] and Za[a] belong to this chunk
+    const int nw = min(SW_NW, v - (int)blockIdx.y * SW_NW);  // waves with a row
     cplx s1{0, 0}, s2{0, 0}, s4{0, 0};
-    for (int ww = 0; ww < SW_NW; ++ww) {
-      if (own) {
-        s1 = cadd(s1, sx[0][ww][a]);
-        s2 = cadd(s2, sx[1][ww][a]);
-      }
+    for (int ww = 0; ww < nw; ++ww) {
+      if (doX) s1 = cadd(s1, sP[0][ww][a]);
+      if (doZ) s2 = cadd(s2, sP[1][ww][a]);
       s4 = cadd(s4, sz[ww][a]);
     }
     if (doX) catomic(&X1[(int64_t)I * v + a], csub(s1, s4));
-    if (doZ && own) catomic(&Z[(int64_t)I * v + a], s2);
+    if (doZ) catomic(&Z[(int64_t)I * v + a], s2);
   }
 }
 
@@ -291,8 +291,8 @@ void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, cons
                      cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s) {
   if (nb <= 0) return;
   if (v <= 64) {
-    const unsigned nxc = (unsigned)((v + SW_XCHUNK - 1) / SW_XCHUNK);
-    hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb, nxc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p,
+    const unsigned nyc = (unsigned)((v + SW_NW - 1) / SW_NW);
+    hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb, nyc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p,
                        Z, o, v, flags);
   } else {
     hipLaunchKernelGGL(small_t3_simple_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1,

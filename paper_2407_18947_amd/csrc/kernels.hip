@@ -827,8 +827,10 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
     const int64_t maxs = d.K / (2 * BKMAX);
     ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
   }
-  if (d.gk_start) {  // a workgroup's K range spans at most GK_MAXSEG - 4 gathered blocks
-    const int64_t span_k = (int64_t)(GK_MAXSEG - 4) * d.K0 / BKMAX * BKMAX;
+  if (d.gk_start) {  // a workgroup's K range spans at most GK_MAXSEG - 4 gathered blocks,
+                     // and at most 16 when it accumulates in FP32
+    const int64_t nblk = d.prec == RTCC3_PREC_FP64 ? GK_MAXSEG - 4 : 16;
+    const int64_t span_k = std::max<int64_t>(BKMAX, nblk * d.K0 / BKMAX * BKMAX);
     ksplit = (int)std::max<int64_t>(ksplit, (d.K + span_k - 1) / span_k);
   }
   const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BKMAX - 1) / BKMAX * BKMAX);

@@ -213,8 +213,12 @@ void finish_window(Window& w, const std::vector<std::array<int, 3>>& blocks) {
 void Triples::build_windows() {
   const int o = d_.o;
   const int64_t v3 = (int64_t)d_.v * d_.v * d_.v;
-  // Four window buffers of nw blocks each; keep them within a 4 GiB budget.
-  const int64_t budget = (int64_t)4 << 30;
+  // Four window buffers of nw blocks each (W for t3 and for lambda3, t3,
+  // lambda3); larger windows mean fewer, larger launches.  Budget: half the
+  // free device memory, at most 24 GiB (of the 288 GB of HBM).
+  size_t free_b = 0, total_b = 0;
+  RTCC3_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)24 << 30, (int64_t)(free_b / 2)));
   int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * v3));
   // ---- RHS windows: canonical triples i <= j <= k with all their orderings
   std::vector<std::array<int, 3>> cur;

@@ -189,8 +189,12 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
 //   t_c[t] = sum_s W[slot_s][t o p_s] / D(t),   T[slot_s][t o p_s] = t_c[t]
 // where slot_s is the window slot of the ordered triple (i,j,k) o p_s, because
 // t_{sigma(ijk)}^{sigma(abc)} = t_{ijk}^{abc}.  Sources are read and
-// destinations written along their unit-stride index through LDS.
+// destinations written along their unit-stride index through LDS.  The LDS
+// cube is padded (row strides CB+1 and CB*(CB+1)+1 elements, both odd) so that
+// walking any of its three axes touches distinct banks.
 constexpr int CB = 8;
+constexpr int CS1 = CB + 1, CS0 = CB * CS1 + 1;
+__device__ __forceinline__ int cube_at(int t0, int t1, int t2) { return t0 * CS0 + t1 * CS1 + t2; }
 __device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}};
 
 // With LAM, each source element first receives the terms of the lambda3 bracket
@@ -201,7 +205,7 @@ template <bool LAM>
 __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ W, cplx* __restrict__ T,
                                                          const int* __restrict__ canon, const int* __restrict__ part,
                                                          const double* __restrict__ eps, int o, int v, LamElem le) {
-  __shared__ cplx acc[CB * CB * CB];
+  __shared__ cplx acc[CB * CS0];
   const int q = blockIdx.y;
   const int I = canon[4 * q], J = canon[4 * q + 1], K = canon[4 * q + 2], n0 = canon[4 * q + 3];
   const int* sl = part + 6 * n0;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   t0[1] = ((cube / nc) % nc) * CB;
   t0[2] = (cube % nc) * CB;
   const int64_t v3 = (int64_t)v * v * v;
-  for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) acc[e] = cplx{0, 0};
+  for (int e = threadIdx.x; e < CB * CS0; e += blockDim.x) acc[e] = cplx{0, 0};
   __syncthreads();
   const int occ[3] = {I, J, K};
   const int nn = o + v;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
           w = cadd(w, cmul(le.F[(int64_t)si * nn + o + X0], le.l2[(((int64_t)sj * o + sk) * v + X1) * v + X2]));
           w = csub(w, cmul(le.F[(int64_t)sj * nn + o + X0], le.l2[(((int64_t)si * o + sk) * v + X1) * v + X2]));
         }
-        cplx& r = acc[(tl[0] * CB + tl[1]) * CB + tl[2]];
+        cplx& r = acc[cube_at(tl[0], tl[1], tl[2])];
         r.re += w.re;
         r.im += w.im;
       }
@@ -246,11 +250,13 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   }
   const double eocc = eps[I] + eps[J] + eps[K];
   for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
-    const int a = t0[0] + e / (CB * CB), b = t0[1] + (e / CB) % CB, c = t0[2] + e % CB;
+    const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
+    const int a = t0[0] + u0, b = t0[1] + u1, c = t0[2] + u2;
     if (a < v && b < v && c < v) {
       const double D = eocc - eps[o + a] - eps[o + b] - eps[o + c];
-      acc[e].re /= D;
-      acc[e].im /= D;
+      cplx& r = acc[cube_at(u0, u1, u2)];
+      r.re /= D;
+      r.im /= D;
     }
   }
   __syncthreads();
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
         tl[p0] = u0;
         tl[p1] = u1;
         tl[p2] = u2;
-        dst[((int64_t)X0 * v + X1) * v + X2] = acc[(tl[0] * CB + tl[1]) * CB + tl[2]];
+        dst[((int64_t)X0 * v + X1) * v + X2] = acc[cube_at(tl[0], tl[1], tl[2])];
       }
     }
   }

@@ -150,6 +150,7 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
   RTCC3_HIP(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_l_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+  RTCC3_HIP(hipEventCreateWithFlags(&ev_t3b_, hipEventDisableTiming));
   (void)e;
 }
 
@@ -167,7 +168,7 @@ Triples::~Triples() {
     }
   if (eps_) (void)hipFree(eps_);
   if (s2_) (void)hipStreamSynchronize(s2_);
-  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_})
+  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_})
     if (ev) (void)hipEventDestroy(ev);
   if (s2_) (void)hipStreamDestroy(s2_);
   if (t0_) (void)hipEventDestroy(t0_);
@@ -457,6 +458,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     build_event(s);
     build_flop_ += 8.0 * nw * v * v2 * (v + o);
   }
+  RTCC3_HIP(hipEventRecord(ev_t3b_, s));
   launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
 
   // ---------------- lambda3 blocks
@@ -478,6 +480,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, v3);
     const int64_t lLC = (int64_t)o * v * o * o;
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
+    RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));  // after the t3 build (overlaps its symmetrisation)
     build_event(s2);
     checked_seg_gemm(g, blh, lA, lB, winlen, s2);
     build_event(s2);

@@ -87,7 +87,7 @@ def test_ccsd_terms(o, v):
         _close(k, g[k], r[k].numpy())
 
 
-@pytest.mark.parametrize("o,v", [(1, 4), (2, 3), (3, 4), (4, 7), (5, 19)])
+@pytest.mark.parametrize("o,v", [(1, 4), (2, 3), (3, 4), (4, 7), (5, 19), (15, 10)])
 def test_triples_terms(o, v):
     _say(f"triples terms o={o} v={v}")
     s = make_system(o, v, seed=12)
@@ -152,3 +152,40 @@ def test_monomer_dipole_series_matches_stored_oracle():
     ctx.close()
     assert np.abs(mu - g["mu"]).max() < 1e-10, np.abs(mu - g["mu"]).max()
     assert np.abs(y - g["y"]).max() < 1e-9 * max(1, np.abs(g["y"]).max())
+
+
+def test_trimer_size_sampled_elements():
+    """Full workload size (o=15, v=57, the benchmark's windows and streams):
+    the (i,j) = (0,0) blocks of X2 and Y2 against the oracle's triples loop over
+    the blocks with second index 0, which are all that those elements depend on
+    (after the P_ij^ab symmetrisation, X2_00^ab = x2_00^ab + x2_00^ba, where x2_{.0}
+    collects blocks (.,0,.), and likewise Y2); both through the density pass
+    (rtcc3_rhs_terms) and the plain right-hand side (rtcc3_rhs, dy = -i(Omega2 +
+    X2), +i(G2 + Y2) for those elements)."""
+    o, v = 15, 57
+    _say(f"trimer-size sampled elements o={o} v={v}")
+    s = make_system(o, v, seed=3)
+    m = orc.Model.from_system(s)
+    y = _random_state(o, v, 8, scale=0.02)
+    E = np.array([0.001, -0.002, 0.002])
+    g = _gpu_terms(s, y, E, 1)
+    ctx = _lib.Context(s)
+    yd = torch.tensor(y, dtype=torch.complex128, device="cuda")
+    dy = torch.zeros_like(yd)
+    torch.cuda.synchronize()
+    _lib.rtcc3_rhs(ctx.ctx, E, yd, dy)
+    dy = dy.cpu().numpy()
+    ctx.close()
+    with torch.no_grad():
+        t1, t2, l1, l2 = orc.unpack(m, y)
+        ti = orc.TriplesIntegrals(orc.Dressed(m, t1, m.h(E)))
+        part = orc.triples_loop(m, ti, t2, l1, l2, want_density=False, max_blocks=o * o)
+    ccsd = orc.rhs_terms(m, y, E, with_triples=False, with_density=False)
+    X2, Y2 = part["X2"][0, 0].numpy(), part["Y2"][0, 0].numpy()
+    _close("X2[0,0]", g["X2"][0, 0], X2)
+    _close("Y2[0,0]", g["Y2"][0, 0], Y2)
+    ov, oovv = o * v, o * o * v * v
+    dt2 = dy[ov:ov + oovv].reshape(o, o, v, v)[0, 0]
+    dl2 = dy[2 * ov + oovv:].reshape(o, o, v, v)[0, 0]
+    _close("dt2[0,0]", dt2, -1j * (ccsd["R2"][0, 0].numpy() + X2))
+    _close("dl2[0,0]", dl2, 1j * (ccsd["G2"][0, 0].numpy() + Y2))

@@ -86,6 +86,7 @@ struct GemmDesc {
   //   sum_s comb_w[s] * X[part[6*n + comb_perm[s]]*comb_stride + offset],  n = bl[4*b + 3],
   // in place of its block-table offset; e.g. a linear combination of a block
   // and blocks of permuted occupied triples read at the same element offset.
+  // comb_n = 1 (B only): B is the single block part[6*n + comb_perm[0]].
   int comb_n, comb_on;
   const int* part;
   int comb_perm[3];

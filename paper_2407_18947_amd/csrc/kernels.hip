@@ -61,7 +61,8 @@ __device__ __forceinline__ void split_k(int k, int K0, float inv, int& q, int& r
 // entry (the empty asm keeps the compiler from turning the address select
 // back into a branch around the load) and is then replaced by zero.
 // CMB = 1 / 2: operand A / B is a combination of three blocks (GemmDesc::comb_*);
-// CMB = 3: gathered K (GemmDesc::gk_*).
+// CMB = 3: gathered K (GemmDesc::gk_*); CMB = 4: B is one block of a permuted
+// occupied triple (comb_n = 1).
 template <bool KFA, bool NFB, int BN, int BK, bool SEG, int CMB = 0>
 struct TileLoader {
   static constexpr int NEA = BM * BK / NT, NEB = BN * BK / NT;
@@ -112,6 +113,7 @@ struct TileLoader {
         B = d.B;
         gs = d.gk_start[b];
       }
+      if (CMB == 4) B = d.B + (int64_t)d.part[6 * n + d.comb_perm[0]] * d.comb_stride;
       if (CMB == 1 || CMB == 2) {
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
@@ -680,7 +682,9 @@ void launch_one(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kch
 template <int MODE, bool ATOMIC, int BN>
 void launch_comb_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk) {
   typedef typename std::conditional<MODE == RTCC3_PREC_FP64, double, float>::type T;
-  if (d.comb_on == 0)
+  if (d.comb_n == 1)
+    hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false, 4>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+  else if (d.comb_on == 0)
     hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false, 1>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   else
     hipLaunchKernelGGL((zgemm_kernel<T, ATOMIC, true, false, BN, false, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
@@ -791,7 +795,8 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   if (d0.K <= 0) return;
   RTCC3_CHECK(d0.M0 >= 1 && d0.N0 >= 1 && d0.K0 >= 1, "gemm: inner extents must be >= 1");
   if (d0.comb_n > 0) {
-    RTCC3_CHECK(d0.comb_n == 3 && d0.bl && d0.part && d0.nseg == 0 && (d0.comb_on == 0 || d0.comb_on == 1),
+    RTCC3_CHECK((d0.comb_n == 3 || (d0.comb_n == 1 && d0.comb_on == 1)) && d0.bl && d0.part && d0.nseg == 0 &&
+                    (d0.comb_on == 0 || d0.comb_on == 1),
                 "gemm: bad combined operand");
   }
   if (d0.gk_start) {

@@ -515,7 +515,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
 
     // The combinations of X2 are read straight from the window: with
     // t_{sigma(ijk)}^{sigma(abc)} = t_ijk^abc, for the block (I,J,K)
-    //   Z1[b][c][e] = 2t[c,b,e] - t[c,e,b] - t[e,b,c] = (2 T_IJK - T_IKJ - T_KJI)[c][b][e]
+    //   Z1[b][c][e] = 2t[c,b,e] - t[c,e,b] - t[e,b,c] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
     //   Zh[a][b][c] = 2t[c,b,a] - t[b,c,a] - t[a,b,c] = (2 T_KJI - T_KIJ - T_IJK)[a][b][c]
     // (window orderings: 0 IJK, 1 JIK, 2 IKJ, 3 KJI, 4 KIJ, 5 JKI).
     auto combine = [&](GemmDesc& g, int on, int p0, int p1, int p2) {
@@ -530,21 +530,19 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.comb_w[2] = -1.0;
       g.comb_stride = v3;
     };
-    {  // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ into X2p[I][J][a][b]
+    {  // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ into X2p[I][J][a][b], with (c,e) contiguous:
+       //   Z1[b][c][e] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
       GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
-      g.K0 = v;
       g.A = gX2a;
       g.sAm0 = v2;
-      g.sAk1 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, v3, 0);
-      g.B = T;  // B[(c,e)][b] = Z1[b][c][e]
-      g.sBk1 = v2;
+      g.B = T;  // B[(c,e)][b] = Z1[b][(c,e)]
       g.sBk0 = 1;
-      g.sBn0 = v;
+      g.sBn0 = v2;
       set4(g.cB, 0, 0, 0, v3);
-      combine(g, 1, 0, 2, 3);
+      combine(g, 1, 1, 4, 5);
       g.C = X2p;
       g.sCm0 = v;
       g.sCn0 = 1;
@@ -572,20 +570,23 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     }
     // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1)
     launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
-    {  // Y2: sum_de (da|eK)~ lambda[d][b][e] into Y2p[I][J][a][b]
+    {  // Y2: sum_de (da|eK)~ lambda[d][b][e] into Y2p[I][J][a][b]; lambda_IJK[d][b][e] =
+       // lambda_JIK[b][d][e], read with (d,e) contiguous
       GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
-      g.K0 = v;
       g.A = gY2a;
       g.sAm0 = v2;
-      g.sAk1 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, v3, 0);
       g.B = L;
-      g.sBk1 = v2;
       g.sBk0 = 1;
-      g.sBn0 = v;
+      g.sBn0 = v2;
       set4(g.cB, 0, 0, 0, v3);
+      g.comb_n = 1;
+      g.comb_on = 1;
+      g.part = w.d_part;
+      g.comb_perm[0] = 1;
+      g.comb_stride = v3;
       g.C = Y2p;
       g.sCm0 = v;
       g.sCn0 = 1;

@@ -61,14 +61,15 @@ struct GemmDesc {
   int atomic;
   int prec;
   // K segments (nseg > 0, block table required): the contraction runs over
-  // consecutive segments, segment s covering k in [seg[s].k0, seg[s+1].k0)
-  // (the last one up to K) with its own operands
+  // consecutive segments, segment s covering k in [seg[s].k0, seg[s].k0 + len)
+  // with its own operands
   //   A_s[m][r] = seg[s].A[cA.(I,J,K,n) + m*sAm + r*sAk],
   //   B_s[r][n] = seg[s].B[cB.(I,J,K,n) + r*sBk + n*sBn],   r = k - seg[s].k0,
   // so one product sums terms whose operands live in different tensors.
   // The plain A/B fields and M0/N0/K0 splits are then unused (M0 = M, N0 = N).
   struct Seg {
-    int k0;
+    int k0;   // first k; a multiple of 16, so that a K step of 16 lies in one segment
+    int len;  // contraction length (k0 + len <= next k0; the gap reads as zero)
     const cplx* A;
     int64_t cA[4], sAm, sAk;
     const cplx* B;

@@ -185,24 +185,26 @@ struct TileLoader {
   __device__ __forceinline__ void load(const GemmDesc& d, int k0) {
     if (SEG) {
       static_assert(!SEG || (KFA && NFB), "segments are read with A k-fast and B n-fast");
-      const int k = k0 + akk[0];
-      const int s = segof(k);
-      const int r = k - pick(s, 0, sk1, sk2, sk3);
-      const cplx* p = pick(s, Ap[0], Ap[1], Ap[2], Ap[3]);
-      const int64_t sm = pick(s, d.seg[0].sAm, d.seg[1].sAm, d.seg[2].sAm, d.seg[3].sAm);
-      const int64_t kof = (int64_t)r * pick(s, d.seg[0].sAk, d.seg[1].sAk, d.seg[2].sAk, d.seg[3].sAk);
+      // Segments start at multiples of BK: the whole step lies in one segment,
+      // whose operands, strides and length are uniform across the workgroup.
+      const int s = segof(k0);
+      const int base = pick(s, 0, sk1, sk2, sk3);
+      const int len = pick(s, d.seg[0].len, d.seg[1].len, d.seg[2].len, d.seg[3].len);
+      const cplx* pa = pick(s, Ap[0], Ap[1], Ap[2], Ap[3]);
+      const cplx* pb = pick(s, Bp[0], Bp[1], Bp[2], Bp[3]);
+      const int sam = (int)pick(s, d.seg[0].sAm, d.seg[1].sAm, d.seg[2].sAm, d.seg[3].sAm);
+      const int sak = (int)pick(s, d.seg[0].sAk, d.seg[1].sAk, d.seg[2].sAk, d.seg[3].sAk);
+      const int sbk = (int)pick(s, d.seg[0].sBk, d.seg[1].sBk, d.seg[2].sBk, d.seg[3].sBk);
+      const int sbn = (int)pick(s, d.seg[0].sBn, d.seg[1].sBn, d.seg[2].sBn, d.seg[3].sBn);
+      const int ka = k0 + akk[0], ra = ka - base;
+      const bool oka = ka < kend && ra < len;
 #pragma unroll
-      for (int t = 0; t < NEA; ++t) av[t] = fetch(p, k < kend && aval[t], (int64_t)(m0 + amm[t]) * sm + kof);
-      const int64_t ncol = n0 + bnn[0];
+      for (int t = 0; t < NEA; ++t) av[t] = fetch(pa, oka && aval[t], (int64_t)((m0 + amm[t]) * sam + ra * sak));
+      const int ncol = n0 + bnn[0];
 #pragma unroll
       for (int t = 0; t < NEB; ++t) {
-        const int kb = k0 + bkk[t];
-        const int sb = segof(kb);
-        const int rb = kb - pick(sb, 0, sk1, sk2, sk3);
-        const cplx* pb = pick(sb, Bp[0], Bp[1], Bp[2], Bp[3]);
-        const int64_t off = (int64_t)rb * pick(sb, d.seg[0].sBk, d.seg[1].sBk, d.seg[2].sBk, d.seg[3].sBk) +
-                            ncol * pick(sb, d.seg[0].sBn, d.seg[1].sBn, d.seg[2].sBn, d.seg[3].sBn);
-        bv[t] = fetch(pb, kb < kend && bval[0], off);
+        const int kb = k0 + bkk[t], rb = kb - base;
+        bv[t] = fetch(pb, kb < kend && rb < len && bval[0], (int64_t)(rb * sbk + ncol * sbn));
       }
       return;
     }
@@ -444,6 +446,7 @@ struct SplitRows {
         const int k = kb + e;
         const int s = (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3);
         const int r = k - (s == 0 ? 0 : s == 1 ? sk1 : s == 2 ? sk2 : sk3);
+        const int len = s == 0 ? d.seg[0].len : s == 1 ? d.seg[1].len : s == 2 ? d.seg[2].len : d.seg[3].len;
         const GemmDesc::Seg& g0 = d.seg[0];
         const GemmDesc::Seg& g1 = d.seg[1];
         const GemmDesc::Seg& g2 = d.seg[2];
@@ -457,7 +460,7 @@ struct SplitRows {
           sx = s == 0 ? g0.sBn : s == 1 ? g1.sBn : s == 2 ? g2.sBn : g3.sBn;
           sk = s == 0 ? g0.sBk : s == 1 ? g1.sBk : s == 2 ? g2.sBk : g3.sBk;
         }
-        const bool ok = val && k < kend;
+        const bool ok = val && k < kend && r < len;
         int64_t o = ok ? (int64_t)xabs * sx + (int64_t)r * sk : 0;
         asm volatile("" : "+v"(o));
         const cplx v = p[o];
@@ -808,8 +811,13 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
     RTCC3_CHECK(d0.nseg <= 4 && d0.bl && d0.seg[0].k0 == 0 && d0.M0 == d0.M && d0.N0 == d0.N,
                 "gemm: bad K segments");
     for (int s = 0; s < d0.nseg; ++s) {
+      const GemmDesc::Seg& g = d0.seg[s];
       const int end = s + 1 < d0.nseg ? d0.seg[s + 1].k0 : d0.K;
-      RTCC3_CHECK(d0.seg[s].A && d0.seg[s].B && end > d0.seg[s].k0, "gemm: bad K segments");
+      RTCC3_CHECK(g.A && g.B && g.len >= 1 && g.k0 % 16 == 0 && g.k0 + g.len <= end, "gemm: bad K segments");
+      // element offsets inside a segment operand are formed in 32 bits
+      RTCC3_CHECK((int64_t)(d0.M + 63) * g.sAm + (int64_t)g.len * g.sAk < (1LL << 31) &&
+                      (int64_t)g.len * g.sBk + (int64_t)(d0.N + 63) * g.sBn < (1LL << 31),
+                  "gemm: segment operand too large");
     }
   }
   RTCC3_CHECK(d0.K < (1 << 22), "gemm: K too long");

@@ -118,7 +118,7 @@ void checked_seg_gemm(const GemmDesc& g, const int* bl_host, const int64_t* lenA
     RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
     for (int t = 0; t < g.nseg; ++t) {
       const GemmDesc::Seg& sg = g.seg[t];
-      const int len = (t + 1 < g.nseg ? g.seg[t + 1].k0 : g.K) - sg.k0;
+      const int len = sg.len;
       RTCC3_CHECK(len >= 1 && sg.sAm >= 0 && sg.sAk >= 0 && sg.sBk >= 0 && sg.sBn >= 0, "triples: bad segment");
       const int64_t oA = sg.cA[0] * q[0] + sg.cA[1] * q[1] + sg.cA[2] * q[2] + sg.cA[3] * q[3];
       const int64_t oB = sg.cB[0] * q[0] + sg.cB[1] * q[1] + sg.cB[2] * q[2] + sg.cB[3] * q[3];
@@ -427,9 +427,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   // P_ijk^abc sums over all simultaneous permutations of (ijk) and (abc), so
   // P Y = P X.
   const int64_t lT2 = t2len, lOVVV_ = lOVVV;
-  auto seg = [](GemmDesc::Seg& sg, int k0, const cplx* A, std::initializer_list<int64_t> cA, int64_t sAm,
+  auto up16 = [](int k) { return (k + 15) / 16 * 16; };
+  // Segments start at multiples of 16 (the kernels' K step).
+  auto seg = [](GemmDesc::Seg& sg, int k0, int len, const cplx* A, std::initializer_list<int64_t> cA, int64_t sAm,
                 int64_t sAk, const cplx* B, std::initializer_list<int64_t> cB, int64_t sBk) {
     sg.k0 = k0;
+    sg.len = len;
     sg.A = A;
     std::copy(cA.begin(), cA.end(), sg.cA);
     sg.sAm = sAm;
@@ -443,11 +446,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   // ---------------- t3 blocks
   {  // W[n][a][(b,c)] = sum_e t2[I][J][a][e] (ck|be)~[K][e][(b,c)]
      //              + sum_m -(mk|ai)~[K][I][a][m] t2[J][m][(b,c)]   (term 2 relabelled)
-    GemmDesc g = base(v, (int)v2, v + o, nw, bl, pr);
+    GemmDesc g = base(v, (int)v2, up16(v) + o, nw, bl, pr);
     g.store = 1;
     g.nseg = 2;
-    seg(g.seg[0], 0, t2, {(int64_t)o * v2, v2, 0, 0}, v, 1, gW1, {0, 0, v3, 0}, v2);
-    seg(g.seg[1], v, gW2, {(int64_t)v * o, 0, (int64_t)o * v * o, 0}, o, 1, t2, {0, (int64_t)o * v2, 0, 0}, v2);
+    seg(g.seg[0], 0, v, t2, {(int64_t)o * v2, v2, 0, 0}, v, 1, gW1, {0, 0, v3, 0}, v2);
+    seg(g.seg[1], up16(v), o, gW2, {(int64_t)v * o, 0, (int64_t)o * v * o, 0}, o, 1, t2, {0, (int64_t)o * v2, 0, 0},
+        v2);
     g.C = W;
     g.sCm0 = v2;
     g.sCn0 = 1;
@@ -466,14 +470,15 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
      //              - sum_l Lt_ijal[I][a][J][l] l2[l][K][(b,c)]
      //              + sum_d l2[J][K][a][d] -(ib|dc)~[I][d][(b,c)]                (relabelled)
      //              + sum_d l2[I][J][a][d] (2(db|kc) - (dc|kb))~[K][d][(b,c)]    (relabelled)
-    GemmDesc g = base(v, (int)v2, 2 * o + 2 * v, nw, bl, pr);
+    const int k1 = up16(o), k2 = 2 * up16(o), k3 = 2 * up16(o) + up16(v);
+    GemmDesc g = base(v, (int)v2, k3 + v, nw, bl, pr);
     g.store = 1;
     g.nseg = 4;
     const int64_t oo = (int64_t)o * o, ov2 = (int64_t)o * v2;
-    seg(g.seg[0], 0, gLC, {0, o, (int64_t)v * oo, 0}, oo, 1, l2, {v2, 0, 0, 0}, ov2);
-    seg(g.seg[1], o, gLD, {(int64_t)v * oo, o, 0, 0}, oo, 1, l2, {0, 0, v2, 0}, ov2);
-    seg(g.seg[2], 2 * o, l2, {0, ov2, v2, 0}, v, 1, gLA, {v3, 0, 0, 0}, v2);
-    seg(g.seg[3], 2 * o + v, l2, {ov2, v2, 0, 0}, v, 1, gLB, {0, 0, v3, 0}, v2);
+    seg(g.seg[0], 0, o, gLC, {0, o, (int64_t)v * oo, 0}, oo, 1, l2, {v2, 0, 0, 0}, ov2);
+    seg(g.seg[1], k1, o, gLD, {(int64_t)v * oo, o, 0, 0}, oo, 1, l2, {0, 0, v2, 0}, ov2);
+    seg(g.seg[2], k2, v, l2, {0, ov2, v2, 0}, v, 1, gLA, {v3, 0, 0, 0}, v2);
+    seg(g.seg[3], k3, v, l2, {ov2, v2, 0, 0}, v, 1, gLB, {0, 0, v3, 0}, v2);
     g.C = Wl;
     g.sCm0 = v2;
     g.sCn0 = 1;
@@ -662,12 +667,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     }
     {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
        //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
-      GemmDesc g = base(v, (int)(o * v), 2 * v, cn, cbl, pr);
+      GemmDesc g = base(v, (int)(o * v), up16(v) + v, cn, cbl, pr);
       g.store = 1;
       g.nseg = 2;
       const int64_t ov2 = (int64_t)o * v2, v2o = v2 * o;
-      seg(g.seg[0], 0, t2, {0, ov2, v2, 0}, v, 1, gG9, {v2o, 0, 0, 0}, (int64_t)v * o);
-      seg(g.seg[1], v, t2, {v2, ov2, 0, 0}, v, 1, gG10, {0, 0, v2o, 0}, (int64_t)v * o);
+      seg(g.seg[0], 0, v, t2, {0, ov2, v2, 0}, v, 1, gG9, {v2o, 0, 0, 0}, (int64_t)v * o);
+      seg(g.seg[1], up16(v), v, t2, {v2, ov2, 0, 0}, v, 1, gG10, {0, 0, v2o, 0}, (int64_t)v * o);
       g.C = S;
       g.sCm0 = (int64_t)v * o;
       g.sCn0 = 1;

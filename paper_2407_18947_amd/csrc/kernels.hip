@@ -240,13 +240,21 @@ struct TileLoader {
 };
 
 // C[m][n] (+)= alpha * x for one element of the tile.
+// Offset of row m (or column n) of C split as (x / X0, x % X0); -1 outside.
+__device__ __forceinline__ int64_t c_off(int x, int X, int X0, int64_t s1, int64_t s0) {
+  if (x >= X) return -1;
+  int q, r;
+  split_k(x, X0, 1.0f / (float)X0, q, r);
+  return (int64_t)q * s1 + (int64_t)r * s0;
+}
+
+// C[row + col] (+)= alpha * x for one element of the tile (offsets from c_off).
 template <bool ATOMIC>
-__device__ __forceinline__ void put(const GemmDesc& d, cplx* C, int m, int n, double xr, double xi) {
-  if (m >= d.M || n >= d.N) return;
+__device__ __forceinline__ void put(const GemmDesc& d, cplx* C, int64_t ro, int64_t co, double xr, double xi) {
+  if (ro < 0 || co < 0) return;
   const double alr = d.alpha.re, ali = d.alpha.im;
   const double vr = alr * xr - ali * xi, vi = alr * xi + ali * xr;
-  cplx* p = C + (int64_t)(m / d.M0) * d.sCm1 + (int64_t)(m % d.M0) * d.sCm0 + (int64_t)(n / d.N0) * d.sCn1 +
-            (int64_t)(n % d.N0) * d.sCn0;
+  cplx* p = C + ro + co;
   if (ATOMIC) {
     atomic_add_cplx(p, vr, vi);
   } else if (d.store) {
@@ -382,14 +390,20 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     __syncthreads();
   }
 
+  int64_t co[JB], ro[IB][4];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) co[j] = c_off(tn * BN + wn + 16 * j + (lane & 15), d.N, d.N0, d.sCn1, d.sCn0);
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      ro[i][r] = c_off(tm * BM + wm + 16 * i + Frag<T>::row(lane, r), d.M, d.M0, d.sCm1, d.sCm0);
 #pragma unroll
   for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int j = 0; j < JB; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        put<ATOMIC>(d, C, tm * BM + wm + 16 * i + Frag<T>::row(lane, r), tn * BN + wn + 16 * j + (lane & 15),
-                    (double)cre[i][j][r], (double)cim[i][j][r]);
+      for (int r = 0; r < 4; ++r) put<ATOMIC>(d, C, ro[i][r], co[j], (double)cre[i][j][r], (double)cim[i][j][r]);
 }
 
 // Split bf16 operands: x = s_0 + s_1 + ... + s_{NSL-1} + O(2^-8NSL |x|) with
@@ -627,14 +641,21 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(GemmDesc d, int ksplit,
     }
   }
 
+  int64_t co[JB], ro[IB][4];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) co[j] = c_off(tn * BN + wn + 16 * j + (lane & 15), d.N, d.N0, d.sCn1, d.sCn0);
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      ro[i][r] = c_off(tm * BM + wm + 16 * i + Frag<float>::row(lane, r), d.M, d.M0, d.sCm1, d.sCm0);
 #pragma unroll
   for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        put<ATOMIC>(d, C, tm * BM + wm + 16 * i + Frag<float>::row(lane, r), tn * BN + wn + 16 * j + (lane & 15),
-                    (double)crr[i][j][r] - (double)cii[i][j][r], (double)cim[i][j][r]);
+        put<ATOMIC>(d, C, ro[i][r], co[j], (double)crr[i][j][r] - (double)cii[i][j][r], (double)cim[i][j][r]);
 }
 
 __global__ void axpy_kernel(AxpyDesc d, int64_t total) {
@@ -820,7 +841,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
                   "gemm: segment operand too large");
     }
   }
-  RTCC3_CHECK(d0.K < (1 << 22), "gemm: K too long");
+  RTCC3_CHECK(d0.K < (1 << 22) && d0.M < (1 << 22) && d0.N < (1 << 22), "gemm: extent too long");
   RTCC3_CHECK(!d0.store || !d0.atomic, "gemm: store mode cannot be atomic");
   // A narrow side (at most 16, e.g. one occupied index) goes on N with 64x16
   // tiles; a narrow M is moved there by transposing the product.

@@ -455,27 +455,21 @@ struct SplitRows {
                                        int xabs, double* re, double* im) const {
     const int kb = k0 + 8 * chunk;
     if (SEG) {
+      // segments start at multiples of 16, so a chunk of eight k lies in one
+      const int s = (int)(kb >= sk1) + (int)(kb >= sk2) + (int)(kb >= sk3);
+      const int r0 = kb - (s == 0 ? 0 : s == 1 ? sk1 : s == 2 ? sk2 : sk3);
+      auto sel = [s](auto x0, auto x1, auto x2, auto x3) { return s == 0 ? x0 : s == 1 ? x1 : s == 2 ? x2 : x3; };
+      const GemmDesc::Seg &g0 = d.seg[0], &g1 = d.seg[1], &g2 = d.seg[2], &g3 = d.seg[3];
+      const cplx* p = sel(Ps[0], Ps[1], Ps[2], Ps[3]);
+      const int len = sel(g0.len, g1.len, g2.len, g3.len);
+      const int sx = (int)(ISA ? sel(g0.sAm, g1.sAm, g2.sAm, g3.sAm) : sel(g0.sBn, g1.sBn, g2.sBn, g3.sBn));
+      const int sk = (int)(ISA ? sel(g0.sAk, g1.sAk, g2.sAk, g3.sAk) : sel(g0.sBk, g1.sBk, g2.sBk, g3.sBk));
+      const int xo = xabs * sx;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int k = kb + e;
-        const int s = (int)(k >= sk1) + (int)(k >= sk2) + (int)(k >= sk3);
-        const int r = k - (s == 0 ? 0 : s == 1 ? sk1 : s == 2 ? sk2 : sk3);
-        const int len = s == 0 ? d.seg[0].len : s == 1 ? d.seg[1].len : s == 2 ? d.seg[2].len : d.seg[3].len;
-        const GemmDesc::Seg& g0 = d.seg[0];
-        const GemmDesc::Seg& g1 = d.seg[1];
-        const GemmDesc::Seg& g2 = d.seg[2];
-        const GemmDesc::Seg& g3 = d.seg[3];
-        const cplx* p = s == 0 ? Ps[0] : s == 1 ? Ps[1] : s == 2 ? Ps[2] : Ps[3];
-        int64_t sx, sk;
-        if (ISA) {
-          sx = s == 0 ? g0.sAm : s == 1 ? g1.sAm : s == 2 ? g2.sAm : g3.sAm;
-          sk = s == 0 ? g0.sAk : s == 1 ? g1.sAk : s == 2 ? g2.sAk : g3.sAk;
-        } else {
-          sx = s == 0 ? g0.sBn : s == 1 ? g1.sBn : s == 2 ? g2.sBn : g3.sBn;
-          sk = s == 0 ? g0.sBk : s == 1 ? g1.sBk : s == 2 ? g2.sBk : g3.sBk;
-        }
-        const bool ok = val && k < kend && r < len;
-        int64_t o = ok ? (int64_t)xabs * sx + (int64_t)r * sk : 0;
+        const int r = r0 + e;
+        const bool ok = val && kb + e < kend && r < len;
+        int64_t o = ok ? (int64_t)(xo + r * sk) : 0;
         asm volatile("" : "+v"(o));
         const cplx v = p[o];
         re[e] = ok ? v.re : 0.0;

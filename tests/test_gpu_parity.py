@@ -154,6 +154,30 @@ def test_monomer_dipole_series_matches_stored_oracle():
     assert np.abs(y - g["y"]).max() < 1e-9 * max(1, np.abs(g["y"]).max())
 
 
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_reduced_precision_dipole_within_target(prec):
+    """The reduced-precision triples paths (FP32; bf16 split with three or two
+    slices) on the monomer workload, 20 steps: the dipole series stays within
+    1e-7 a.u. of the stored FP64 oracle series (the target for reduced
+    precision), and within the error each form is expected to have."""
+    import os
+
+    from paper_2407_18947_amd.inputs import CONFIGS, config_field
+
+    _say(f"monomer 20 steps precision {prec}")
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "monomer_20steps.npz"))
+    c = CONFIGS["monomer"]
+    s = make_system(c["o"], c["v"], seed=c["seed"])
+    ctx = _lib.Context(s, prec)
+    ctx.set_state(initial_state(s))
+    mu = ctx.propagate(c["steps"], c["dt"], config_field("monomer"))
+    ctx.close()
+    err = np.abs(mu - g["mu"]).max()
+    _say(f"  max dipole error {err:.3e}")
+    assert err < {1: 1e-9, 2: 1e-9, 3: 1e-8}[prec], err
+    assert err < 1e-7
+
+
 def test_trimer_size_sampled_elements():
     """Full workload size (o=15, v=57, the benchmark's windows and streams):
     the (i,j) = (0,0) blocks of X2 and Y2 against the oracle's triples loop over

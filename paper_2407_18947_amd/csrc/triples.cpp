@@ -216,10 +216,11 @@ void Triples::build_windows() {
   const int64_t v3 = (int64_t)d_.v * d_.v * d_.v;
   // Four window buffers of nw blocks each (W for t3 and for lambda3, t3,
   // lambda3); larger windows mean fewer, larger launches.  Budget: half the
-  // free device memory, at most 24 GiB (of the 288 GB of HBM).
+  // free device memory, at most 48 GiB (of the 288 GB of HBM); when all o^3
+  // blocks fit, one window serves both passes and nothing is built twice.
   size_t free_b = 0, total_b = 0;
   RTCC3_HIP(hipMemGetInfo(&free_b, &total_b));
-  const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)24 << 30, (int64_t)(free_b / 2)));
+  const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)48 << 30, (int64_t)(free_b / 2)));
   int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * v3));
   // ---- RHS windows: canonical triples i <= j <= k with all their orderings
   std::vector<std::array<int, 3>> cur;
@@ -238,6 +239,24 @@ void Triples::build_windows() {
         for (auto& t : ords) cur.push_back(t);
       }
   flush();
+  if ((int64_t)o * o * o <= wmax) {
+    // ---- every block in one window, in slab order (i fastest, then k, then l):
+    // all slabs (., l, k) are contiguous and every block is owned
+    std::vector<std::array<int, 3>> all;
+    Window w;
+    for (int l = 0; l < o; ++l)
+      for (int k = 0; k < o; ++k) {
+        w.slabs.insert(w.slabs.end(), {0, 0, 0, (int)all.size()});
+        for (int i = 0; i < o; ++i) all.push_back({i, l, k});
+      }
+    finish_window(w, all);
+    for (int n = 0; n < w.nw; ++n) w.owned.insert(w.owned.end(), {all[n][0], all[n][1], all[n][2], n});
+    den_windows_.push_back(w);
+    max_nw_ = 0;
+    for (auto& x : rhs_windows_) max_nw_ = std::max(max_nw_, x.nw);
+    max_nw_ = std::max(max_nw_, w.nw);
+    return;
+  }
   // ---- density (pair) windows.  The pairs (l,k), k >= l, of one l are grouped
   // into windows up to the budget; a window holds every ordering of {i,l,k}
   // for all i and its pairs, with the slabs (i,l,k) and (i,k,l) first and in

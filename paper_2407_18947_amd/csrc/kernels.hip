@@ -855,6 +855,11 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
     const int64_t maxs = d.K / (2 * BKMAX);
     ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
   }
+  if (d.prec != RTCC3_PREC_FP64 && !d.store && !d.gk_start) {
+    // FP32 accumulation: no workgroup sums more than 4096 terms (partial sums
+    // are added in FP64)
+    ksplit = (int)std::max<int64_t>(ksplit, (d.K + 4095) / 4096);
+  }
   if (d.gk_start) {  // a workgroup's K range spans at most GK_MAXSEG - 4 gathered blocks,
                      // and at most 16 when it accumulates in FP32
     const int64_t nblk = d.prec == RTCC3_PREC_FP64 ? GK_MAXSEG - 4 : 16;

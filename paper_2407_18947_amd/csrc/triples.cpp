@@ -151,6 +151,7 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
   RTCC3_HIP(hipEventCreateWithFlags(&ev_l_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_t3b_, hipEventDisableTiming));
+  RTCC3_HIP(hipEventCreateWithFlags(&ev_t_, hipEventDisableTiming));
   (void)e;
 }
 
@@ -168,7 +169,7 @@ Triples::~Triples() {
     }
   if (eps_) (void)hipFree(eps_);
   if (s2_) (void)hipStreamSynchronize(s2_);
-  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_})
+  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_, ev_t_})
     if (ev) (void)hipEventDestroy(ev);
   if (s2_) (void)hipStreamDestroy(s2_);
   if (t0_) (void)hipEventDestroy(t0_);
@@ -483,6 +484,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   }
   RTCC3_HIP(hipEventRecord(ev_t3b_, s));
   launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
+  RTCC3_HIP(hipEventRecord(ev_t_, s));  // t3 blocks ready
 
   // ---------------- lambda3 blocks
   {  // W[n][a][(b,c)] = sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)]
@@ -537,6 +539,9 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     cplx* R12 = P("tr_R12", {o, o, o, v});
     const int64_t lR = (int64_t)o * o * v * o;
 
+    // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1); first on the t3
+    // side, where it overlaps the lambda3 build
+    launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
     // The combinations of X2 are read straight from the window: with
     // t_{sigma(ijk)}^{sigma(abc)} = t_ijk^abc, for the block (I,J,K)
     //   Z1[b][c][e] = 2t[c,b,e] - t[c,e,b] - t[e,b,c] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
@@ -592,8 +597,6 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, 0, v2, 0, 0);
       checked_gemm(g, cblh, winlen, lOOOV, oovv, s);
     }
-    // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1)
-    launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
     {  // Y2: sum_de (da|eK)~ lambda[d][b][e] into Y2p[I][J][a][b]; lambda_IJK[d][b][e] =
        // lambda_JIK[b][d][e], read with (d,e) contiguous
       GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
@@ -800,7 +803,9 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     }
   }
   if (density_terms && !w.slabs.empty()) {
-    // D_ij += -1/2 sum_abc t_{ilk} lambda_{jlk}, one batch entry per slab (., l, k)
+    // D_ij += -1/2 sum_abc t_{ilk} lambda_{jlk}, one batch entry per slab (., l, k);
+    // on the lambda3 side, once the t3 blocks are ready
+    RTCC3_HIP(hipStreamWaitEvent(s2, ev_t_, 0));
     cplx* Dij = P("td_Dij", {o, o});
     GemmDesc g = base(o, o, (int)v3, (int)w.slabs.size() / 4, w.d_slabs, pr);
     g.atomic = 1;
@@ -816,7 +821,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     g.C = Dij;
     g.sCm0 = o;
     g.sCn0 = 1;
-    checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s);
+    checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s2);
   }
   // the next window reuses every window buffer: join the lambda3 side
   RTCC3_HIP(hipEventRecord(ev_join_, s2));

@@ -85,6 +85,7 @@ class Triples {
   // ev_l_ / ev_join_ order the two.
   hipStream_t s2_ = nullptr;
   hipEvent_t ev_fork_ = nullptr, ev_l_ = nullptr, ev_join_ = nullptr;
+  hipEvent_t ev_t_ = nullptr;    // t3 blocks ready (D_ij on the lambda3 side reads them)
   hipEvent_t ev_t3b_ = nullptr;  // after the t3 build: both builds are bound by the
                                  // matrix cores, so the lambda3 build follows it
   int nbev_ = 0;                 // pairs recorded in the current run

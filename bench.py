@@ -189,12 +189,13 @@ def main():
                          f"integrals (seed {args.seed}), delta kick {amp} a.u. along z, dt={dt}"),
             "o": o, "v": v, "naux": s.naux, "precision": args.precision,
         },
-        # Dominant kernel: the segmented product that builds a window's t3 (and,
-        # in a second launch, lambda3) blocks before symmetrisation.
+        # Dominant kernel: the segmented store-mode product, launched for a
+        # window's t3 blocks, its lambda3 blocks (before symmetrisation) and
+        # the S intermediate of Y1.
         "roofline": {
             "bound": "mfma",
-            "kernel": "zgemm_kernel<double, false, true, true, 64, true> (t3 and lambda3 build products)"
-            if args.precision == "fp64" else "segmented build products",
+            "kernel": "zgemm_kernel<double, false, true, true, 64, true, 0> (t3, lambda3 and S products)"
+            if args.precision == "fp64" else "segmented products (t3, lambda3, S)",
             "achieved": b_achieved,
             "peak": peak,
             "unit": "TFLOP/s",

@@ -114,9 +114,10 @@ int rtcc3_set_option(rtcc3_ctx *ctx, int option, int value);
 /* Timing of the last rtcc3_propagate (milliseconds, from HIP events on the
  * context's stream): total and the part spent in the triples kernels.
  * kernel_ms[0] = total, [1] = triples, [2] = triples launches counted,
- * [3] = milliseconds in the products that build t3 and lambda3 (eq. cc3-t3 and
- * eq. cc3-l3 before symmetrisation), [4] = their launches, [5] = their
- * algorithmic flops (8 per complex multiply-add). */
+ * [3] = milliseconds in the segmented products that build t3 and lambda3
+ * (eq. cc3-t3 and eq. cc3-l3 before symmetrisation) and the S intermediate of
+ * Y1, [4] = their launches, [5] = their algorithmic flops (8 per complex
+ * multiply-add). */
 int rtcc3_last_timing(rtcc3_ctx *ctx, double kernel_ms[6]);
 
 /* Library self-test of the complex GEMM the contractions run on:

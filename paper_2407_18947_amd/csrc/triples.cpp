@@ -701,7 +701,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, 0, 0, 0, v2o);
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
       const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
+      build_event(s2);  // same kernel as the builds: timed with them
       checked_seg_gemm(g, cblh, lA, lB, lS, s2);
+      build_event(s2);
+      build_flop_ += 8.0 * cn * v * (o * v) * (2 * v);
       // Y1[x][a] -= sum_(c,d) S[n][(c,d)][x] lambda[n][a][(c,d)] for every block of the table
       GemmDesc h = base(o, v, (int)v2, cn, cbl, pr);
       h.atomic = 1;

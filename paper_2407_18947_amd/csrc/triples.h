@@ -60,8 +60,9 @@ class Triples {
     ms = ms_;
     launches = (double)launches_;
   }
-  // The segmented build products (t3 and lambda3): event-timed milliseconds,
-  // launches and algorithmic flops (8 per complex multiply-add).
+  // The segmented store-mode products (the t3 and lambda3 builds and the Y1 S
+  // intermediate, one kernel): event-timed milliseconds, launches and
+  // algorithmic flops (8 per complex multiply-add).
   void build_timing(double& ms, double& launches, double& flop) const {
     ms = build_ms_;
     launches = (double)build_launches_;

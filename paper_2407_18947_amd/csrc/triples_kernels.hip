@@ -99,10 +99,11 @@ __device__ __forceinline__ void wave_sum8(cplx* v, int lane) {
 
 // One workgroup of SW_NW waves per block and chunk of SW_NW rows y
 // (blockIdx.y); wave w owns the row y = SW_NW*chunk + w, lane = z (unit
-// stride, v <= 64), and the wave walks x eight at a time.  Sums over z use
-// wave_sum8 on eight x at once; sums over x stay in registers, so X2b and Zb
-// are complete per workgroup; X1a, Za, X1b (sums over y) go through LDS and
-// are added per chunk.
+// stride, v <= 64), and the wave walks x four at a time (fewer live registers,
+// so the kernel shares the chip with the products that run beside it).  Sums
+// over z use wave_sum8 on the terms of four x at once; sums over x stay in
+// registers, so X2b and Zb are complete per workgroup; X1a, Za, X1b (sums
+// over y) go through LDS and are added per chunk.
 constexpr int SW_NW = 8;
 
 __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* __restrict__ T, const int* __restrict__ bl,
@@ -129,33 +130,40 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
   const cplx lyz = ok ? l2JK[(int64_t)y * v + z] : cplx{0, 0};
   const cplx fz = zin ? fK[z] : cplx{0, 0};
   cplx a3{0, 0}, a4{0, 0}, a5{0, 0};
-  for (int xg = 0; xg < v; xg += 8) {
-    cplx r[8], p1[8], p2[8];
+  for (int xg = 0; xg < v; xg += 4) {
+    // four x at a time: u = (X2a terms, X1a terms), zq = (Za terms, unused)
+    cplx u[8], zq[8];
 #pragma unroll
-    for (int xl = 0; xl < 8; ++xl) {
+    for (int xl = 0; xl < 4; ++xl) {
       const int x = xg + xl;
       const bool xin = x < v;
       const cplx tv = ok && xin ? t[(int64_t)x * v2 + (int64_t)y * v + z] : cplx{0, 0};
-      r[xl] = cmul(tv, fz);
-      p1[xl] = cmul(tv, Lyz);
-      p2[xl] = cmul(tv, lyz);
+      u[xl] = cmul(tv, fz);
+      u[4 + xl] = cmul(tv, Lyz);
+      zq[xl] = cmul(tv, lyz);
+      zq[4 + xl] = cplx{0, 0};
       if (xin) {
         a3 = cadd(a3, cmul(tv, fK[x]));
         a4 = cadd(a4, cmul(tv, yin ? LJy[x] : cplx{0, 0}));
         a5 = cadd(a5, cmul(tv, zin ? l2JK[(int64_t)x * v + z] : cplx{0, 0}));
       }
     }
-    const int xs = xg + (lane >> 3);  // the x a lane's reduced value belongs to
+    const int qi = lane >> 3;                   // the entry a lane's reduced value belongs to
+    const int xs = xg + (qi & 3);               // ... and its x
     if (doX) {
-      // X2a[x][y] = sum_z t[x,y,z] f[z]
-      wave_sum8(r, lane);
-      if ((lane & 7) == 0 && xs < v && yin) catomic(&X2p[(((int64_t)I * o + J) * v + xs) * v + y], r[0]);
-      wave_sum8(p1, lane);
-      if ((lane & 7) == 0 && xs < v) sP[0][w][xs] = p1[0];
+      // X2a[x][y] = sum_z t[x,y,z] f[z] (entries 0..3), X1a[x] per row (entries 4..7)
+      wave_sum8(u, lane);
+      if ((lane & 7) == 0 && xs < v) {
+        if (qi < 4) {
+          if (yin) catomic(&X2p[(((int64_t)I * o + J) * v + xs) * v + y], u[0]);
+        } else {
+          sP[0][w][xs] = u[0];
+        }
+      }
     }
     if (doZ) {
-      wave_sum8(p2, lane);
-      if ((lane & 7) == 0 && xs < v) sP[1][w][xs] = p2[0];
+      wave_sum8(zq, lane);
+      if ((lane & 7) == 0 && qi < 4 && xs < v) sP[1][w][xs] = zq[0];
     }
   }
   // X2b[z][y] = sum_x t[x,y,z] f[x] (subtracted); Zb[y] = sum_xz t l2[x][z] (subtracted)

@@ -107,8 +107,15 @@ int rtcc3_propagate(rtcc3_ctx *ctx, int steps, double dt, const double *field, r
 /* Dipole of the context's current state at field E[3] (host) -> out[3] (host). */
 int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
 
-/* Options: RTCC3_OPT_TRIPLES (1 = CC3, 0 = CCSD model), RTCC3_OPT_PRECISION. */
-enum { RTCC3_OPT_TRIPLES = 1, RTCC3_OPT_PRECISION = 2 };
+/* Options: RTCC3_OPT_TRIPLES (1 = CC3, 0 = CCSD model), RTCC3_OPT_PRECISION,
+ * RTCC3_OPT_WINDOW_BLOCKS: the most ordered occupied triples (i,j,k) whose t3
+ * and lambda3 blocks are held at once (4 * 16 * v^3 bytes each); 0 (default)
+ * sizes the windows from half the free device memory, at most 48 GiB.  Values
+ * below 6 count as 6 (a window holds every ordering of a triple), and the
+ * windows of the density pass hold whole slabs (i,l,k) of an occupied pair
+ * (l,k), about 6*o blocks, however small the value.  The answer does not
+ * depend on it.  Setting it waits for the context's streams. */
+enum { RTCC3_OPT_TRIPLES = 1, RTCC3_OPT_PRECISION = 2, RTCC3_OPT_WINDOW_BLOCKS = 3 };
 int rtcc3_set_option(rtcc3_ctx *ctx, int option, int value);
 
 /* Timing of the last rtcc3_propagate (milliseconds, from HIP events on the

@@ -32,6 +32,19 @@ int Engine::buffer(const std::string& name, int64_t n) {
   return (int)bufs_.size() - 1;
 }
 
+void Engine::release(const std::string& name) {
+  auto it = names_.find(name);
+  if (it == names_.end()) return;
+  RTCC3_HIP(hipStreamSynchronize(stream));
+  Buf& b = bufs_[it->second];
+  if (b.p) RTCC3_HIP(hipFree(b.p));
+  if (b.g) RTCC3_HIP(hipFree(b.g));
+  b.p = b.g = nullptr;
+  b.n = 0;
+  b.rg = false;
+  names_.erase(it);
+}
+
 View Engine::tensor_of(int buf, std::vector<int64_t> shape) {
   View v;
   v.nd = (int)shape.size();

@@ -37,6 +37,9 @@ class Engine {
 
   // Named buffers, allocated once and reused (get-or-create).
   int buffer(const std::string& name, int64_t n);
+  // Free a named buffer after the stream has drained (the name may then be
+  // requested again with another size); views into it become invalid.
+  void release(const std::string& name);
   View tensor(const std::string& name, std::vector<int64_t> shape);  // contiguous, zeroed on request
   View tensor_of(int buf, std::vector<int64_t> shape);
   void zero(const View& v);

@@ -422,6 +422,13 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
     c->tri->set_precision(value);
     return RTCC3_OK;
   }
+  if (option == RTCC3_OPT_WINDOW_BLOCKS) {
+    if (value < 0) return fail(c, RTCC3_EINVAL, "negative window size");
+    return guarded(c, [&]() -> int {
+      c->tri->set_window_blocks(*c->e, value);
+      return RTCC3_OK;
+    });
+  }
   return fail(c, RTCC3_EINVAL, "unknown option");
 }
 

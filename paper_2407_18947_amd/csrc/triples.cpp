@@ -79,25 +79,26 @@ void checked_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t l
   gemm(g, s);
 }
 
-// A gathered-K product (GemmDesc::gk_*) over a window's J groups after the
-// same check for every gathered block and every group's output.
-void checked_gather_gemm(GemmDesc& g, const Window& w, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
-  const int ng = (int)w.gkey.size() / 4;
+// A gathered-K product (GemmDesc::gk_*) over one grouping of a window's
+// contraction blocks after the same check for every gathered block and every
+// group's output.
+void checked_gather_gemm(GemmDesc& g, const Groups& gr, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
+  const int ng = (int)gr.key.size() / 4;
   if (ng == 0) return;
   g.batch = ng;
-  g.bl = w.d_gkey;
-  g.gk_start = w.d_gstart;
-  g.gk_bl = w.d_gbl;
-  RTCC3_CHECK(g.K == g.K0 * w.gmax && g.sAk1 == 0 && g.sBk1 == 0, "triples: bad gathered product");
+  g.bl = gr.d_key;
+  g.gk_start = gr.d_start;
+  g.gk_bl = gr.d_bl;
+  RTCC3_CHECK(g.K == g.K0 * gr.max && g.sAk1 == 0 && g.sBk1 == 0, "triples: bad gathered product");
   const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + (int64_t)(g.K0 - 1) * g.sAk0;
   const int64_t eB = (int64_t)(g.K0 - 1) * g.sBk0 + span(g.N, g.N0, g.sBn1, g.sBn0);
   const int64_t eC = span(g.M, g.M0, g.sCm1, g.sCm0) + span(g.N, g.N0, g.sCn1, g.sCn0);
   auto dot = [](const int64_t* c, const int* q) { return c[0] * q[0] + c[1] * q[1] + c[2] * q[2] + c[3] * q[3]; };
   for (int b = 0; b < ng; ++b) {
-    const int64_t oC = dot(g.cC, &w.gkey[4 * b]);
+    const int64_t oC = dot(g.cC, &gr.key[4 * b]);
     RTCC3_CHECK(oC >= 0 && oC + eC < lenC, "triples: C operand out of bounds");
-    for (int p = w.gstart[b]; p < w.gstart[b + 1]; ++p) {
-      const int64_t oA = dot(g.cA, &w.gbl[4 * p]), oB = dot(g.cB, &w.gbl[4 * p]);
+    for (int p = gr.start[b]; p < gr.start[b + 1]; ++p) {
+      const int64_t oA = dot(g.cA, &gr.bl[4 * p]), oB = dot(g.cB, &gr.bl[4 * p]);
       RTCC3_CHECK(oA >= 0 && oA + eA < lenA, "triples: A operand out of bounds");
       RTCC3_CHECK(oB >= 0 && oB + eB < lenB, "triples: B operand out of bounds");
     }
@@ -155,20 +156,35 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
   (void)e;
 }
 
-Triples::~Triples() {
-  for (auto* ws : {&rhs_windows_, &den_windows_})
+void Triples::free_windows() {
+  for (auto* ws : {&rhs_windows_, &den_windows_}) {
     for (auto& w : *ws) {
-      if (w.d_bl) (void)hipFree(w.d_bl);
-      if (w.d_part) (void)hipFree(w.d_part);
-      if (w.d_owned) (void)hipFree(w.d_owned);
-      if (w.d_canon) (void)hipFree(w.d_canon);
-      if (w.d_slabs) (void)hipFree(w.d_slabs);
-      if (w.d_gkey) (void)hipFree(w.d_gkey);
-      if (w.d_gstart) (void)hipFree(w.d_gstart);
-      if (w.d_gbl) (void)hipFree(w.d_gbl);
+      for (int* p : {w.d_bl, w.d_part, w.d_owned, w.d_canon, w.d_slabs})
+        if (p) (void)hipFree(p);
+      for (Groups* gr : {&w.gJ, &w.gK})
+        for (int* p : {gr->d_key, gr->d_start, gr->d_bl})
+          if (p) (void)hipFree(p);
     }
-  if (eps_) (void)hipFree(eps_);
+    ws->clear();
+  }
+}
+
+void Triples::set_window_blocks(Engine& e, int n) {
+  RTCC3_CHECK(n >= 0, "triples: negative window size");
+  RTCC3_HIP(hipStreamSynchronize(e.stream));
+  RTCC3_HIP(hipStreamSynchronize(s2_));
+  free_windows();
+  for (const char* b : {"tw_W", "tw_Wl", "tw_T", "tw_L", "tw_S"}) e.release(b);
+  wcap_ = n;
+  build_windows();
+  for (auto& w : rhs_windows_) upload(w);
+  for (auto& w : den_windows_) upload(w);
+}
+
+Triples::~Triples() {
   if (s2_) (void)hipStreamSynchronize(s2_);
+  free_windows();
+  if (eps_) (void)hipFree(eps_);
   for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_, ev_t_})
     if (ev) (void)hipEventDestroy(ev);
   if (s2_) (void)hipStreamDestroy(s2_);
@@ -223,6 +239,7 @@ void Triples::build_windows() {
   RTCC3_HIP(hipMemGetInfo(&free_b, &total_b));
   const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)48 << 30, (int64_t)(free_b / 2)));
   int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * v3));
+  if (wcap_ > 0) wmax = std::max(6, std::min(wmax, wcap_));
   // ---- RHS windows: canonical triples i <= j <= k with all their orderings
   std::vector<std::array<int, 3>> cur;
   auto flush = [&]() {
@@ -315,27 +332,30 @@ void Triples::build_windows() {
 }
 
 void Triples::upload(Window& w) {
-  {  // group the contraction blocks by J
-    const std::vector<int>& cb = w.owned.empty() ? w.bl : w.owned;
+  auto put = [](int** d, const std::vector<int>& h) {
+    RTCC3_HIP(hipMalloc(d, sizeof(int) * h.size()));
+    RTCC3_HIP(hipMemcpy(*d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
+  };
+  // group the contraction blocks by J (position 1) and by K (position 2)
+  const std::vector<int>& cb = w.owned.empty() ? w.bl : w.owned;
+  for (int pos : {1, 2}) {
+    Groups& gr = pos == 1 ? w.gJ : w.gK;
     std::map<int, std::vector<int>> by;
-    for (size_t e = 0; e < cb.size(); e += 4) by[cb[e + 1]].push_back((int)e);
-    w.gkey.clear();
-    w.gstart.assign(1, 0);
-    w.gbl.clear();
-    w.gmax = 0;
+    for (size_t e = 0; e < cb.size(); e += 4) by[cb[e + pos]].push_back((int)e);
+    gr.key.clear();
+    gr.start.assign(1, 0);
+    gr.bl.clear();
+    gr.max = 0;
     for (auto& kv : by) {
-      w.gkey.insert(w.gkey.end(), {0, kv.first, 0, 0});
-      for (int e : kv.second) w.gbl.insert(w.gbl.end(), cb.begin() + e, cb.begin() + e + 4);
-      w.gstart.push_back((int)w.gbl.size() / 4);
-      w.gmax = std::max(w.gmax, (int)kv.second.size());
+      gr.key.insert(gr.key.end(), {0, 0, 0, 0});
+      gr.key[gr.key.size() - 4 + pos] = kv.first;
+      for (int e : kv.second) gr.bl.insert(gr.bl.end(), cb.begin() + e, cb.begin() + e + 4);
+      gr.start.push_back((int)gr.bl.size() / 4);
+      gr.max = std::max(gr.max, (int)kv.second.size());
     }
-    auto put = [](int** d, const std::vector<int>& h) {
-      RTCC3_HIP(hipMalloc(d, sizeof(int) * h.size()));
-      RTCC3_HIP(hipMemcpy(*d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
-    };
-    put(&w.d_gkey, w.gkey);
-    put(&w.d_gstart, w.gstart);
-    put(&w.d_gbl, w.gbl);
+    put(&gr.d_key, gr.key);
+    put(&gr.d_start, gr.start);
+    put(&gr.d_bl, gr.bl);
   }
   RTCC3_HIP(hipMalloc(&w.d_bl, sizeof(int) * w.bl.size()));
   RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
@@ -384,6 +404,9 @@ void Triples::blocks(Engine& e, const CCSDResult& r) {
   e.einsum("Pac,Pke->kace", ONE, B('v', 'v'), B('o', 'v'), t);
   t = make("tb_X2b", {o, o, o, v});  // (ki|mc) at [k][m][i][c]
   e.einsum("Pki,Pmc->kmic", ONE, B('o', 'o'), B('o', 'v'), t);
+  t = make("tb_X2c", {o, o, o, v});  // (ki|mc) - 2(mi|kc) at [k][m][i][c]
+  e.einsum("Pki,Pmc->kmic", ONE, B('o', 'o'), B('o', 'v'), t);
+  e.einsum("Pmi,Pkc->kmic", R(-2), B('o', 'o'), B('o', 'v'), t);
   t = make("tb_Y2a", {o, v, v, v});  // (da|el) at [l][a][d][e]
   e.einsum("Pda,Pel->lade", ONE, B('v', 'v'), B('v', 'o'), t);
   t = make("tb_Y2b", {o, o, o, v});  // (xi|dk) at [i][k][x][d]
@@ -428,6 +451,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const cplx* gLD = P("tb_LD", {o, v, o, o});
   const cplx* gX2a = P("tb_X2a", {o, v, v, v});
   const cplx* gX2b = P("tb_X2b", {o, o, o, v});
+  const cplx* gX2c = P("tb_X2c", {o, o, o, v});
   const cplx* gY2a = P("tb_Y2a", {o, v, v, v});
   const cplx* gY2b = P("tb_Y2b", {o, o, o, v});
   const cplx* gG1 = P("tb_G1", {o, o, v, v});
@@ -542,7 +566,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1); first on the t3
     // side, where it overlaps the lambda3 build
     launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
-    // The combinations of X2 are read straight from the window: with
+    // The combinations of X2 in terms of the window's blocks: with
     // t_{sigma(ijk)}^{sigma(abc)} = t_ijk^abc, for the block (I,J,K)
     //   Z1[b][c][e] = 2t[c,b,e] - t[c,e,b] - t[e,b,c] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
     //   Zh[a][b][c] = 2t[c,b,a] - t[b,c,a] - t[a,b,c] = (2 T_KJI - T_KIJ - T_IJK)[a][b][c]
@@ -578,24 +602,37 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
       checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
     }
-    {  // X2: -sum_c Zh[(a,b)][c] (Ki|Ic)~ into X2p[x][J]
-      GemmDesc g = base((int)v2, o, v, cn, cbl, pr);
-      g.atomic = 1;
-      g.alpha = R(-1);
-      g.A = T;  // A[(a,b)][c] = Zh[a][b][c]
+    // X2 -= sum_c Zh[(a,b)][c] G[K][I][c][x] into X2p[x][J], G[k][m][c][x] = (kx|mc)~.
+    // The contraction set holds every ordering of its triples, so each term of
+    // Zh can be summed with its occupied labels renamed until it reads the
+    // block itself:
+    //   -2 T_KJI G[K][I] -> -2 T_IJK G[I][K]   (I <-> K)
+    //      T_KIJ G[K][I] ->    T_IJK G[I][J] into X2p[x][K]   ((K,I,J) -> (I,J,K))
+    //      T_IJK G[K][I] stays.
+    // Two gathered products, over the blocks of each J and of each K, without atomics:
+    auto x2b = [&](const cplx* Bp, const int64_t* cb, const int64_t* cc, const Groups& gr) {
+      GemmDesc g = base((int)v2, o, v * gr.max, 0, nullptr, pr);
+      g.K0 = v;
+      g.A = T;  // A[(a,b)][c] = T_IJK[a][b][c]
       g.sAm0 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, 0, v3);
-      combine(g, 0, 3, 4, 0);
-      g.B = gX2b;
+      g.B = Bp;
       g.sBk0 = 1;
       g.sBn0 = v;
-      set4(g.cB, (int64_t)o * v, 0, (int64_t)o * o * v, 0);
+      std::memcpy(g.cB, cb, sizeof(g.cB));
       g.C = X2p;
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
-      set4(g.cC, 0, v2, 0, 0);
-      checked_gemm(g, cblh, winlen, lOOOV, oovv, s);
+      std::memcpy(g.cC, cc, sizeof(g.cC));
+      checked_gather_gemm(g, gr, winlen, lOOOV, oovv, s);
+    };
+    {
+      // (G[K][I] - 2 G[I][K]) is tb_X2c at [K][I]; G[I][J] is tb_X2b at [I][J]
+      const int64_t cbJ[4] = {(int64_t)o * v, 0, (int64_t)o * o * v, 0}, ccJ[4] = {0, v2, 0, 0};
+      const int64_t cbK[4] = {(int64_t)o * o * v, (int64_t)o * v, 0, 0}, ccK[4] = {0, 0, v2, 0};
+      x2b(gX2c, cbJ, ccJ, w.gJ);
+      x2b(gX2b, cbK, ccK, w.gK);
     }
     {  // Y2: sum_de (da|eK)~ lambda[d][b][e] into Y2p[I][J][a][b]; lambda_IJK[d][b][e] =
        // lambda_JIK[b][d][e], read with (d,e) contiguous
@@ -621,7 +658,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       checked_gemm(g, cblh, lOVVV, winlen, oovv, s2);
     }
     {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J], summed over the blocks of each J
-      GemmDesc g = base((int)v2, o, v * w.gmax, 0, nullptr, pr);
+      GemmDesc g = base((int)v2, o, v * w.gJ.max, 0, nullptr, pr);
       g.K0 = v;
       g.alpha = R(-1);
       g.A = L;
@@ -636,7 +673,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
-      checked_gather_gemm(g, w, winlen, lOOOV, oovv, s2);
+      checked_gather_gemm(g, w.gJ, winlen, lOOOV, oovv, s2);
     }
     // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates over (b,x)
     auto tl = [&](const cplx* Bp, int64_t lenB, int64_t sbk, int64_t sbn, const int64_t* cb, cplx* Cp,
@@ -724,7 +761,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     }
     {  // term 11: Zi[J][b][(d,e)] += sum_c t2[K][I][b][c] lambda[c][(d,e)]   (block (k,i,j) = (I,J,K)),
        // summed over the blocks of each J
-      GemmDesc g = base(v, (int)v2, v * w.gmax, 0, nullptr, pr);
+      GemmDesc g = base(v, (int)v2, v * w.gJ.max, 0, nullptr, pr);
       g.K0 = v;
       g.A = t2;
       g.sAm0 = v;
@@ -738,7 +775,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v2;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
-      checked_gather_gemm(g, w, t2len, winlen, lOVVV, s2);
+      checked_gather_gemm(g, w.gJ, t2len, winlen, lOVVV, s2);
     }
     {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
       GemmDesc g = base(o, v, (int)v2, cn, cbl, pr);

@@ -13,8 +13,22 @@ struct TriplesOut {
   View Dij, Dab, Dia;   // triples part of the T1-frame density (when requested)
 };
 
+// The blocks the right-hand-side contractions run over (all blocks, or the
+// owned ones of a pair window) grouped by one of their occupied indices, for
+// products that reduce over the blocks sharing an output (GemmDesc::gk_*).
+struct Groups {
+  std::vector<int> key;    // [ng][4]: the shared index at its position, zeros elsewhere
+  std::vector<int> start;  // [ng + 1]: group g is bl entries [start[g], start[g+1])
+  std::vector<int> bl;     // [*][4]: (I, J, K, n) in group order
+  int max = 0;             // largest group
+  int* d_key = nullptr;
+  int* d_start = nullptr;
+  int* d_bl = nullptr;
+};
+
 // A window: a set of ordered occupied triples that is closed under permutation,
-// so every block's P_ijk^abc partners are in it.
+// so every block's P_ijk^abc partners are in it.  The contraction set (all
+// blocks, or the owned ones) is a union of whole permutation orbits as well.
 struct Window {
   int nw = 0;                 // ordered blocks
   std::vector<int> bl;        // [nw][4]: I, J, K, n (host copy)
@@ -23,15 +37,7 @@ struct Window {
   std::vector<int> canon;     // [*][4]: I <= J <= K and the slot of that ordering, one per distinct triple
   std::vector<int> slabs;     // density windows: [*][4] = (0, 0, 0, slot of block (0,l,k)); the o blocks
                               // (i,l,k) of a slab occupy consecutive slots in i
-  // The blocks the right-hand-side contractions run over (all blocks, or the
-  // owned ones of a pair window) grouped by their second index J:
-  std::vector<int> gkey;    // [ng][4]: (0, J, 0, 0)
-  std::vector<int> gstart;  // [ng + 1]: group g is gbl entries [gstart[g], gstart[g+1])
-  std::vector<int> gbl;     // [*][4]: (I, J, K, n) in group order
-  int gmax = 0;             // largest group
-  int* d_gkey = nullptr;
-  int* d_gstart = nullptr;
-  int* d_gbl = nullptr;
+  Groups gJ, gK;              // contraction blocks grouped by J and by K
   int* d_bl = nullptr;
   int* d_part = nullptr;
   int* d_owned = nullptr;
@@ -49,6 +55,9 @@ class Triples {
   // the blocks each window owns.
   TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density);
   void set_precision(int p) { prec_ = p; }
+  // Cap the blocks per window (0: sized from free device memory) and rebuild
+  // the windows; the window buffers are released and reallocated on use.
+  void set_window_blocks(Engine& e, int n);
   void reset_timing() {
     ms_ = 0;
     launches_ = 0;
@@ -75,6 +84,7 @@ class Triples {
   double* eps_ = nullptr;  // device
   std::vector<Window> rhs_windows_, den_windows_;
   int max_nw_ = 0;
+  int wcap_ = 0;  // blocks per window requested by the caller (0: from the memory budget)
   double ms_ = 0;
   long launches_ = 0;
   hipEvent_t t0_ = nullptr, t1_ = nullptr;
@@ -94,6 +104,7 @@ class Triples {
 
   void build_windows();
   void upload(Window& w);
+  void free_windows();
   void blocks(Engine& e, const CCSDResult& r);
   void window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_terms, bool density_terms);
 };

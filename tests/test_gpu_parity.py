@@ -35,8 +35,10 @@ def _random_state(o, v, seed, scale=0.1):
     return np.concatenate([x.ravel() for x in (t1, t2, l1, l2)])
 
 
-def _gpu_terms(s, y, E, with_triples, precision=0):
+def _gpu_terms(s, y, E, with_triples, precision=0, window_blocks=0):
     ctx = _lib.Context(s, precision)
+    if window_blocks:
+        ctx.set_option(_lib.RTCC3_OPT_WINDOW_BLOCKS, window_blocks)
     yd = torch.tensor(y, dtype=torch.complex128, device="cuda")
     td = torch.zeros(ctx.terms_size(), dtype=torch.complex128, device="cuda")
     torch.cuda.synchronize()
@@ -97,6 +99,41 @@ def test_triples_terms(o, v):
     r = orc.rhs_terms(m, y, FIELD, triples="explicit" if o * v < 40 else "loop")
     for k in ["X1", "X2", "Y1", "Y2", "D", "mu", "R1", "G2"]:
         _close(k, g[k], r[k].numpy())
+
+
+@pytest.mark.parametrize("o,v,wb", [(3, 4, 6), (5, 19, 30), (15, 10, 400)])
+def test_triples_terms_small_windows(o, v, wb):
+    """A window cap below o^3 splits the density pass into pair windows (each
+    holding the slabs of a few occupied pairs and owning part of their blocks)."""
+    _say(f"triples terms o={o} v={v} window_blocks={wb}")
+    s = make_system(o, v, seed=15)
+    m = orc.Model.from_system(s)
+    y = _random_state(o, v, 7)
+    g = _gpu_terms(s, y, FIELD, 1, window_blocks=wb)
+    r = orc.rhs_terms(m, y, FIELD, triples="explicit" if o * v < 40 else "loop")
+    for k in ["X1", "X2", "Y1", "Y2", "D", "mu"]:
+        _close(k, g[k], r[k].numpy())
+
+
+@pytest.mark.parametrize("wb", [0, 6, 20])
+def test_rhs_matches_oracle_windows(wb):
+    """The right-hand side alone runs over windows of whole canonical triples;
+    caps of 6 and 20 blocks give one or a few triples per window."""
+    o, v = 4, 6
+    _say(f"rhs o={o} v={v} window_blocks={wb}")
+    s = make_system(o, v, seed=16)
+    m = orc.Model.from_system(s)
+    y = _random_state(o, v, 8)
+    ctx = _lib.Context(s)
+    if wb:
+        ctx.set_option(_lib.RTCC3_OPT_WINDOW_BLOCKS, wb)
+    yd = torch.tensor(y, dtype=torch.complex128, device="cuda")
+    dy = torch.zeros_like(yd)
+    torch.cuda.synchronize()
+    _lib.rtcc3_rhs(ctx.ctx, FIELD, yd, dy)
+    ref = orc.rhs(m, y, FIELD, triples="explicit").numpy()
+    _close("dy", dy.cpu().numpy(), ref)
+    ctx.close()
 
 
 def test_rhs_matches_oracle():

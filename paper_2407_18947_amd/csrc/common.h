@@ -117,5 +117,9 @@ struct AxpyDesc {
 void axpy_strided(const AxpyDesc& d, hipStream_t s);
 
 void fill(cplx* p, int64_t n, cplx val, hipStream_t s);
+// dst[0..n) = src[0..n) on the device (non-overlapping).  A kernel on the
+// stream, not a DMA-engine copy, so it orders with the kernels around it
+// without an engine switch.
+void copy(cplx* dst, const cplx* src, int64_t n, hipStream_t s);
 
 }  // namespace rtcc3

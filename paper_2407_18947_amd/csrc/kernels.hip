@@ -675,6 +675,11 @@ __global__ void fill_kernel(cplx* p, int64_t n, cplx v) {
     p[e] = v;
 }
 
+__global__ void copy_kernel(cplx* __restrict__ dst, const cplx* __restrict__ src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
 inline unsigned grid_for(int64_t n, int bs) {
   int64_t g = (n + bs - 1) / bs;
   if (g > 65536) g = 65536;
@@ -848,11 +853,20 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   int ksplit = 1;
   const int64_t wgs = tiles * d.batch;
   constexpr int BKMAX = 32;  // K chunks are multiples of every kernel's K step
-  // A gathered product has few entries with long K: aim at a fuller chip.
-  const int64_t below = d.gk_start ? 2048 : 512, target = d.gk_start ? 2048 : 1024;
-  if (!d.store && wgs < below && d.K >= 4 * BKMAX) {
-    const int64_t want = (target + wgs - 1) / wgs;
-    const int64_t maxs = d.K / (2 * BKMAX);
+  // A gathered product has few entries with long K: aim at a fuller chip.  A
+  // plain product with a handful of tiles splits K down to chunks of 64 for
+  // about 512 workgroups; one that already has half a workgroup per CU splits
+  // only into chunks of at least 512 (short chunks cost more in atomics and
+  // loop overhead than the extra workgroups gain).
+  if (!d.store && d.K >= 4 * BKMAX) {
+    int64_t want = 1, maxs = 1;
+    if (d.gk_start) {
+      if (wgs < 2048) want = (2048 + wgs - 1) / wgs, maxs = d.K / (2 * BKMAX);
+    } else if (wgs < 128) {
+      want = (512 + wgs - 1) / wgs, maxs = d.K / (2 * BKMAX);
+    } else if (wgs < 512) {
+      want = (1024 + wgs - 1) / wgs, maxs = d.K / 512;
+    }
     ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
   }
   if (d.prec != RTCC3_PREC_FP64 && !d.store && !d.gk_start) {
@@ -913,6 +927,12 @@ void axpy_strided(const AxpyDesc& d, hipStream_t s) {
 void fill(cplx* p, int64_t n, cplx val, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, val);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void copy(cplx* dst, const cplx* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
   RTCC3_HIP(hipGetLastError());
 }
 

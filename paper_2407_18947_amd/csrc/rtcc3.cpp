@@ -65,7 +65,7 @@ View sub(cplx* p, int64_t off, std::vector<int64_t> shape) { return Engine::raw(
 void build_h(rtcc3_ctx* c, const double E[3]) {
   Engine& e = *c->e;
   const int64_t n = c->d.n;
-  RTCC3_HIP(hipMemcpyAsync(c->h.p, c->h0.p, sizeof(cplx) * n * n, hipMemcpyDeviceToDevice, c->stream));
+  copy(c->h.p, c->h0.p, n * n, c->stream);
   for (int x = 0; x < 3; ++x)
     if (E[x] != 0.0) e.axpy(C(-E[x]), Engine::raw(c->mu.p + x * n * n, {n, n}), c->h);
 }
@@ -127,7 +127,7 @@ void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const Te
     View m3 = e.tensor("mu3", {3});
     e.zero(m3);
     e.einsum("pq,xpq->x", ONE, D, mut, m3);
-    if (t.mu) RTCC3_HIP(hipMemcpyAsync(t.mu, m3.p, sizeof(cplx) * 3, hipMemcpyDeviceToDevice, c->stream));
+    if (t.mu) copy(t.mu, m3.p, 3, c->stream);
     if (t.terms) {
       cplx* p = t.terms;
       auto put = [&](const View& src, int64_t len) {
@@ -362,9 +362,7 @@ extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double*
     const bool tri = c->with_triples != 0;
     View Y = Engine::raw(c->y, {L}), YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}),
          A = Engine::raw(c->acc, {L});
-    auto copy = [&](cplx* dst, const cplx* src) {
-      RTCC3_HIP(hipMemcpyAsync(dst, src, sizeof(cplx) * L, hipMemcpyDeviceToDevice, c->stream));
-    };
+    auto copyL = [&](cplx* dst, const cplx* src) { copy(dst, src, L, c->stream); };
     c->tri->reset_timing();
     RTCC3_HIP(hipEventRecord(c->ev0, c->stream));
     for (int s = 0; s < steps; ++s) {
@@ -374,16 +372,16 @@ extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double*
       TermsOut t;
       t.mu = mus.p + 3 * s;
       rhs_impl(c, E0, c->y, c->k, t, tri);  // k1 (and mu(t_s))
-      copy(c->acc, c->k);
-      copy(c->ytmp, c->y);
+      copyL(c->acc, c->k);
+      copyL(c->ytmp, c->y);
       e.axpy(C(0.5 * dt), K, YT);
       rhs_impl(c, Eh, c->ytmp, c->k, TermsOut{}, tri);  // k2
       e.axpy(C(2.0), K, A);
-      copy(c->ytmp, c->y);
+      copyL(c->ytmp, c->y);
       e.axpy(C(0.5 * dt), K, YT);
       rhs_impl(c, Eh, c->ytmp, c->k, TermsOut{}, tri);  // k3
       e.axpy(C(2.0), K, A);
-      copy(c->ytmp, c->y);
+      copyL(c->ytmp, c->y);
       e.axpy(C(dt), K, YT);
       rhs_impl(c, E1, c->ytmp, c->k, TermsOut{}, tri);  // k4
       e.axpy(ONE, K, A);

@@ -101,6 +101,25 @@ struct GemmDesc {
   // share an output without atomics.
   const int* gk_start;
   const int* gk_bl;
+  // Column segments (ncs in 1..4, block table required, A read k-fast, K not
+  // split in two levels, atomic accumulation): columns [16s, 16s + cs[s].n) of
+  // the product belong to segment s, which has its own B operand, output and
+  // scale,
+  //   C_s[m][c] += alpha_s * sum_k A[m][k] B_s[k][c],
+  //   B_s[k][c] = cs[s].B[cB_s.(I,J,K,n) + k*sBk + c*sBn],
+  //   C_s[m][c] at cs[s].C[cC_s.(I,J,K,n) + m*sCm + c*sCn],
+  // so products that share their A operand read it once.  N, the plain B/C
+  // fields and alpha are then unused.
+  struct ColSeg {
+    int n;  // columns, 1..16
+    const cplx* B;
+    int64_t cB[4], sBk, sBn;
+    cplx* C;
+    int64_t cC[4], sCm, sCn;
+    cplx alpha;
+  };
+  int ncs;
+  ColSeg cs[4];
 };
 void gemm(const GemmDesc& d, hipStream_t s);
 

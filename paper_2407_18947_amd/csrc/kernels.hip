@@ -77,6 +77,8 @@ struct TileLoader {
   const cplx* Bp[4];
   const cplx* Xc[3];  // bases of the combined operand's blocks
   double wc[3];
+  const cplx* Bq[NNB];   // column segments: B base of each loaded column, and its k stride
+  int sbq[NNB];
   int gs;                // first gathered block of the entry
   int gq0;               // first gathered block of this workgroup's K range
   const int64_t* gofs;   // LDS: A and B offsets of the gathered blocks from gq0 on
@@ -157,6 +159,20 @@ struct TileLoader {
       bval[r] = n < d.N;
       boff[r] = bval[r] ? (int64_t)(n / d.N0) * d.sBn1 + (int64_t)(n % d.N0) * d.sBn0 : 0;
     }
+    if (CMB == 5) {
+      static_assert(CMB != 5 || (!NFB && BN == 64 && NNB == 4), "column segments: B k-fast, 64-wide tiles");
+      // entry r of a thread is column bnn[r] = 16 r + tid / 16, i.e. column
+      // tid / 16 of segment r; masked columns read the entry's own A base
+      const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const GemmDesc::ColSeg& g = d.cs[r];
+        const int c = bnn[r] - 16 * r;
+        bval[r] = r < d.ncs && c < g.n;
+        Bq[r] = bval[r] ? g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n + (int64_t)c * g.sBn : A;
+        sbq[r] = bval[r] ? (int)g.sBk : 0;
+      }
+    }
     return C;
   }
 
@@ -233,7 +249,10 @@ struct TileLoader {
       for (int t = 0; t < NNB; ++t) {
         const int e = NFB ? s : t;
         const bool ok = k < kend && bval[NFB ? 0 : t];
-        bv[e] = CMB == 2 ? fetch3(ok, boff[NFB ? 0 : t] + ko) : fetch(B, ok, boff[NFB ? 0 : t] + ko);
+        if (CMB == 5)
+          bv[e] = fetch(Bq[t], ok, (int64_t)k * sbq[t]);
+        else
+          bv[e] = CMB == 2 ? fetch3(ok, boff[NFB ? 0 : t] + ko) : fetch(B, ok, boff[NFB ? 0 : t] + ko);
       }
     }
   }
@@ -390,6 +409,35 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     __syncthreads();
   }
 
+  if (CMB == 5) {
+    // column segments: the wave's 16-column blocks are segments wn/16 + j
+    const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const bool lo = wn == 0;
+      const GemmDesc::ColSeg& g0 = d.cs[j];
+      const GemmDesc::ColSeg& g1 = d.cs[2 + j];
+      const int sg = (wn >> 4) + j;
+      const int ns = lo ? g0.n : g1.n;
+      const int c = lane & 15;
+      if (sg >= d.ncs || c >= ns) continue;
+      cplx* Cs = lo ? g0.C : g1.C;
+      const int64_t base = lo ? g0.cC[0] * I + g0.cC[1] * J + g0.cC[2] * K + g0.cC[3] * n
+                              : g1.cC[0] * I + g1.cC[1] * J + g1.cC[2] * K + g1.cC[3] * n;
+      const int64_t sCm = lo ? g0.sCm : g1.sCm, sCn = lo ? g0.sCn : g1.sCn;
+      const double alr = lo ? g0.alpha.re : g1.alpha.re, ali = lo ? g0.alpha.im : g1.alpha.im;
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = tm * BM + wm + 16 * i + Frag<T>::row(lane, r);
+          if (row >= d.M) continue;
+          const double xr = (double)cre[i][j][r], xi = (double)cim[i][j][r];
+          atomic_add_cplx(Cs + base + row * sCm + c * sCn, alr * xr - ali * xi, alr * xi + ali * xr);
+        }
+    }
+    return;
+  }
   int64_t co[JB], ro[IB][4];
 #pragma unroll
   for (int j = 0; j < JB; ++j) co[j] = c_off(tn * BN + wn + 16 * j + (lane & 15), d.N, d.N0, d.sCn1, d.sCn0);
@@ -741,6 +789,15 @@ void launch_gather_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit,
 
 template <int MODE, bool ATOMIC>
 void launch_layout(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb, int bn) {
+  if (d.ncs > 0) {
+    if constexpr (ATOMIC && (MODE == RTCC3_PREC_FP64 || MODE == RTCC3_PREC_FP32)) {
+      typedef typename std::conditional<MODE == RTCC3_PREC_FP64, double, float>::type T;
+      hipLaunchKernelGGL((zgemm_kernel<T, true, true, false, 64, false, 5>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+    } else {
+      RTCC3_CHECK(false, "gemm: column segments run in FP64 or FP32 with atomics");
+    }
+    return;
+  }
   if (d.gk_start) {
     if (MODE == RTCC3_PREC_FP64 || MODE == RTCC3_PREC_FP32) launch_gather_gemm<MODE, ATOMIC>(d, grid, s, ksplit, kchunk, kfa, nfb, bn);
   } else if (d.comb_n > 0) {
@@ -822,6 +879,17 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
                     (d0.comb_on == 0 || d0.comb_on == 1),
                 "gemm: bad combined operand");
   }
+  if (d0.ncs > 0) {
+    RTCC3_CHECK(d0.ncs <= 4 && d0.bl && d0.nseg == 0 && d0.comb_n == 0 && !d0.gk_start && !d0.store &&
+                    d0.atomic && d0.K0 == d0.K && d0.M0 == d0.M && d0.sAk0 == 1,
+                "gemm: bad column segments");
+    for (int s = 0; s < d0.ncs; ++s) {
+      const GemmDesc::ColSeg& g = d0.cs[s];
+      RTCC3_CHECK(g.n >= 1 && g.n <= 16 && g.B && g.C && g.sBk >= 0 && g.sBn >= 0 && g.sCm >= 0 && g.sCn >= 0 &&
+                      (int64_t)d0.K * g.sBk < (1LL << 31),
+                  "gemm: bad column segment");
+    }
+  }
   if (d0.gk_start) {
     RTCC3_CHECK(d0.gk_bl && d0.bl && d0.nseg == 0 && d0.comb_n == 0 && d0.K % d0.K0 == 0 && d0.sAk1 == 0 &&
                     d0.sBk1 == 0,
@@ -844,8 +912,9 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   RTCC3_CHECK(!d0.store || !d0.atomic, "gemm: store mode cannot be atomic");
   // A narrow side (at most 16, e.g. one occupied index) goes on N with 64x16
   // tiles; a narrow M is moved there by transposing the product.
-  const bool tr = d0.M <= 16 && d0.N > 16 && d0.nseg == 0 && !d0.gk_start;
-  const GemmDesc d = tr ? transposed(d0) : d0;
+  const bool tr = d0.M <= 16 && d0.N > 16 && d0.nseg == 0 && !d0.gk_start && d0.ncs == 0;
+  GemmDesc d = tr ? transposed(d0) : d0;
+  if (d.ncs > 0) d.N = d.N0 = 64;  // one 64-wide tile of four 16-column segments
   const int bn = d.N <= 16 && d.nseg == 0 ? 16 : 64;  // the segmented kernel has 64-wide tiles
   const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + bn - 1) / bn);
   // Split K across workgroups when the grid is too small to fill the chip and
@@ -896,7 +965,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   // long segmented builds); the other products of a split-precision run use
   // FP32, which is at least as accurate.
   const bool split = d.prec == RTCC3_PREC_BF16X3 || d.prec == RTCC3_PREC_BF16X2;
-  const int prec = split && ((d.nseg == 0 && !d.force_prec) || d.comb_n || d.gk_start) ? RTCC3_PREC_FP32 : d.prec;
+  const int prec = split && ((d.nseg == 0 && !d.force_prec) || d.comb_n || d.gk_start || d.ncs) ? RTCC3_PREC_FP32 : d.prec;
   switch (prec) {
     case RTCC3_PREC_FP64:
       launch_mode<RTCC3_PREC_FP64>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);

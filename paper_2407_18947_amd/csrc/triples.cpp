@@ -132,6 +132,30 @@ void checked_seg_gemm(const GemmDesc& g, const int* bl_host, const int64_t* lenA
   gemm(g, s);
 }
 
+// A column-segment product (GemmDesc::cs) after the same check per segment;
+// lenB[s], lenC[s]: lengths of segment s's B and C tensors.
+void checked_colseg_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, const int64_t* lenB, const int64_t* lenC,
+                         hipStream_t s) {
+  if (g.batch <= 0) return;
+  RTCC3_CHECK(g.bl && g.ncs >= 1 && g.ncs <= 4, "triples: column segments need a block table");
+  const int64_t eA = span(g.M, g.M0, g.sAm1, g.sAm0) + span(g.K, g.K0, g.sAk1, g.sAk0);
+  auto dot = [](const int64_t* c, const int* q) { return c[0] * q[0] + c[1] * q[1] + c[2] * q[2] + c[3] * q[3]; };
+  for (int b = 0; b < g.batch; ++b) {
+    const int* q = bl_host + 4 * b;
+    const int64_t oA = dot(g.cA, q);
+    RTCC3_CHECK(oA >= 0 && oA + eA < lenA, "triples: A operand out of bounds");
+    for (int t = 0; t < g.ncs; ++t) {
+      const GemmDesc::ColSeg& c = g.cs[t];
+      const int64_t oB = dot(c.cB, q), oC = dot(c.cC, q);
+      RTCC3_CHECK(oB >= 0 && oB + (int64_t)(g.K - 1) * c.sBk + (int64_t)(c.n - 1) * c.sBn < lenB[t],
+                  "triples: B segment out of bounds");
+      RTCC3_CHECK(oC >= 0 && oC + (int64_t)(g.M - 1) * c.sCm + (int64_t)(c.n - 1) * c.sCn < lenC[t],
+                  "triples: C segment out of bounds");
+    }
+  }
+  gemm(g, s);
+}
+
 void set4(int64_t* c, int64_t a, int64_t b, int64_t d, int64_t n) {
   c[0] = a;
   c[1] = b;
@@ -675,54 +699,48 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, 0, v2, 0, 0);
       checked_gather_gemm(g, w.gJ, winlen, lOOOV, oovv, s2);
     }
-    // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates over (b,x)
-    auto tl = [&](const cplx* Bp, int64_t lenB, int64_t sbk, int64_t sbn, const int64_t* cb, cplx* Cp,
-                  const int64_t* cc, double alpha, bool tmajor) {
-      // C[b][x] += alpha * sum_{(c,d)} t[b][(c,d)] B[(c,d)][x]   (tmajor: t[n][b][cd])
-      // or, !tmajor: C[d][x] += alpha * sum_{(b,c)} t[(b,c)][d] B[(b,c)][x]
-      GemmDesc g = base(v, o, (int)v2, cn, cbl, pr);
+    // Products that read one block of the window as A[m][(k,l)] (M = v,
+    // K = v^2, unit stride along (k,l)) and differ in B and C run as column
+    // segments of one product: the block is read once for all of them.
+    auto seg_product = [&](const cplx* X, std::initializer_list<GemmDesc::ColSeg> segs, const int64_t* lenB,
+                           const int64_t* lenC, hipStream_t st) {
+      GemmDesc g = base(v, 16 * (int)segs.size(), (int)v2, cn, cbl, pr);
       g.atomic = 1;
-      g.alpha = R(alpha);
-      g.A = T;
-      g.sAm0 = tmajor ? v2 : 1;
-      g.sAk0 = tmajor ? 1 : v;
+      g.A = X;
+      g.sAm0 = v2;
+      g.sAk0 = 1;
       set4(g.cA, 0, 0, 0, v3);
-      g.B = Bp;
-      g.sBk0 = sbk;
-      g.sBn0 = sbn;
-      std::memcpy(g.cB, cb, sizeof(g.cB));
-      g.C = Cp;
-      g.sCm0 = o;
-      g.sCn0 = 1;
-      std::memcpy(g.cC, cc, sizeof(g.cC));
-      checked_gemm(g, cblh, winlen, lenB, lR, s);
+      g.ncs = (int)segs.size();
+      std::copy(segs.begin(), segs.end(), g.cs);
+      checked_colseg_gemm(g, cblh, winlen, lenB, lenC, st);
     };
-    {
-      const int64_t cb1[4] = {(int64_t)o * v2, 0, 0, 0}, cc1[4] = {0, (int64_t)o * v * o, (int64_t)v * o, 0};
-      tl(gG1, lOOVV, 1, v2, cb1, R15, cc1, 1.0, true);    // term 1: (xc|Id)
-      tl(gG5, lOOVV, 1, v2, cb1, R15, cc1, -1.0, false);  // term 5: L_Ibxc
-      const int64_t cb2[4] = {v2, 0, 0, 0};
-      tl(l2, l2len, 1, (int64_t)o * v2, cb2, R2t, cc1, 1.0, true);  // term 2: l2[x][I]
-      const int64_t cb6[4] = {0, 0, v2, 0}, cc6[4] = {(int64_t)o * v * o, (int64_t)v * o, 0, 0};
-      tl(l2, l2len, 1, (int64_t)o * v2, cb6, R6, cc6, 1.0, true);  // term 6: l2[x][K]
-    }
-    {  // terms 7, 8: Q[d][j] = sum_bc lambda[(b,c)][d] t2[j][J][(b,c)] into R8[I][K]
-      // (the term-7 intermediate R7[K][I] is the same sum with the first two indices swapped)
-      GemmDesc g = base(v, o, (int)v2, cn, cbl, pr);
-      g.atomic = 1;
-      g.A = L;
-      g.sAm0 = 1;
-      g.sAk0 = v;
-      set4(g.cA, 0, 0, 0, v3);
-      g.B = t2;
-      g.sBk0 = 1;
-      g.sBn0 = (int64_t)o * v2;
-      set4(g.cB, 0, v2, 0, 0);
-      g.C = R8;
-      g.sCm0 = o;
-      g.sCn0 = 1;
-      set4(g.cC, (int64_t)o * v * o, 0, (int64_t)v * o, 0);
-      checked_gemm(g, cblh, winlen, t2len, lR, s2);
+    auto cseg = [&](const cplx* Bp, std::initializer_list<int64_t> cb, int64_t sbk, int64_t sbn, cplx* Cp,
+                    std::initializer_list<int64_t> cc, int64_t scm, int64_t scn, double alpha) {
+      GemmDesc::ColSeg c;
+      std::memset(&c, 0, sizeof(c));
+      c.n = o;
+      c.B = Bp;
+      std::copy(cb.begin(), cb.end(), c.cB);
+      c.sBk = sbk;
+      c.sBn = sbn;
+      c.C = Cp;
+      std::copy(cc.begin(), cc.end(), c.cC);
+      c.sCm = scm;
+      c.sCn = scn;
+      c.alpha = R(alpha);
+      return c;
+    };
+    {  // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates C[b][x] = sum_(c,d) t[b][(c,d)] B[(c,d)][x].
+       // Term 5 sums t[(b,c)][d] = t_KIJ[d][(b,c)] over the blocks; with the labels renamed
+       // ((K,I,J) -> (I,J,K)) it reads the block itself, into R15[K][I] with G5[J].
+      const int64_t ovo = (int64_t)o * v * o, vo = (int64_t)v * o, ov2 = (int64_t)o * v2;
+      const int64_t lenB[4] = {lOOVV, lOOVV, l2len, l2len}, lenC[4] = {lR, lR, lR, lR};
+      seg_product(T,
+                  {cseg(gG1, {ov2, 0, 0, 0}, 1, v2, R15, {0, ovo, vo, 0}, o, 1, 1.0),     // term 1: (xc|Id)
+                   cseg(gG5, {0, ov2, 0, 0}, 1, v2, R15, {vo, 0, ovo, 0}, o, 1, -1.0),    // term 5: L_Ibxc
+                   cseg(l2, {v2, 0, 0, 0}, 1, ov2, R2t, {0, ovo, vo, 0}, o, 1, 1.0),      // term 2: l2[x][I]
+                   cseg(l2, {0, 0, v2, 0}, 1, ov2, R6, {ovo, vo, 0, 0}, o, 1, 1.0)},      // term 6: l2[x][K]
+                  lenB, lenC, s);
     }
     {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
        //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
@@ -742,22 +760,22 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       checked_seg_gemm(g, cblh, lA, lB, lS, s2);
       build_event(s2);
       build_flop_ += 8.0 * cn * v * (o * v) * (2 * v);
-      // Y1[x][a] -= sum_(c,d) S[n][(c,d)][x] lambda[n][a][(c,d)] for every block of the table
-      GemmDesc h = base(o, v, (int)v2, cn, cbl, pr);
-      h.atomic = 1;
-      h.alpha = R(-1);
-      h.A = S;
-      h.sAm0 = 1;
-      h.sAk0 = o;
-      set4(h.cA, 0, 0, 0, v2 * o);
-      h.B = L;
-      h.sBk0 = 1;
-      h.sBn0 = v2;
-      set4(h.cB, 0, 0, 0, v3);
-      h.C = Y1;
-      h.sCm0 = v;
-      h.sCn0 = 1;
-      checked_gemm(h, cblh, lS, winlen, ov, s2);
+    }
+    {  // One column-segment product over lambda_n[a][(b,c)], after S:
+       //  terms 7, 8: Q[d][j] = sum_bc lambda[(b,c)][d] t2[j][J][(b,c)] into R8[I][K]; with
+       //    lambda[b][c][d] = lambda_KIJ[d][b][c] and the labels renamed ((K,I,J) -> (I,J,K)):
+       //    sum_bc lambda_n[d][(b,c)] t2[j][K][(b,c)] into R8[J][I]
+       //    (the term-7 intermediate R7[K][I] is the same sum with the first two indices swapped);
+       //  Y1[x][a] -= sum_(c,d) lambda_n[a][(c,d)] S[n][(c,d)][x];
+       //  term 12: R12[I][j][J][a] += sum_bc lambda_n[a][(b,c)] t2[j][K][(b,c)]   (block (l,m,k) = (I,J,K)).
+      const int64_t ovo = (int64_t)o * v * o, vo = (int64_t)v * o, ov2 = (int64_t)o * v2;
+      const int64_t lS = (int64_t)max_nw_ * v2 * o;
+      const int64_t lenB[3] = {t2len, lS, t2len}, lenC[3] = {lR, ov, (int64_t)o * o * o * v};
+      seg_product(L,
+                  {cseg(t2, {0, 0, v2, 0}, 1, ov2, R8, {vo, ovo, 0, 0}, o, 1, 1.0),
+                   cseg(S, {0, 0, 0, v2 * o}, o, 1, Y1, {0, 0, 0, 0}, 1, v, -1.0),
+                   cseg(t2, {0, 0, v2, 0}, 1, ov2, R12, {(int64_t)o * o * v, v, 0, 0}, 1, vo, 1.0)},
+                  lenB, lenC, s2);
     }
     {  // term 11: Zi[J][b][(d,e)] += sum_c t2[K][I][b][c] lambda[c][(d,e)]   (block (k,i,j) = (I,J,K)),
        // summed over the blocks of each J
@@ -777,24 +795,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, 0, v3, 0, 0);
       checked_gather_gemm(g, w.gJ, t2len, winlen, lOVVV, s2);
     }
-    {  // term 12: R12[I][j][J][a] += sum_bc t2[j][K][(b,c)] lambda[a][(b,c)]   (block (l,m,k) = (I,J,K))
-      GemmDesc g = base(o, v, (int)v2, cn, cbl, pr);
-      g.atomic = 1;
-      g.A = t2;
-      g.sAm0 = (int64_t)o * v2;
-      g.sAk0 = 1;
-      set4(g.cA, 0, 0, v2, 0);
-      g.B = L;
-      g.sBk0 = 1;
-      g.sBn0 = v2;
-      set4(g.cB, 0, 0, 0, v3);
-      g.C = R12;
-      g.sCm0 = (int64_t)o * v;
-      g.sCn0 = 1;
-      set4(g.cC, (int64_t)o * o * v, v, 0, 0);
-      checked_gemm(g, cblh, t2len, winlen, (int64_t)o * o * o * v, s2);
-    }
-    launches_ += 18;
+    launches_ += 10;
   }
 
   // the density terms read t3 and lambda3: join the lambda3 side's blocks

@@ -848,21 +848,29 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     // on the lambda3 side, once the t3 blocks are ready
     RTCC3_HIP(hipStreamWaitEvent(s2, ev_t_, 0));
     cplx* Dij = P("td_Dij", {o, o});
-    GemmDesc g = base(o, o, (int)v3, (int)w.slabs.size() / 4, w.d_slabs, pr);
-    g.atomic = 1;
-    g.alpha = R(-0.5);
-    g.A = T;
-    g.sAm0 = v3;
-    g.sAk0 = 1;
-    set4(g.cA, 0, 0, 0, v3);
-    g.B = L;
-    g.sBk0 = 1;
-    g.sBn0 = v3;
-    set4(g.cB, 0, 0, 0, v3);
-    g.C = Dij;
-    g.sCm0 = o;
-    g.sCn0 = 1;
-    checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s2);
+    const int nslab = (int)w.slabs.size() / 4;
+    if (o <= 16) {
+      for (int q = 0; q < nslab; ++q)
+        RTCC3_CHECK(w.slabs[4 * q + 3] >= 0 && (int64_t)(w.slabs[4 * q + 3] + o) * v3 <= winlen,
+                    "triples: slab out of bounds");
+      launch_gram(T, L, w.d_slabs, nslab, o, v3, R(-0.5), Dij, s2);
+    } else {
+      GemmDesc g = base(o, o, (int)v3, nslab, w.d_slabs, pr);
+      g.atomic = 1;
+      g.alpha = R(-0.5);
+      g.A = T;
+      g.sAm0 = v3;
+      g.sAk0 = 1;
+      set4(g.cA, 0, 0, 0, v3);
+      g.B = L;
+      g.sBk0 = 1;
+      g.sBn0 = v3;
+      set4(g.cB, 0, 0, 0, v3);
+      g.C = Dij;
+      g.sCm0 = o;
+      g.sCn0 = 1;
+      checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s2);
+    }
   }
   // the next window reuses every window buffer: join the lambda3 side
   RTCC3_HIP(hipEventRecord(ev_join_, s2));

@@ -20,6 +20,11 @@ struct LamElem {
 // every source element first.
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
                      int v, const LamElem* le, hipStream_t s);
+// D[i][j] += alpha * sum_s sum_k A[(slot_s + i)*K + k] B[(slot_s + j)*K + k] for
+// i, j < o <= 16, slot_s = slabs[4 s + 3] (the slab's o blocks are consecutive
+// slots of K elements each).  D is [o][o], accumulated with atomics.
+void launch_gram(const cplx* A, const cplx* B, const int* slabs, int nslab, int o, int64_t K, cplx alpha, cplx* D,
+                 hipStream_t s);
 void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, const cplx* F, const cplx* l2, cplx* X1,
                      cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s);
 

@@ -2,6 +2,8 @@
 // [v,v,v] per ordered occupied triple n, row-major [a][b][c]).
 #include "triples_kernels.h"
 
+#include <algorithm>
+
 namespace rtcc3 {
 
 namespace {
@@ -17,20 +19,12 @@ __device__ __forceinline__ void catomic(cplx* p, cplx x) {
   unsafeAtomicAdd(&p->im, x.im);
 }
 
-// Contractions with one free virtual index per block (I,J,K), all from one
-// coalesced sweep over t[x][y][z] (z fastest), slab by slab in x:
-//   flags&1: X1[I][a]      += sum_bc t[a,b,c] L[J,b,K,c]  - sum_bc t[c,b,a] L[J,b,K,c]
-//            X2p[I,J][a,b] += sum_c  t[a,b,c] f~[K,c]     - sum_c  t[c,b,a] f~[K,c]
-//   flags&2: Z[I][a]       += sum_bc t[a,b,c] l2[J,K,b,c] - sum_bc t[b,a,c] l2[J,K,b,c]
-// In sweep coordinates (x,y,z) the six pieces are: X1a[x] = sum_yz t L[y][z],
-// X1b[z] = sum_xy t L[y][x], X2a[x][y] = sum_z t f[z], X2b[z][y] = sum_x t f[x],
-// Za[x] = sum_yz t l2[y][z], Zb[y] = sum_xz t l2[x][z].
-// Same contractions, one (block, a) per workgroup; used when v*v is too large for
-// the slab buffer of small_t3_kernel.
 // Contractions with one free virtual index per block (I,J,K):
 //   flags&1: X1[I][a]     += sum_bc (t[a,b,c] - t[c,b,a]) L[J,b,K,c]
 //            X2p[I,J][a,b]+= sum_c  (t[a,b,c] - t[c,b,a]) f~[K, c]
 //   flags&2: Z[I][a]      += sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]
+// One (block, a) per workgroup; used when v > 64 (the wave kernel below maps
+// the unit-stride index onto the 64 lanes of a wave).
 __global__ void small_t3_simple_kernel(const cplx* __restrict__ T, const int* __restrict__ bl, const cplx* __restrict__ Lov,
                                 const cplx* __restrict__ F, const cplx* __restrict__ l2, cplx* __restrict__ X1,
                                 cplx* __restrict__ X2p, cplx* __restrict__ Z, int o, int v, int flags) {
@@ -286,6 +280,83 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   }
 }
 
+
+// Gram product of the density's slabs:
+//   D[i][j] += alpha * sum_s sum_k A[(slot_s + i) K + k] B[(slot_s + j) K + k],  i, j < o <= 16,
+// one slab s per blockIdx.y and one K range per blockIdx.x.  A 16x16 output
+// needs one MFMA block, so the four waves split K instead of the output: each
+// stage puts 64 k of the o rows of both operands in LDS (a wave reads one
+// row's 64 consecutive elements), and wave w takes k in [16w, 16w + 16) of it.
+// The four partial sums are added through LDS and the result with atomics.
+constexpr int GR_KC = 64;
+typedef double gr_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gram_kernel(const cplx* __restrict__ A, const cplx* __restrict__ B,
+                                                   const int* __restrict__ slabs, int o, int64_t K, int64_t kchunk,
+                                                   cplx alpha, cplx* __restrict__ D) {
+  __shared__ double sm[2][2][16][GR_KC + 1];  // [A, B][re, im][row][k]
+  const int64_t slot = slabs[4 * blockIdx.y + 3];
+  const int64_t k0 = (int64_t)blockIdx.x * kchunk, k1 = min(K, k0 + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  gr_d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+  // the next stage's elements are loaded into registers while the MFMAs of
+  // the current one run
+  cplx ra[4], rb[4];
+  auto load = [&](int64_t kb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r, row = e / GR_KC, c = e % GR_KC;
+      const bool ok = row < o && kb + c < k1;
+      const int64_t off = ok ? (slot + row) * K + kb + c : 0;
+      ra[r] = ok ? A[off] : cplx{0, 0};
+      rb[r] = ok ? B[off] : cplx{0, 0};
+    }
+  };
+  load(k0);
+  for (int64_t kb = k0; kb < k1; kb += GR_KC) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r, row = e / GR_KC, c = e % GR_KC;
+      sm[0][0][row][c] = ra[r].re;
+      sm[0][1][row][c] = ra[r].im;
+      sm[1][0][row][c] = rb[r].re;
+      sm[1][1][row][c] = rb[r].im;
+    }
+    __syncthreads();
+    if (kb + GR_KC < k1) load(kb + GR_KC);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      // lane l holds A[l%16][k] and, for B^T, B[l%16][k] with k = 16w + 4s + l/16
+      const int m = lane & 15, kk = 16 * w + 4 * s + (lane >> 4);
+      const double ar = sm[0][0][m][kk], ai = sm[0][1][m][kk];
+      const double br = sm[1][0][m][kk], bi = sm[1][1][m][kk];
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, cim, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, cim, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // partial sums of the four waves: result element [4r + l/16][l%16] of register r
+  double* red = &sm[0][0][0][0];  // [wave][re, im][16][16], 16 KB of the 33 KB
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * r + (lane >> 4), j = lane & 15;
+    red[((w * 2 + 0) * 16 + i) * 16 + j] = cre[r];
+    red[((w * 2 + 1) * 16 + i) * 16 + j] = cim[r];
+  }
+  __syncthreads();
+  const int i = tid >> 4, j = tid & 15;
+  if (i < o && j < o) {
+    double xr = 0, xi = 0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      xr += red[((ww * 2 + 0) * 16 + i) * 16 + j];
+      xi += red[((ww * 2 + 1) * 16 + i) * 16 + j];
+    }
+    catomic(&D[i * o + j], cplx{alpha.re * xr - alpha.im * xi, alpha.re * xi + alpha.im * xr});
+  }
+}
 }  // namespace
 
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
@@ -298,6 +369,19 @@ void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const
   } else {
     hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, LamElem{});
   }
+  RTCC3_HIP(hipGetLastError());
+}
+
+void launch_gram(const cplx* A, const cplx* B, const int* slabs, int nslab, int o, int64_t K, cplx alpha, cplx* D,
+                 hipStream_t s) {
+  if (nslab <= 0 || K <= 0) return;
+  RTCC3_CHECK(o >= 1 && o <= 16, "gram: at most 16 rows");
+  // about 2048 workgroups over the slabs, K ranges in whole LDS stages
+  const int64_t per = std::max<int64_t>(1, (2048 + nslab - 1) / nslab);
+  const int64_t kchunk = ((K + per - 1) / per + GR_KC - 1) / GR_KC * GR_KC;
+  const unsigned nx = (unsigned)((K + kchunk - 1) / kchunk);
+  RTCC3_CHECK(nslab < 65536, "gram: too many slabs");
+  hipLaunchKernelGGL(gram_kernel, dim3(nx, (unsigned)nslab), dim3(256), 0, s, A, B, slabs, o, K, kchunk, alpha, D);
   RTCC3_HIP(hipGetLastError());
 }
 

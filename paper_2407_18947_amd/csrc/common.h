@@ -110,6 +110,8 @@ struct GemmDesc {
   //   C_s[m][c] at cs[s].C[cC_s.(I,J,K,n) + m*sCm + c*sCn],
   // so products that share their A operand read it once.  N, the plain B/C
   // fields and alpha are then unused.
+  // With tB set (n <= 15), column 15 of the group is a tail column of its own:
+  //   C_t[m] += talpha * sum_k A[m][k] tB[tcB.(I,J,K,n) + k*tsBk]  at tC[tcC.(I,J,K,n) + m*tsCm].
   struct ColSeg {
     int n;  // columns, 1..16
     const cplx* B;
@@ -117,6 +119,11 @@ struct GemmDesc {
     cplx* C;
     int64_t cC[4], sCm, sCn;
     cplx alpha;
+    const cplx* tB;
+    int64_t tcB[4], tsBk;
+    cplx* tC;
+    int64_t tcC[4], tsCm;
+    cplx talpha;
   };
   int ncs;
   ColSeg cs[4];

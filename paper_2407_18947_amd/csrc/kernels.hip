@@ -168,9 +168,12 @@ struct TileLoader {
       for (int r = 0; r < 4; ++r) {
         const GemmDesc::ColSeg& g = d.cs[r];
         const int c = bnn[r] - 16 * r;
-        bval[r] = r < d.ncs && c < g.n;
-        Bq[r] = bval[r] ? g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n + (int64_t)c * g.sBn : A;
-        sbq[r] = bval[r] ? (int)g.sBk : 0;
+        const bool tail = r < d.ncs && c == 15 && g.tB;
+        bval[r] = r < d.ncs && (c < g.n || tail);
+        Bq[r] = !bval[r] ? A
+                : tail   ? g.tB + g.tcB[0] * I + g.tcB[1] * J + g.tcB[2] * K + g.tcB[3] * n
+                         : g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n + (int64_t)c * g.sBn;
+        sbq[r] = !bval[r] ? 0 : tail ? (int)g.tsBk : (int)g.sBk;
       }
     }
     return C;
@@ -420,12 +423,28 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
       const int sg = (wn >> 4) + j;
       const int ns = lo ? g0.n : g1.n;
       const int c = lane & 15;
-      if (sg >= d.ncs || c >= ns) continue;
-      cplx* Cs = lo ? g0.C : g1.C;
-      const int64_t base = lo ? g0.cC[0] * I + g0.cC[1] * J + g0.cC[2] * K + g0.cC[3] * n
-                              : g1.cC[0] * I + g1.cC[1] * J + g1.cC[2] * K + g1.cC[3] * n;
-      const int64_t sCm = lo ? g0.sCm : g1.sCm, sCn = lo ? g0.sCn : g1.sCn;
-      const double alr = lo ? g0.alpha.re : g1.alpha.re, ali = lo ? g0.alpha.im : g1.alpha.im;
+      const bool tail = c == 15 && (lo ? g0.tB : g1.tB) != nullptr;
+      if (sg >= d.ncs || (c >= ns && !tail)) continue;
+      cplx* Cs;
+      int64_t base, sCm, sCn;
+      double alr, ali;
+      if (tail) {
+        Cs = lo ? g0.tC : g1.tC;
+        base = lo ? g0.tcC[0] * I + g0.tcC[1] * J + g0.tcC[2] * K + g0.tcC[3] * n
+                  : g1.tcC[0] * I + g1.tcC[1] * J + g1.tcC[2] * K + g1.tcC[3] * n;
+        sCm = lo ? g0.tsCm : g1.tsCm;
+        sCn = 0;
+        alr = lo ? g0.talpha.re : g1.talpha.re;
+        ali = lo ? g0.talpha.im : g1.talpha.im;
+      } else {
+        Cs = lo ? g0.C : g1.C;
+        base = lo ? g0.cC[0] * I + g0.cC[1] * J + g0.cC[2] * K + g0.cC[3] * n
+                  : g1.cC[0] * I + g1.cC[1] * J + g1.cC[2] * K + g1.cC[3] * n;
+        sCm = lo ? g0.sCm : g1.sCm;
+        sCn = lo ? g0.sCn : g1.sCn;
+        alr = lo ? g0.alpha.re : g1.alpha.re;
+        ali = lo ? g0.alpha.im : g1.alpha.im;
+      }
 #pragma unroll
       for (int i = 0; i < IB; ++i)
 #pragma unroll
@@ -888,6 +907,8 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
       RTCC3_CHECK(g.n >= 1 && g.n <= 16 && g.B && g.C && g.sBk >= 0 && g.sBn >= 0 && g.sCm >= 0 && g.sCn >= 0 &&
                       (int64_t)d0.K * g.sBk < (1LL << 31),
                   "gemm: bad column segment");
+      RTCC3_CHECK(!g.tB || (g.n <= 15 && g.tC && g.tsBk >= 0 && g.tsCm >= 0 && (int64_t)d0.K * g.tsBk < (1LL << 31)),
+                  "gemm: bad tail column");
     }
   }
   if (d0.gk_start) {

@@ -133,7 +133,8 @@ void checked_seg_gemm(const GemmDesc& g, const int* bl_host, const int64_t* lenA
 }
 
 // A column-segment product (GemmDesc::cs) after the same check per segment;
-// lenB[s], lenC[s]: lengths of segment s's B and C tensors.
+// lenB[s], lenC[s]: lengths of segment s's B and C tensors, lenB[4 + s],
+// lenC[4 + s] those of its tail column's (when it has one).
 void checked_colseg_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, const int64_t* lenB, const int64_t* lenC,
                          hipStream_t s) {
   if (g.batch <= 0) return;
@@ -151,6 +152,11 @@ void checked_colseg_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, co
                   "triples: B segment out of bounds");
       RTCC3_CHECK(oC >= 0 && oC + (int64_t)(g.M - 1) * c.sCm + (int64_t)(c.n - 1) * c.sCn < lenC[t],
                   "triples: C segment out of bounds");
+      if (c.tB) {
+        const int64_t tB = dot(c.tcB, q), tC = dot(c.tcC, q);
+        RTCC3_CHECK(tB >= 0 && tB + (int64_t)(g.K - 1) * c.tsBk < lenB[4 + t], "triples: tail B out of bounds");
+        RTCC3_CHECK(tC >= 0 && tC + (int64_t)(g.M - 1) * c.tsCm < lenC[4 + t], "triples: tail C out of bounds");
+      }
     }
   }
   gemm(g, s);
@@ -177,6 +183,7 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
   RTCC3_HIP(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_t3b_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_t_, hipEventDisableTiming));
+  RTCC3_HIP(hipEventCreateWithFlags(&ev_l3b_, hipEventDisableTiming));
   (void)e;
 }
 
@@ -209,7 +216,7 @@ Triples::~Triples() {
   if (s2_) (void)hipStreamSynchronize(s2_);
   free_windows();
   if (eps_) (void)hipFree(eps_);
-  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_, ev_t_})
+  for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_, ev_t_, ev_l3b_})
     if (ev) (void)hipEventDestroy(ev);
   if (s2_) (void)hipStreamDestroy(s2_);
   if (t0_) (void)hipEventDestroy(t0_);
@@ -428,9 +435,25 @@ void Triples::blocks(Engine& e, const CCSDResult& r) {
   e.einsum("Pac,Pke->kace", ONE, B('v', 'v'), B('o', 'v'), t);
   t = make("tb_X2b", {o, o, o, v});  // (ki|mc) at [k][m][i][c]
   e.einsum("Pki,Pmc->kmic", ONE, B('o', 'o'), B('o', 'v'), t);
-  t = make("tb_X2c", {o, o, o, v});  // (ki|mc) - 2(mi|kc) at [k][m][i][c]
+  t = make("tb_X2c", {o, o, o, v});  // (ki|mc) - 2(mi|kc) at [k][m][i][c] (+ the f~ term below)
   e.einsum("Pki,Pmc->kmic", ONE, B('o', 'o'), B('o', 'v'), t);
   e.einsum("Pmi,Pkc->kmic", R(-2), B('o', 'o'), B('o', 'v'), t);
+  if (o <= 15) {
+    // The f~ term of X2, sum_c (t[a,b,c] - t[c,b,a]) f~_kc into X2p[I][J], goes through
+    // the same gathered product: its second part relabelled (t_IJK[c][b][a] = t_KJI[a][b][c],
+    // then I <-> K), both read the block itself, so
+    //   X2c[k][m][i][c] += delta_im f~_kc - delta_ik f~_mc.
+    auto bcast = [&](int64_t s0, int64_t s1) {  // f~[.][o + c] over (k, m, c) with strides s0, s1
+      View x;
+      x.nd = 3;
+      x.sh[0] = o, x.sh[1] = o, x.sh[2] = v;
+      x.st[0] = s0, x.st[1] = s1, x.st[2] = 1;
+      x.p = r.F.p + o;
+      return x;
+    };
+    e.axpy(ONE, bcast(n, 0), Engine::diag(t, 1, 2));   // [k][m][m][c] += f~_kc
+    e.axpy(R(-1), bcast(0, n), Engine::diag(t, 0, 2));  // [k][m][k][c] -= f~_mc
+  }
   t = make("tb_Y2a", {o, v, v, v});  // (da|el) at [l][a][d][e]
   e.einsum("Pda,Pel->lade", ONE, B('v', 'v'), B('v', 'o'), t);
   t = make("tb_Y2b", {o, o, o, v});  // (xi|dk) at [i][k][x][d]
@@ -559,6 +582,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     checked_seg_gemm(g, blh, lA, lB, winlen, s2);
     build_event(s2);
     build_flop_ += 8.0 * nw * v * v2 * (2 * o + 2 * v);
+    RTCC3_HIP(hipEventRecord(ev_l3b_, s2));
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
@@ -587,9 +611,14 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     cplx* R12 = P("tr_R12", {o, o, o, v});
     const int64_t lR = (int64_t)o * o * v * o;
 
-    // X1, the f~ term of X2, and Z34 (terms 3 and 4 of Y1); first on the t3
-    // side, where it overlaps the lambda3 build
-    launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
+    // X1, the f~ term of X2 and Z34 (terms 3 and 4 of Y1): with o <= 15 they ride
+    // along with products that read the block anyway (tail columns of the Y1
+    // product below; the f~ term inside tb_X2c); else one sweep per block
+    const bool tails = o <= 15;
+    if (!tails) launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
+    // the t3 side's products are bound by the matrix cores like the lambda3
+    // build: they start once it is done
+    RTCC3_HIP(hipStreamWaitEvent(s, ev_l3b_, 0));
     // The combinations of X2 in terms of the window's blocks: with
     // t_{sigma(ijk)}^{sigma(abc)} = t_ijk^abc, for the block (I,J,K)
     //   Z1[b][c][e] = 2t[c,b,e] - t[c,e,b] - t[e,b,c] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
@@ -730,17 +759,38 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       c.alpha = R(alpha);
       return c;
     };
+    auto tail = [&](GemmDesc::ColSeg& c, const cplx* Bp, std::initializer_list<int64_t> cb, cplx* Cp,
+                    std::initializer_list<int64_t> cc, double alpha) {
+      c.tB = Bp;
+      std::copy(cb.begin(), cb.end(), c.tcB);
+      c.tsBk = 1;
+      c.tC = Cp;
+      std::copy(cc.begin(), cc.end(), c.tcC);
+      c.tsCm = 1;
+      c.talpha = R(alpha);
+    };
     {  // Y1 terms 1, 2, 5, 6: per block (j,k,l) = (I,J,K), intermediates C[b][x] = sum_(c,d) t[b][(c,d)] B[(c,d)][x].
        // Term 5 sums t[(b,c)][d] = t_KIJ[d][(b,c)] over the blocks; with the labels renamed
        // ((K,I,J) -> (I,J,K)) it reads the block itself, into R15[K][I] with G5[J].
       const int64_t ovo = (int64_t)o * v * o, vo = (int64_t)v * o, ov2 = (int64_t)o * v2;
-      const int64_t lenB[4] = {lOOVV, lOOVV, l2len, l2len}, lenC[4] = {lR, lR, lR, lR};
-      seg_product(T,
-                  {cseg(gG1, {ov2, 0, 0, 0}, 1, v2, R15, {0, ovo, vo, 0}, o, 1, 1.0),     // term 1: (xc|Id)
-                   cseg(gG5, {0, ov2, 0, 0}, 1, v2, R15, {vo, 0, ovo, 0}, o, 1, -1.0),    // term 5: L_Ibxc
-                   cseg(l2, {v2, 0, 0, 0}, 1, ov2, R2t, {0, ovo, vo, 0}, o, 1, 1.0),      // term 2: l2[x][I]
-                   cseg(l2, {0, 0, v2, 0}, 1, ov2, R6, {ovo, vo, 0, 0}, o, 1, 1.0)},      // term 6: l2[x][K]
-                  lenB, lenC, s);
+      const int64_t lenB[8] = {lOOVV, lOOVV, l2len, l2len, lOOVV, lOOVV, l2len, l2len};
+      const int64_t lenC[8] = {lR, lR, lR, lR, ov, ov, ov, ov};
+      GemmDesc::ColSeg c1 = cseg(gG1, {ov2, 0, 0, 0}, 1, v2, R15, {0, ovo, vo, 0}, o, 1, 1.0);   // term 1: (xc|Id)
+      GemmDesc::ColSeg c5 = cseg(gG5, {0, ov2, 0, 0}, 1, v2, R15, {vo, 0, ovo, 0}, o, 1, -1.0);  // term 5: L_Ibxc
+      GemmDesc::ColSeg c2 = cseg(l2, {v2, 0, 0, 0}, 1, ov2, R2t, {0, ovo, vo, 0}, o, 1, 1.0);    // term 2: l2[x][I]
+      GemmDesc::ColSeg c6 = cseg(l2, {0, 0, v2, 0}, 1, ov2, R6, {ovo, vo, 0, 0}, o, 1, 1.0);     // term 6: l2[x][K]
+      if (tails) {
+        // X1[I][a] += sum_bc t[a][b][c] L_JbKc, and -sum_bc t[c][b][a] L_JbKc relabelled
+        // (t_IJK[c][b][a] = t_KJI[a][b][c], then I <-> K) into X1[K] with L_JbIc;
+        // Z34[I][a] += sum_bc t[a][b][c] l2[J][K][b][c], and -sum_bc t[b][a][c] l2[J][K][b][c]
+        // relabelled (t_IJK[b][a][c] = t_JIK[a][b][c], then I <-> J) into Z34[J] with l2[I][K].
+        // L_JbKc = (tb_G5)[J][K][b][c].
+        tail(c1, gG5, {0, ov2, v2, 0}, X1, {v, 0, 0, 0}, 1.0);
+        tail(c5, gG5, {v2, ov2, 0, 0}, X1, {0, 0, v, 0}, -1.0);
+        tail(c2, l2, {0, ov2, v2, 0}, Z34, {v, 0, 0, 0}, 1.0);
+        tail(c6, l2, {ov2, 0, v2, 0}, Z34, {0, v, 0, 0}, -1.0);
+      }
+      seg_product(T, {c1, c5, c2, c6}, lenB, lenC, s);
     }
     {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
        //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)

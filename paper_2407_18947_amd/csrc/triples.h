@@ -99,6 +99,8 @@ class Triples {
   hipEvent_t ev_t_ = nullptr;    // t3 blocks ready (D_ij on the lambda3 side reads them)
   hipEvent_t ev_t3b_ = nullptr;  // after the t3 build: both builds are bound by the
                                  // matrix cores, so the lambda3 build follows it
+  hipEvent_t ev_l3b_ = nullptr;  // after the lambda3 build: the t3 side's products wait for it
+                                 // and only the t3 symmetrisation runs beside it
   int nbev_ = 0;                 // pairs recorded in the current run
   void build_event(hipStream_t s);
 

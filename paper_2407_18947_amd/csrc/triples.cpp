@@ -730,18 +730,46 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     }
     // Products that read one block of the window as A[m][(k,l)] (M = v,
     // K = v^2, unit stride along (k,l)) and differ in B and C run as column
-    // segments of one product: the block is read once for all of them.
-    auto seg_product = [&](const cplx* X, std::initializer_list<GemmDesc::ColSeg> segs, const int64_t* lenB,
-                           const int64_t* lenC, hipStream_t st) {
-      GemmDesc g = base(v, 16 * (int)segs.size(), (int)v2, cn, cbl, pr);
-      g.atomic = 1;
-      g.A = X;
-      g.sAm0 = v2;
-      g.sAk0 = 1;
-      set4(g.cA, 0, 0, 0, v3);
-      g.ncs = (int)segs.size();
-      std::copy(segs.begin(), segs.end(), g.cs);
-      checked_colseg_gemm(g, cblh, winlen, lenB, lenC, st);
+    // segments of one product: the block is read once for all of them.  A
+    // product wider than 16 columns (o > 16) takes several segments, and more
+    // than four segments take several launches.
+    struct SegSpec {
+      GemmDesc::ColSeg c;
+      int64_t lenB, lenC, tlenB, tlenC;  // lengths of the B and C tensors (and the tail's)
+    };
+    auto seg_product = [&](const cplx* X, const std::vector<SegSpec>& specs, hipStream_t st) {
+      std::vector<SegSpec> parts;
+      for (const SegSpec& sp : specs)
+        for (int c0 = 0; c0 < sp.c.n; c0 += 16) {
+          SegSpec q = sp;
+          q.c.n = std::min(16, sp.c.n - c0);
+          q.c.B = sp.c.B + c0 * sp.c.sBn;
+          q.lenB = sp.lenB - c0 * sp.c.sBn;
+          q.c.C = sp.c.C + c0 * sp.c.sCn;
+          q.lenC = sp.lenC - c0 * sp.c.sCn;
+          if (c0 > 0) q.c.tB = nullptr, q.c.tC = nullptr;
+          parts.push_back(q);
+        }
+      for (size_t p0 = 0; p0 < parts.size(); p0 += 4) {
+        const int ns = (int)std::min<size_t>(4, parts.size() - p0);
+        GemmDesc g = base(v, 16 * ns, (int)v2, cn, cbl, pr);
+        g.atomic = 1;
+        g.A = X;
+        g.sAm0 = v2;
+        g.sAk0 = 1;
+        set4(g.cA, 0, 0, 0, v3);
+        g.ncs = ns;
+        int64_t lenB[8] = {0}, lenC[8] = {0};
+        for (int t = 0; t < ns; ++t) {
+          const SegSpec& q = parts[p0 + t];
+          g.cs[t] = q.c;
+          lenB[t] = q.lenB;
+          lenC[t] = q.lenC;
+          lenB[4 + t] = q.tlenB;
+          lenC[4 + t] = q.tlenC;
+        }
+        checked_colseg_gemm(g, cblh, winlen, lenB, lenC, st);
+      }
     };
     auto cseg = [&](const cplx* Bp, std::initializer_list<int64_t> cb, int64_t sbk, int64_t sbn, cplx* Cp,
                     std::initializer_list<int64_t> cc, int64_t scm, int64_t scn, double alpha) {
@@ -773,8 +801,6 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
        // Term 5 sums t[(b,c)][d] = t_KIJ[d][(b,c)] over the blocks; with the labels renamed
        // ((K,I,J) -> (I,J,K)) it reads the block itself, into R15[K][I] with G5[J].
       const int64_t ovo = (int64_t)o * v * o, vo = (int64_t)v * o, ov2 = (int64_t)o * v2;
-      const int64_t lenB[8] = {lOOVV, lOOVV, l2len, l2len, lOOVV, lOOVV, l2len, l2len};
-      const int64_t lenC[8] = {lR, lR, lR, lR, ov, ov, ov, ov};
       GemmDesc::ColSeg c1 = cseg(gG1, {ov2, 0, 0, 0}, 1, v2, R15, {0, ovo, vo, 0}, o, 1, 1.0);   // term 1: (xc|Id)
       GemmDesc::ColSeg c5 = cseg(gG5, {0, ov2, 0, 0}, 1, v2, R15, {vo, 0, ovo, 0}, o, 1, -1.0);  // term 5: L_Ibxc
       GemmDesc::ColSeg c2 = cseg(l2, {v2, 0, 0, 0}, 1, ov2, R2t, {0, ovo, vo, 0}, o, 1, 1.0);    // term 2: l2[x][I]
@@ -790,7 +816,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
         tail(c2, l2, {0, ov2, v2, 0}, Z34, {v, 0, 0, 0}, 1.0);
         tail(c6, l2, {ov2, 0, v2, 0}, Z34, {0, v, 0, 0}, -1.0);
       }
-      seg_product(T, {c1, c5, c2, c6}, lenB, lenC, s);
+      seg_product(T,
+                  {{c1, lOOVV, lR, lOOVV, ov}, {c5, lOOVV, lR, lOOVV, ov}, {c2, l2len, lR, l2len, ov},
+                   {c6, l2len, lR, l2len, ov}},
+                  s);
     }
     {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
        //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
@@ -820,12 +849,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
        //  term 12: R12[I][j][J][a] += sum_bc lambda_n[a][(b,c)] t2[j][K][(b,c)]   (block (l,m,k) = (I,J,K)).
       const int64_t ovo = (int64_t)o * v * o, vo = (int64_t)v * o, ov2 = (int64_t)o * v2;
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
-      const int64_t lenB[3] = {t2len, lS, t2len}, lenC[3] = {lR, ov, (int64_t)o * o * o * v};
+      const int64_t lR12 = (int64_t)o * o * o * v;
       seg_product(L,
-                  {cseg(t2, {0, 0, v2, 0}, 1, ov2, R8, {vo, ovo, 0, 0}, o, 1, 1.0),
-                   cseg(S, {0, 0, 0, v2 * o}, o, 1, Y1, {0, 0, 0, 0}, 1, v, -1.0),
-                   cseg(t2, {0, 0, v2, 0}, 1, ov2, R12, {(int64_t)o * o * v, v, 0, 0}, 1, vo, 1.0)},
-                  lenB, lenC, s2);
+                  {{cseg(t2, {0, 0, v2, 0}, 1, ov2, R8, {vo, ovo, 0, 0}, o, 1, 1.0), t2len, lR, 0, 0},
+                   {cseg(S, {0, 0, 0, v2 * o}, o, 1, Y1, {0, 0, 0, 0}, 1, v, -1.0), lS, ov, 0, 0},
+                   {cseg(t2, {0, 0, v2, 0}, 1, ov2, R12, {(int64_t)o * o * v, v, 0, 0}, 1, vo, 1.0), t2len, lR12, 0, 0}},
+                  s2);
     }
     {  // term 11: Zi[J][b][(d,e)] += sum_c t2[K][I][b][c] lambda[c][(d,e)]   (block (k,i,j) = (I,J,K)),
        // summed over the blocks of each J

@@ -89,7 +89,10 @@ def test_ccsd_terms(o, v):
         _close(k, g[k], r[k].numpy())
 
 
-@pytest.mark.parametrize("o,v", [(1, 4), (2, 3), (3, 4), (4, 7), (5, 19), (15, 10)])
+@pytest.mark.parametrize("o,v", [(1, 4), (2, 3), (3, 4), (4, 7), (5, 19), (15, 10),
+                                 # o = 16: X1 and Z by the separate sweep, D_ij on 16 rows;
+                                 # o = 17: D_ij by the general product as well
+                                 (16, 3), (17, 2)])
 def test_triples_terms(o, v):
     _say(f"triples terms o={o} v={v}")
     s = make_system(o, v, seed=12)

@@ -19,8 +19,27 @@ constexpr cplx ONE{1.0, 0.0};
 inline cplx R(double x) { return cplx{x, 0.0}; }
 }  // namespace
 
+namespace {
+CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
+                        const View& ones_o, bool want_grad);
+}  // namespace
+
 CCSDResult ccsd_evaluate(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
                          const View& ones_o, bool want_grad) {
+  CCSDResult r = forward_impl(e, d, y, h, B, I, ones_o, want_grad);
+  if (want_grad) ccsd_backward(e, d, y, ones_o, r);
+  return r;
+}
+
+CCSDResult ccsd_forward(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
+                        const View& ones_o) {
+  return forward_impl(e, d, y, h, B, I, ones_o, true);
+}
+
+namespace {
+
+CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
+                        const View& ones_o, bool want_grad) {
   const int64_t o = d.o, v = d.v, n = d.n, na = d.naux;
   const int64_t ov = o * v, oovv = o * o * v * v;
   CCSDResult r;
@@ -146,26 +165,43 @@ CCSDResult ccsd_evaluate(Engine& e, const Dims& d, const cplx* y, const View& h,
   r.Y = Y;
   r.R1 = R1;
   r.R2 = R2;
-  if (!want_grad) return r;
+  if (want_grad) e.tape_end();
+  return r;
+}
 
-  e.tape_end();
+}  // namespace
+
+void ccsd_backward(Engine& e, const Dims& d, const cplx* y, const View& ones_o, CCSDResult& r) {
+  const int64_t o = d.o, v = d.v, n = d.n;
+  const int64_t ov = o * v, oovv = o * o * v * v;
+  auto blk = [&](const View& x, char a, char b) {
+    auto rng = [&](char c, int64_t& lo, int64_t& hi) {
+      lo = (c == 'o') ? 0 : o;
+      hi = (c == 'o') ? o : n;
+    };
+    int64_t l0, h0, l1, h1;
+    rng(a, l0, h0);
+    rng(b, l1, h1);
+    return Engine::slice(Engine::slice(x, x.nd - 2, l0, h0), x.nd - 1, l1, h1);
+  };
+  const View t1 = e.tensor("t1", {o, v}), t2 = e.tensor("t2", {o, o, v, v});
+  const View ht = e.tensor("ht", {n, n}), Lov = e.tensor("Lov", {o, v, o, v});
 
   // ---- reverse sweep.  Seeds: dL/dOmega1 = l1, dL/dOmega2 = 1/2 l2, and the
   // energy E = sum_i (h~_ii + F_ii) + sum_ijab t_ij^ab L_iajb contributes
   // dE/dh~_ii = dE/dF_ii = 1 (occupied i) and dE/dt2 = L.
   e.zero_grads();
-  View gR1 = e.grad(R1), gR2 = e.grad(R2);
+  View gR1 = e.grad(r.R1), gR2 = e.grad(r.R2);
   copy(gR1.p, y + ov + oovv, ov, e.stream);
   View l2 = Engine::raw(const_cast<cplx*>(y) + 2 * ov + oovv, {o, o, v, v});
   e.axpy(R(0.5), l2, gR2);
-  e.axpy(ONE, ones_o, Engine::diag(blk(e.grad(F), 'o', 'o'), 0, 1));
+  e.axpy(ONE, ones_o, Engine::diag(blk(e.grad(r.F), 'o', 'o'), 0, 1));
   e.axpy(ONE, ones_o, Engine::diag(blk(e.grad(ht), 'o', 'o'), 0, 1));
   e.axpy(ONE, Engine::permute(Lov, {0, 2, 1, 3}), e.grad(t2));
   e.backward();
   r.G1 = e.grad(t1);
   r.G2 = e.grad(t2);
   r.Dt = e.grad(ht);
-  return r;
 }
 
 cplx ccsd_energy(Engine& e, const Dims& d, const CCSDResult& r) {

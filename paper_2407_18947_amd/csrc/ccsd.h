@@ -22,8 +22,16 @@ struct CCSDResult {
 
 // Evaluate with t1, t2 and lambda seeds taken from the state vector y (device).
 // h: bare one-electron operator including the field [n,n] (complex view).
+// want_grad: also the reverse sweep (G1, G2, Dt).
 CCSDResult ccsd_evaluate(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B,
                          const View& I, const View& ones_o, bool want_grad);
+// The two halves of ccsd_evaluate(..., true): the forward program (recorded),
+// and the reverse sweep that fills r.G1, r.G2, r.Dt.  The sweep reads only the
+// engine buffers of the forward program and y, and writes gradient buffers, so
+// it may run on another stream while other work reads those buffers.
+CCSDResult ccsd_forward(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
+                        const View& ones_o);
+void ccsd_backward(Engine& e, const Dims& d, const cplx* y, const View& ones_o, CCSDResult& r);
 
 // Energy of the CCSD part (for tests): E = sum_i (h~_ii + F~_ii) + sum t2 L.
 cplx ccsd_energy(Engine& e, const Dims& d, const CCSDResult& r);

@@ -132,7 +132,8 @@ View Engine::diag(View v, int d0, int d1) {
 
 cplx* Engine::scratch(int64_t n) {
   if (n > scratch_n_) {
-    RTCC3_HIP(hipStreamSynchronize(stream));
+    // work on any stream may still read the old scratch
+    RTCC3_HIP(hipDeviceSynchronize());
     if (scratch_) RTCC3_HIP(hipFree(scratch_));
     scratch_ = nullptr;
     hipError_t e = hipMalloc(&scratch_, sizeof(cplx) * n);

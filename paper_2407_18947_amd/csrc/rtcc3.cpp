@@ -29,6 +29,9 @@ struct rtcc3_ctx {
   int64_t mus_n = 0;
   std::string err;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // the CCSD reverse sweep runs on side_stream beside the triples windows
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_side1 = nullptr;
 };
 
 namespace {
@@ -82,12 +85,29 @@ void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const Te
   const int64_t o = d.o, v = d.v, n = d.n;
   const int64_t ov = o * v, oovv = o * o * v * v;
   build_h(c, E);
-  CCSDResult r = ccsd_evaluate(e, d, y, c->h, c->B, c->I, c->ones_o, true);
+  CCSDResult r = ccsd_forward(e, d, y, c->h, c->B, c->I, c->ones_o);
   const bool want_density = t.terms || t.mu;
 
   TriplesOut to;
   if (with_triples) {
-    to = c->tri->run(e, d, r, y, want_density);
+    // the reverse sweep needs only the forward program: it runs on the side
+    // stream beside the triples contractions (after the first lambda3 build,
+    // which itself follows the forward program)
+    to = c->tri->run(e, d, r, y, want_density, [&](hipEvent_t after) -> hipEvent_t {
+      RTCC3_HIP(hipStreamWaitEvent(c->side_stream, after, 0));
+      e.stream = c->side_stream;
+      try {
+        ccsd_backward(e, d, y, c->ones_o, r);
+      } catch (...) {
+        e.stream = c->stream;
+        throw;
+      }
+      e.stream = c->stream;
+      RTCC3_HIP(hipEventRecord(c->ev_side1, c->side_stream));
+      return c->ev_side1;
+    });
+  } else {
+    ccsd_backward(e, d, y, c->ones_o, r);
   }
 
   if (dy) {
@@ -215,6 +235,8 @@ extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const do
     }
     RTCC3_HIP(hipEventCreate(&c->ev0));
     RTCC3_HIP(hipEventCreate(&c->ev1));
+    RTCC3_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+    RTCC3_HIP(hipEventCreateWithFlags(&c->ev_side1, hipEventDisableTiming));
     c->e.reset(new Engine(c->stream));
     Engine& e = *c->e;
     // constants in complex form
@@ -445,6 +467,9 @@ extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
   c->e.reset();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
+  if (c->ev_side1) (void)hipEventDestroy(c->ev_side1);
+  if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
   if (c->mus) (void)hipFree(c->mus);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;

@@ -583,6 +583,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     build_event(s2);
     build_flop_ += 8.0 * nw * v * v2 * (2 * o + 2 * v);
     RTCC3_HIP(hipEventRecord(ev_l3b_, s2));
+    if (beside_) {
+      side_done_ = (*beside_)(ev_l3b_);
+      beside_ = nullptr;
+    }
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
@@ -965,7 +969,8 @@ void Triples::build_event(hipStream_t s) {
   RTCC3_HIP(hipEventRecord(bev_[nbev_++], s));
 }
 
-TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density) {
+TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density,
+                        const Beside& beside) {
   const int64_t o = d.o, v = d.v;
   const int64_t ov = o * v, oovv = o * o * v * v;
   hipStream_t s = e.stream;
@@ -976,6 +981,8 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   RTCC3_HIP(hipEventRecord(t0_, s));
   nbev_ = 0;
   blocks(e, r);
+  beside_ = beside ? &beside : nullptr;
+  side_done_ = nullptr;
   // accumulators
   const char* names[] = {"tr_X1", "tr_X2p", "tr_Y1", "tr_Y2p", "tr_Z34", "tr_R15",
                          "tr_R2", "tr_R6", "tr_R8", "tr_Zi",  "tr_R12"};
@@ -994,6 +1001,12 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
     for (auto& w : rhs_windows_) window_pass(e, w, y, true, false);
   }
 
+  if (beside_) {  // no window ran (nothing to overlap): start the side work here
+    RTCC3_HIP(hipEventRecord(ev_l3b_, s));
+    side_done_ = (*beside_)(ev_l3b_);
+    beside_ = nullptr;
+  }
+  if (side_done_) RTCC3_HIP(hipStreamWaitEvent(s, side_done_, 0));
   // ---- final contractions of the Y1 intermediates
   View Y1 = e.tensor("tr_Y1", {o, v});
   View l2 = Engine::raw(const_cast<cplx*>(y) + 2 * ov + oovv, {o, o, v, v});

@@ -1,6 +1,7 @@
 // Approximate triples of CC3 evaluated one occupied triple (i,j,k) at a time.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "ccsd.h"
@@ -53,7 +54,15 @@ class Triples {
   // then runs over pair windows that hold, for occupied pairs (l,k), the
   // slabs of blocks (i,l,k) of every i, and evaluates the right-hand side for
   // the blocks each window owns.
-  TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density);
+  // beside (optional) is called once, after the first window's lambda3 build
+  // has been enqueued, with an event recorded after that build: it may enqueue
+  // independent work on another stream that waits for the event (so the work
+  // runs beside the contractions rather than the builds) and returns an event
+  // recorded after it; the final contractions, which use the engine's scratch
+  // memory, wait for that event.
+  typedef std::function<hipEvent_t(hipEvent_t)> Beside;
+  TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density,
+                 const Beside& beside = nullptr);
   void set_precision(int p) { prec_ = p; }
   // Cap the blocks per window (0: sized from free device memory) and rebuild
   // the windows; the window buffers are released and reallocated on use.
@@ -102,6 +111,8 @@ class Triples {
   hipEvent_t ev_l3b_ = nullptr;  // after the lambda3 build: the t3 side's products wait for it
                                  // and only the t3 symmetrisation runs beside it
   int nbev_ = 0;                 // pairs recorded in the current run
+  const Beside* beside_ = nullptr;  // pending side work of the current run
+  hipEvent_t side_done_ = nullptr;
   void build_event(hipStream_t s);
 
   void build_windows();

@@ -19,26 +19,28 @@ constexpr cplx ONE{1.0, 0.0};
 inline cplx R(double x) { return cplx{x, 0.0}; }
 }  // namespace
 
-namespace {
-CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
-                        const View& ones_o, bool want_grad);
-}  // namespace
-
 CCSDResult ccsd_evaluate(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
                          const View& ones_o, bool want_grad) {
-  CCSDResult r = forward_impl(e, d, y, h, B, I, ones_o, want_grad);
+  CCSDResult r = ccsd_forward(e, d, y, h, B, I, ones_o, want_grad);
+  ccsd_residual(e, d, r);
   if (want_grad) ccsd_backward(e, d, y, ones_o, r);
   return r;
 }
 
-CCSDResult ccsd_forward(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
-                        const View& ones_o) {
-  return forward_impl(e, d, y, h, B, I, ones_o, true);
-}
-
 namespace {
+View fresh_view(Engine& e, const char* name, std::vector<int64_t> shape) {
+  View t = e.tensor(name, shape);
+  e.zero(t);
+  e.set_requires_grad(t.buf, false);
+  return t;
+}
+View block_of(const View& x, int64_t o, int64_t n, char a, char b) {
+  const int64_t l0 = a == 'o' ? 0 : o, h0 = a == 'o' ? o : n, l1 = b == 'o' ? 0 : o, h1 = b == 'o' ? o : n;
+  return Engine::slice(Engine::slice(x, x.nd - 2, l0, h0), x.nd - 1, l1, h1);
+}
+}  // namespace
 
-CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
+CCSDResult ccsd_forward(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
                         const View& ones_o, bool want_grad) {
   const int64_t o = d.o, v = d.v, n = d.n, na = d.naux;
   const int64_t ov = o * v, oovv = o * o * v * v;
@@ -53,22 +55,8 @@ CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, 
   e.set_requires_grad(t2.buf, want_grad);
   if (want_grad) e.tape_begin();
 
-  auto fresh = [&](const char* name, std::vector<int64_t> shape) {
-    View t = e.tensor(name, shape);
-    e.zero(t);
-    e.set_requires_grad(t.buf, false);
-    return t;
-  };
-  auto blk = [&](const View& x, char a, char b) {
-    auto rng = [&](char c, int64_t& lo, int64_t& hi) {
-      lo = (c == 'o') ? 0 : o;
-      hi = (c == 'o') ? o : n;
-    };
-    int64_t l0, h0, l1, h1;
-    rng(a, l0, h0);
-    rng(b, l1, h1);
-    return Engine::slice(Engine::slice(x, x.nd - 2, l0, h0), x.nd - 1, l1, h1);
-  };
+  auto fresh = [&](const char* name, std::vector<int64_t> shape) { return fresh_view(e, name, shape); };
+  auto blk = [&](const View& x, char a, char b) { return block_of(x, o, n, a, b); };
 
   // ---- T1 transformation: X = 1 - T, Y = 1 + T with T[a,i] = t_i^a
   View Tm = fresh("Tm", {n, n});
@@ -95,9 +83,8 @@ CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, 
   e.axpy(ONE, ht, F);
   e.einsum("Ppq,P->pq", R(2), Bt, Bd, F);
   e.einsum("Ppk,Pkq->pq", R(-1), Engine::slice(Bt, 2, 0, o), Engine::slice(Bt, 1, 0, o), F);
-  View Foo = blk(F, 'o', 'o'), Fov = blk(F, 'o', 'v'), Fvo = blk(F, 'v', 'o'), Fvv = blk(F, 'v', 'v');
 
-  // ---- transformed Mulliken blocks (pq|rs)~
+  // ---- (ia|jb), invariant under the T1 transformation, for L
   auto gblock = [&](const char* name, const View& BB, const char* s) {
     auto ext = [&](char c) { return c == 'o' ? o : v; };
     View g = fresh(name, {ext(s[0]), ext(s[1]), ext(s[2]), ext(s[3])});
@@ -105,6 +92,39 @@ CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, 
     return g;
   };
   View g_ovov = gblock("g_ovov", B, "ovov");  // invariant under the T1 transformation
+
+  View u = fresh("u", {o, o, v, v});  // u_ij^ab = 2 t_ij^ab - t_ij^ba
+  e.axpy(R(2), t2, u);
+  e.axpy(R(-1), Engine::permute(t2, {0, 1, 3, 2}), u);
+  View Lov = fresh("Lov", {o, v, o, v});  // L_iajb = 2(ia|jb) - (ib|ja)
+  e.axpy(R(2), g_ovov, Lov);
+  e.axpy(R(-1), Engine::permute(g_ovov, {0, 3, 2, 1}), Lov);
+
+  r.Bt = Bt;
+  r.F = F;
+  r.X = X;
+  r.Y = Y;
+  if (want_grad) e.tape_end();  // paused: the residual continues this tape
+  return r;
+}
+
+void ccsd_residual(Engine& e, const Dims& d, CCSDResult& r) {
+  const int64_t o = d.o, v = d.v, n = d.n;
+  const bool want_grad = e.requires_grad(e.tensor("t1", {o, v}).buf);
+  if (want_grad) e.tape_resume();
+  auto fresh = [&](const char* name, std::vector<int64_t> shape) { return fresh_view(e, name, shape); };
+  auto blk = [&](const View& x, char a, char b) { return block_of(x, o, n, a, b); };
+  const View t2 = e.tensor("t2", {o, o, v, v}), u = e.tensor("u", {o, o, v, v}), Lov = e.tensor("Lov", {o, v, o, v});
+  const View g_ovov = e.tensor("g_ovov", {o, v, o, v});
+  const View Bt = r.Bt, F = r.F;
+  const View Foo = blk(F, 'o', 'o'), Fov = blk(F, 'o', 'v'), Fvo = blk(F, 'v', 'o'), Fvv = blk(F, 'v', 'v');
+  // ---- transformed Mulliken blocks (pq|rs)~
+  auto gblock = [&](const char* name, const View& BB, const char* s) {
+    auto ext = [&](char c) { return c == 'o' ? o : v; };
+    View g = fresh(name, {ext(s[0]), ext(s[1]), ext(s[2]), ext(s[3])});
+    e.einsum("Ppq,Prs->pqrs", ONE, blk(BB, s[0], s[1]), blk(BB, s[2], s[3]), g);
+    return g;
+  };
   View g_vvov = gblock("g_vvov", Bt, "vvov");
   View g_ooov = gblock("g_ooov", Bt, "ooov");
   View g_vovo = gblock("g_vovo", Bt, "vovo");
@@ -113,13 +133,6 @@ CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, 
   View g_oovv = gblock("g_oovv", Bt, "oovv");
   View g_voov = gblock("g_voov", Bt, "voov");
   View g_vvoo = gblock("g_vvoo", Bt, "vvoo");
-
-  View u = fresh("u", {o, o, v, v});  // u_ij^ab = 2 t_ij^ab - t_ij^ba
-  e.axpy(R(2), t2, u);
-  e.axpy(R(-1), Engine::permute(t2, {0, 1, 3, 2}), u);
-  View Lov = fresh("Lov", {o, v, o, v});  // L_iajb = 2(ia|jb) - (ib|ja)
-  e.axpy(R(2), g_ovov, Lov);
-  e.axpy(R(-1), Engine::permute(g_ovov, {0, 3, 2, 1}), Lov);
 
   // ---- singles
   View R1 = fresh("R1", {o, v});
@@ -159,31 +172,15 @@ CCSDResult forward_impl(Engine& e, const Dims& d, const cplx* y, const View& h, 
   e.axpy(ONE, Cx, R2);
   e.axpy(ONE, Engine::permute(Cx, {1, 0, 3, 2}), R2);
 
-  r.Bt = Bt;
-  r.F = F;
-  r.X = X;
-  r.Y = Y;
   r.R1 = R1;
   r.R2 = R2;
   if (want_grad) e.tape_end();
-  return r;
 }
-
-}  // namespace
 
 void ccsd_backward(Engine& e, const Dims& d, const cplx* y, const View& ones_o, CCSDResult& r) {
   const int64_t o = d.o, v = d.v, n = d.n;
   const int64_t ov = o * v, oovv = o * o * v * v;
-  auto blk = [&](const View& x, char a, char b) {
-    auto rng = [&](char c, int64_t& lo, int64_t& hi) {
-      lo = (c == 'o') ? 0 : o;
-      hi = (c == 'o') ? o : n;
-    };
-    int64_t l0, h0, l1, h1;
-    rng(a, l0, h0);
-    rng(b, l1, h1);
-    return Engine::slice(Engine::slice(x, x.nd - 2, l0, h0), x.nd - 1, l1, h1);
-  };
+  auto blk = [&](const View& x, char a, char b) { return block_of(x, o, n, a, b); };
   const View t1 = e.tensor("t1", {o, v}), t2 = e.tensor("t2", {o, o, v, v});
   const View ht = e.tensor("ht", {n, n}), Lov = e.tensor("Lov", {o, v, o, v});
 

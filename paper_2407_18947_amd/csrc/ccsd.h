@@ -25,12 +25,17 @@ struct CCSDResult {
 // want_grad: also the reverse sweep (G1, G2, Dt).
 CCSDResult ccsd_evaluate(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B,
                          const View& I, const View& ones_o, bool want_grad);
-// The two halves of ccsd_evaluate(..., true): the forward program (recorded),
-// and the reverse sweep that fills r.G1, r.G2, r.Dt.  The sweep reads only the
-// engine buffers of the forward program and y, and writes gradient buffers, so
-// it may run on another stream while other work reads those buffers.
+// The three parts of ccsd_evaluate, in this order on one engine tape:
+// ccsd_forward - T1 transformation, f~, L and u (what the triples read);
+// ccsd_residual - the transformed (pq|rs)~ blocks and Omega1, Omega2 (r.R1, r.R2);
+// ccsd_backward - the reverse sweep (r.G1, r.G2, r.Dt).
+// The last two read only engine buffers of the forward part and y, and write
+// their own, so they may run on another stream (the engine's stream switched)
+// while other work reads the forward part's buffers; the tape is paused
+// between the forward part and the residual.
 CCSDResult ccsd_forward(Engine& e, const Dims& d, const cplx* y, const View& h, const View& B, const View& I,
-                        const View& ones_o);
+                        const View& ones_o, bool want_grad = true);
+void ccsd_residual(Engine& e, const Dims& d, CCSDResult& r);
 void ccsd_backward(Engine& e, const Dims& d, const cplx* y, const View& ones_o, CCSDResult& r);
 
 // Energy of the CCSD part (for tests): E = sum_i (h~_ii + F~_ii) + sum t2 L.

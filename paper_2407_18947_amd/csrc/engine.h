@@ -66,6 +66,7 @@ class Engine {
   View grad(const View& v);
   void tape_begin();
   void tape_end() { recording_ = false; }
+  void tape_resume() { recording_ = true; }  // continue the current tape (after a pause with tape_end)
   void zero_grads();
   void backward();
 

@@ -86,13 +86,14 @@ void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const Te
   const int64_t ov = o * v, oovv = o * o * v * v;
   build_h(c, E);
   CCSDResult r = ccsd_forward(e, d, y, c->h, c->B, c->I, c->ones_o);
+  ccsd_residual(e, d, r);
   const bool want_density = t.terms || t.mu;
 
   TriplesOut to;
   if (with_triples) {
-    // the reverse sweep needs only the forward program: it runs on the side
-    // stream beside the triples contractions (after the first lambda3 build,
-    // which itself follows the forward program)
+    // the reverse sweep needs only the CCSD forward part and residual: it runs
+    // on the side stream beside the triples contractions (after the first
+    // lambda3 build, which itself follows them)
     to = c->tri->run(e, d, r, y, want_density, [&](hipEvent_t after) -> hipEvent_t {
       RTCC3_HIP(hipStreamWaitEvent(c->side_stream, after, 0));
       e.stream = c->side_stream;

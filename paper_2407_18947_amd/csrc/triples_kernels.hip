@@ -197,6 +197,9 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
 constexpr int CB = 8;
 constexpr int CS1 = CB + 1, CS0 = CB * CS1 + 1;
 __device__ __forceinline__ int cube_at(int t0, int t1, int t2) { return t0 * CS0 + t1 * CS1 + t2; }
+// LDS stride of cube axis p: an element whose source coordinates u_k lie on
+// cube axes p_k sits at sum_k u_k * cstride(p_k)
+__device__ __forceinline__ int cstride(int p) { return p == 0 ? CS0 : p == 1 ? CS1 : 1; }
 __device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}};
 
 // With LAM, each source element first receives the terms of the lambda3 bracket
@@ -213,37 +216,60 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   const int* sl = part + 6 * n0;
   const int nc = (v + CB - 1) / CB;
   const int cube = blockIdx.x;
-  int t0[3];
-  t0[0] = (cube / (nc * nc)) * CB;
-  t0[1] = ((cube / nc) % nc) * CB;
-  t0[2] = (cube % nc) * CB;
+  const int c0 = (cube / (nc * nc)) * CB, c1 = ((cube / nc) % nc) * CB, c2 = (cube % nc) * CB;  // cube corner
+  // (selects rather than arrays indexed by the permutation, which would live in scratch memory)
+  auto pick = [](int p, int a, int b, int c) { return p == 0 ? a : p == 1 ? b : c; };
   const int64_t v3 = (int64_t)v * v * v;
   for (int e = threadIdx.x; e < CB * CS0; e += blockDim.x) acc[e] = cplx{0, 0};
   __syncthreads();
-  const int occ[3] = {I, J, K};
   const int nn = o + v;
+  // With LAM, a source's terms without a summation index need, per cube, only
+  // 8x8 slices of L and l2 and 8-vectors of l1 and f~: staged in LDS first.
+  __shared__ cplx lt[LAM ? 4 : 1][CB][CB];  // L[si,X0,sj,X1], L[si,X0,sj,X2], l2[sj,sk,X1,X2], l2[si,sk,X1,X2]
+  __shared__ cplx lv[LAM ? 4 : 1][CB];      // l1[sk,X2], l1[sk,X1], f~[si,X0], f~[sj,X0]
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
-    const int x0 = t0[p0], x1 = t0[p1], x2 = t0[p2];
+    const int x0 = pick(p0, c0, c1, c2), x1 = pick(p1, c0, c1, c2), x2 = pick(p2, c0, c1, c2);
     const cplx* src = W + (int64_t)sl[s] * v3;
-    const int si = occ[p0], sj = occ[p1], sk = occ[p2];  // the source's occupied triple
+    const int si = pick(p0, I, J, K), sj = pick(p1, I, J, K), sk = pick(p2, I, J, K);  // the source's occupied triple
+    if (LAM) {
+      static_assert(CB == 8, "the staging below maps 256 threads onto four 8x8 tables");
+      const int q = threadIdx.x >> 6, i = (threadIdx.x >> 3) & 7, j = threadIdx.x & 7;
+      // table q, row i, column j: one pointer and one range test per thread
+      const int ri = q < 2 ? x0 : x1, cj = q == 0 ? x1 : x2;  // virtual offsets of the row and column
+      const cplx* tb = q < 2    ? le.Lov + ((int64_t)si * v * o + sj) * v         // L[si, ., sj, .]
+                       : q == 2 ? le.l2 + ((int64_t)sj * o + sk) * v * v         // l2[sj, sk, ., .]
+                                : le.l2 + ((int64_t)si * o + sk) * v * v;        // l2[si, sk, ., .]
+      const int64_t rs = q < 2 ? (int64_t)o * v : v;  // row stride
+      const bool okt = ri + i < v && cj + j < v;  // a masked element reads the table's first one
+      const cplx xt = tb[okt ? (int64_t)(ri + i) * rs + cj + j : 0];
+      lt[q][i][j] = okt ? xt : cplx{0, 0};
+      if (threadIdx.x < 4 * CB) {
+        const int r = threadIdx.x >> 3;
+        const int off = r == 0 ? x2 : r == 1 ? x1 : x0;
+        const cplx* vp = r == 0 ? le.l1 + (int64_t)sk * v + x2
+                         : r == 1 ? le.l1 + (int64_t)sk * v + x1
+                         : r == 2 ? le.F + (int64_t)si * nn + o + x0
+                                  : le.F + (int64_t)sj * nn + o + x0;
+        const bool okv = off + j < v;
+        const cplx xv = vp[okv ? j : 0];
+        lv[r][j] = okv ? xv : cplx{0, 0};
+      }
+      __syncthreads();
+    }
     for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
       const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
       if (X0 < v && X1 < v && X2 < v) {
-        int tl[3];
-        tl[p0] = u0;
-        tl[p1] = u1;
-        tl[p2] = u2;
         cplx w = src[((int64_t)X0 * v + X1) * v + X2];
         if (LAM) {
-          const cplx* Lij = le.Lov + (((int64_t)si * v + X0) * o + sj) * v;  // L[si,X0,sj,:]
-          w = cadd(w, cmul(Lij[X1], le.l1[(int64_t)sk * v + X2]));
-          w = csub(w, cmul(Lij[X2], le.l1[(int64_t)sk * v + X1]));
-          w = cadd(w, cmul(le.F[(int64_t)si * nn + o + X0], le.l2[(((int64_t)sj * o + sk) * v + X1) * v + X2]));
-          w = csub(w, cmul(le.F[(int64_t)sj * nn + o + X0], le.l2[(((int64_t)si * o + sk) * v + X1) * v + X2]));
+          //   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik at the source's indices
+          w = cadd(w, cmul(lt[0][u0][u1], lv[0][u2]));
+          w = csub(w, cmul(lt[1][u0][u2], lv[1][u1]));
+          w = cadd(w, cmul(lv[2][u0], lt[2][u1][u2]));
+          w = csub(w, cmul(lv[3][u0], lt[3][u1][u2]));
         }
-        cplx& r = acc[cube_at(tl[0], tl[1], tl[2])];
+        cplx& r = acc[u0 * cstride(p0) + u1 * cstride(p1) + u2 * cstride(p2)];
         r.re += w.re;
         r.im += w.im;
       }
@@ -253,7 +279,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   const double eocc = eps[I] + eps[J] + eps[K];
   for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
     const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
-    const int a = t0[0] + u0, b = t0[1] + u1, c = t0[2] + u2;
+    const int a = c0 + u0, b = c1 + u1, c = c2 + u2;
     if (a < v && b < v && c < v) {
       const double D = eocc - eps[o + a] - eps[o + b] - eps[o + c];
       cplx& r = acc[cube_at(u0, u1, u2)];
@@ -264,18 +290,13 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   __syncthreads();
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
-    const int x0 = t0[p0], x1 = t0[p1], x2 = t0[p2];
+    const int x0 = pick(p0, c0, c1, c2), x1 = pick(p1, c0, c1, c2), x2 = pick(p2, c0, c1, c2);
     cplx* dst = T + (int64_t)sl[s] * v3;
     for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
       const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
-      if (X0 < v && X1 < v && X2 < v) {
-        int tl[3];
-        tl[p0] = u0;
-        tl[p1] = u1;
-        tl[p2] = u2;
-        dst[((int64_t)X0 * v + X1) * v + X2] = acc[cube_at(tl[0], tl[1], tl[2])];
-      }
+      if (X0 < v && X1 < v && X2 < v)
+        dst[((int64_t)X0 * v + X1) * v + X2] = acc[u0 * cstride(p0) + u1 * cstride(p1) + u2 * cstride(p2)];
     }
   }
 }

@@ -51,9 +51,10 @@ class Triples {
   Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int precision);
   ~Triples();
   // Run all windows.  want_density: also the triples density terms; the pass
-  // then runs over pair windows that hold, for occupied pairs (l,k), the
-  // slabs of blocks (i,l,k) of every i, and evaluates the right-hand side for
-  // the blocks each window owns.
+  // then runs over the density windows: one window of every block when all o^3
+  // fit, else pair windows that hold, for occupied pairs (l,k), the slabs of
+  // blocks (i,l,k) of every i and evaluate the right-hand side for the blocks
+  // each window owns.
   // beside (optional) is called once, after the first window's lambda3 build
   // has been enqueued, with an event recorded after that build: it may enqueue
   // independent work on another stream that waits for the event (so the work

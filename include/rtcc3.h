@@ -26,9 +26,10 @@
  * no exception or abort crosses the ABI.  rtcc3_last_error() gives a message.
  * Ownership.  Host arrays passed in are copied; the caller keeps them.  Device
  * pointers passed to rtcc3_rhs / rtcc3_rhs_terms are caller-owned and must stay
- * valid for the call; all work is ordered on the context's stream and the
- * functions return after that stream has been synchronised.  A context serves
- * one thread at a time.
+ * valid for the call; all work is ordered on the context's stream (the library
+ * forks two streams of its own from it and joins them back within each call)
+ * and the functions return after that stream has been synchronised.  A
+ * context serves one thread at a time.
  */
 #ifndef RTCC3_H
 #define RTCC3_H
@@ -61,8 +62,9 @@ enum {
  *                 24 significand bits), six slice products on the bf16 matrix
  *                 cores, FP32 accumulation
  *   RTCC3_BF16X2  two bf16 slices (16 bits), three slice products
- * The bf16 splits apply to the products that build t3 and lambda3; the other
- * triples products of such a run use FP32. */
+ * The bf16 splits apply to the segmented products (the builds of t3 and
+ * lambda3 and the S intermediate of Y1); the other triples products of such a
+ * run use FP32. */
 enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1, RTCC3_BF16X3 = 2, RTCC3_BF16X2 = 3 };
 
 /* Create a context.

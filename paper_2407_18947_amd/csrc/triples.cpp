@@ -476,19 +476,21 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int nw = w.nw;
   hipStream_t s = e.stream;  // t3 side
   hipStream_t s2 = s2_;      // lambda3 side
-  RTCC3_HIP(hipEventRecord(ev_fork_, s));
-  RTCC3_HIP(hipStreamWaitEvent(s2, ev_fork_, 0));
   const cplx* t2 = y + ov;
   const cplx* l1 = y + ov + oovv;
   const cplx* l2 = y + 2 * ov + oovv;
   const int64_t t2len = oovv, l2len = oovv;
   (void)ylen;
   const int64_t winlen = (int64_t)max_nw_ * v3;
+  // The window buffers first: a buffer's first request zero-fills it on the
+  // engine stream, which must come before the fork below.
   cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, v}).p;
   cplx* Wl = e.tensor("tw_Wl", {(int64_t)max_nw_, v, v, v}).p;
   cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, v}).p;
   cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, v}).p;
   cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
+  RTCC3_HIP(hipEventRecord(ev_fork_, s));
+  RTCC3_HIP(hipStreamWaitEvent(s2, ev_fork_, 0));
   auto P = [&](const char* name, std::vector<int64_t> shape) { return e.tensor(name, shape).p; };
   const cplx* gW1 = P("tb_W1", {o, v, v, v});
   const cplx* gW2 = P("tb_W2", {o, o, v, o});
@@ -557,6 +559,37 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
   RTCC3_HIP(hipEventRecord(ev_t_, s));  // t3 blocks ready
 
+  // Contractions run over the blocks this window is responsible for: all of
+  // them in a plain window, the owned ones in a pair window.
+  const bool pairwin = !w.owned.empty() && density_terms;
+  const int* cbl = pairwin ? w.d_owned : bl;
+  const int* cblh = pairwin ? w.owned.data() : blh;
+  const int cn = pairwin ? (int)w.owned.size() / 4 : nw;
+  if (rhs_terms) {
+    // S needs only t2 and integrals: it goes first on the lambda3 side, beside
+    // the t3 symmetrisation (memory bound) rather than beside other products
+    RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));
+    {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
+       //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
+      GemmDesc g = base(v, (int)(o * v), up16(v) + v, cn, cbl, pr);
+      g.store = 1;
+      g.nseg = 2;
+      const int64_t ov2 = (int64_t)o * v2, v2o = v2 * o;
+      seg(g.seg[0], 0, v, t2, {0, ov2, v2, 0}, v, 1, gG9, {v2o, 0, 0, 0}, (int64_t)v * o);
+      seg(g.seg[1], up16(v), v, t2, {v2, ov2, 0, 0}, v, 1, gG10, {0, 0, v2o, 0}, (int64_t)v * o);
+      g.C = S;
+      g.sCm0 = (int64_t)v * o;
+      g.sCn0 = 1;
+      set4(g.cC, 0, 0, 0, v2o);
+      const int64_t lS = (int64_t)max_nw_ * v2 * o;
+      const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
+      build_event(s2);  // same kernel as the builds: timed with them
+      checked_seg_gemm(g, cblh, lA, lB, lS, s2);
+      build_event(s2);
+      build_flop_ += 8.0 * cn * v * (o * v) * (2 * v);
+    }
+  }
+
   // ---------------- lambda3 blocks
   {  // W[n][a][(b,c)] = sum_l (ka|jl)~[K][a][J][l] l2[l][I][(b,c)]
      //              - sum_l Lt_ijal[I][a][J][l] l2[l][K][(b,c)]
@@ -596,12 +629,6 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   launches_ += 4;
 
   if (rhs_terms) {
-    // Contractions run over the blocks this window is responsible for: all of
-    // them in a plain window, the owned ones in a pair window.
-    const bool pairwin = !w.owned.empty() && density_terms;
-    const int* cbl = pairwin ? w.d_owned : bl;
-    const int* cblh = pairwin ? w.owned.data() : blh;
-    const int cn = pairwin ? (int)w.owned.size() / 4 : nw;
     cplx* X1 = P("tr_X1", {o, v});
     cplx* X2p = P("tr_X2p", {o, o, v, v});
     cplx* Y1 = P("tr_Y1", {o, v});
@@ -825,26 +852,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
                    {c6, l2len, lR, l2len, ov}},
                   s);
     }
-    {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
-       //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
-      GemmDesc g = base(v, (int)(o * v), up16(v) + v, cn, cbl, pr);
-      g.store = 1;
-      g.nseg = 2;
-      const int64_t ov2 = (int64_t)o * v2, v2o = v2 * o;
-      seg(g.seg[0], 0, v, t2, {0, ov2, v2, 0}, v, 1, gG9, {v2o, 0, 0, 0}, (int64_t)v * o);
-      seg(g.seg[1], up16(v), v, t2, {v2, ov2, 0, 0}, v, 1, gG10, {0, 0, v2o, 0}, (int64_t)v * o);
-      g.C = S;
-      g.sCm0 = (int64_t)v * o;
-      g.sCn0 = 1;
-      set4(g.cC, 0, 0, 0, v2o);
-      const int64_t lS = (int64_t)max_nw_ * v2 * o;
-      const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
-      build_event(s2);  // same kernel as the builds: timed with them
-      checked_seg_gemm(g, cblh, lA, lB, lS, s2);
-      build_event(s2);
-      build_flop_ += 8.0 * cn * v * (o * v) * (2 * v);
-    }
-    {  // One column-segment product over lambda_n[a][(b,c)], after S:
+    {  // One column-segment product over lambda_n[a][(b,c)] (S is ready: same stream, earlier):
        //  terms 7, 8: Q[d][j] = sum_bc lambda[(b,c)][d] t2[j][J][(b,c)] into R8[I][K]; with
        //    lambda[b][c][d] = lambda_KIJ[d][b][c] and the labels renamed ((K,I,J) -> (I,J,K)):
        //    sum_bc lambda_n[d][(b,c)] t2[j][K][(b,c)] into R8[J][I]

@@ -610,7 +610,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, v3);
     const int64_t lLC = (int64_t)o * v * o * o;
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
-    RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));  // after the t3 build (overlaps its symmetrisation)
+    RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));  // after the t3 build (a no-op when S went first)
     build_event(s2);
     checked_seg_gemm(g, blh, lA, lB, winlen, s2);
     build_event(s2);
@@ -886,7 +886,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       set4(g.cC, 0, v3, 0, 0);
       checked_gather_gemm(g, w.gJ, t2len, winlen, lOVVV, s2);
     }
-    launches_ += 10;
+    launches_ += tails ? 9 : 10;
   }
 
   // the density terms read t3 and lambda3: join the lambda3 side's blocks

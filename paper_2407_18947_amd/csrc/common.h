@@ -66,7 +66,8 @@ struct GemmDesc {
   //   A_s[m][r] = seg[s].A[cA.(I,J,K,n) + m*sAm + r*sAk],
   //   B_s[r][n] = seg[s].B[cB.(I,J,K,n) + r*sBk + n*sBn],   r = k - seg[s].k0,
   // so one product sums terms whose operands live in different tensors.
-  // The plain A/B fields and M0/N0/K0 splits are then unused (M0 = M, N0 = N).
+  // The plain A/B fields and the M0/K0 splits are then unused (M0 = M); N0
+  // (with sCn1) splits the columns of C only, B reads the flattened n.
   struct Seg {
     int k0;   // first k; a multiple of 16, so that a K step of 16 lies in one segment
     int len;  // contraction length (k0 + len <= next k0; the gap reads as zero)
@@ -101,8 +102,9 @@ struct GemmDesc {
   // share an output without atomics.
   const int* gk_start;
   const int* gk_bl;
-  // Column segments (ncs in 1..4, block table required, A read k-fast, K not
-  // split in two levels, atomic accumulation): columns [16s, 16s + cs[s].n) of
+  // Column segments (ncs in 1..4, block table required, A read k-fast, atomic
+  // accumulation; K0 with sAk1 splits A's k only, the segments' B read the
+  // flattened k): columns [16s, 16s + cs[s].n) of
   // the product belong to segment s, which has its own B operand, output and
   // scale,
   //   C_s[m][c] += alpha_s * sum_k A[m][k] B_s[k][c],

@@ -900,7 +900,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   }
   if (d0.ncs > 0) {
     RTCC3_CHECK(d0.ncs <= 4 && d0.bl && d0.nseg == 0 && d0.comb_n == 0 && !d0.gk_start && !d0.store &&
-                    d0.atomic && d0.K0 == d0.K && d0.M0 == d0.M && d0.sAk0 == 1,
+                    d0.atomic && d0.M0 == d0.M && d0.sAk0 == 1,
                 "gemm: bad column segments");
     for (int s = 0; s < d0.ncs; ++s) {
       const GemmDesc::ColSeg& g = d0.cs[s];
@@ -917,8 +917,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
                 "gemm: bad gathered K");
   }
   if (d0.nseg > 0) {
-    RTCC3_CHECK(d0.nseg <= 4 && d0.bl && d0.seg[0].k0 == 0 && d0.M0 == d0.M && d0.N0 == d0.N,
-                "gemm: bad K segments");
+    RTCC3_CHECK(d0.nseg <= 4 && d0.bl && d0.seg[0].k0 == 0 && d0.M0 == d0.M, "gemm: bad K segments");
     for (int s = 0; s < d0.nseg; ++s) {
       const GemmDesc::Seg& g = d0.seg[s];
       const int end = s + 1 < d0.nseg ? d0.seg[s + 1].k0 : d0.K;

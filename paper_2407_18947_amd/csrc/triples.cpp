@@ -162,6 +162,9 @@ void checked_colseg_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, co
   gemm(g, s);
 }
 
+// The innermost index of a window block padded to a multiple of 8.
+int pad8(int v) { return (v + 7) / 8 * 8; }
+
 void set4(int64_t* c, int64_t a, int64_t b, int64_t d, int64_t n) {
   c[0] = a;
   c[1] = b;
@@ -261,7 +264,6 @@ void finish_window(Window& w, const std::vector<std::array<int, 3>>& blocks) {
 
 void Triples::build_windows() {
   const int o = d_.o;
-  const int64_t v3 = (int64_t)d_.v * d_.v * d_.v;
   // Four window buffers of nw blocks each (W for t3 and for lambda3, t3,
   // lambda3); larger windows mean fewer, larger launches.  Budget: half the
   // free device memory, at most 48 GiB (of the 288 GB of HBM); when all o^3
@@ -269,7 +271,7 @@ void Triples::build_windows() {
   size_t free_b = 0, total_b = 0;
   RTCC3_HIP(hipMemGetInfo(&free_b, &total_b));
   const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)48 << 30, (int64_t)(free_b / 2)));
-  int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * v3));
+  int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * (int64_t)d_.v * d_.v * pad8(d_.v)));
   if (wcap_ > 0) wmax = std::max(6, std::min(wmax, wcap_));
   // ---- RHS windows: canonical triples i <= j <= k with all their orderings
   std::vector<std::array<int, 3>> cur;
@@ -481,13 +483,17 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const cplx* l2 = y + 2 * ov + oovv;
   const int64_t t2len = oovv, l2len = oovv;
   (void)ylen;
-  const int64_t winlen = (int64_t)max_nw_ * v3;
+  // Window blocks are [v][v][vp]: the innermost index is padded to a multiple
+  // of 8 so that every row starts on a 128-byte line; the padding stays zero.
+  const int vp = pad8(v);
+  const int64_t va = (int64_t)v * vp, vb = va * v;  // strides of the first index and of a block
+  const int64_t winlen = (int64_t)max_nw_ * vb;
   // The window buffers first: a buffer's first request zero-fills it on the
   // engine stream, which must come before the fork below.
-  cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, v}).p;
-  cplx* Wl = e.tensor("tw_Wl", {(int64_t)max_nw_, v, v, v}).p;
-  cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, v}).p;
-  cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, v}).p;
+  cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, vp}).p;
+  cplx* Wl = e.tensor("tw_Wl", {(int64_t)max_nw_, v, v, vp}).p;
+  cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, vp}).p;
+  cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, vp}).p;
   cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
   RTCC3_HIP(hipEventRecord(ev_fork_, s));
   RTCC3_HIP(hipStreamWaitEvent(s2, ev_fork_, 0));
@@ -545,10 +551,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     seg(g.seg[0], 0, v, t2, {(int64_t)o * v2, v2, 0, 0}, v, 1, gW1, {0, 0, v3, 0}, v2);
     seg(g.seg[1], up16(v), o, gW2, {(int64_t)v * o, 0, (int64_t)o * v * o, 0}, o, 1, t2, {0, (int64_t)o * v2, 0, 0},
         v2);
-    g.C = W;
-    g.sCm0 = v2;
+    g.C = W;  // C[a][(b,c)] at a*va + b*vp + c
+    g.sCm0 = va;
+    g.N0 = v;
+    g.sCn1 = vp;
     g.sCn0 = 1;
-    set4(g.cC, 0, 0, 0, v3);
+    set4(g.cC, 0, 0, 0, vb);
     const int64_t lA[2] = {lT2, lOOOV}, lB[2] = {lOVVV_, lT2};
     build_event(s);
     checked_seg_gemm(g, blh, lA, lB, winlen, s);
@@ -556,7 +564,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     build_flop_ += 8.0 * nw * v * v2 * (v + o);
   }
   RTCC3_HIP(hipEventRecord(ev_t3b_, s));
-  launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, nullptr, s);
+  launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, nullptr, s);
   RTCC3_HIP(hipEventRecord(ev_t_, s));  // t3 blocks ready
 
   // Contractions run over the blocks this window is responsible for: all of
@@ -605,9 +613,11 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     seg(g.seg[2], k2, v, l2, {0, ov2, v2, 0}, v, 1, gLA, {v3, 0, 0, 0}, v2);
     seg(g.seg[3], k3, v, l2, {ov2, v2, 0, 0}, v, 1, gLB, {0, 0, v3, 0}, v2);
     g.C = Wl;
-    g.sCm0 = v2;
+    g.sCm0 = va;
+    g.N0 = v;
+    g.sCn1 = vp;
     g.sCn0 = 1;
-    set4(g.cC, 0, 0, 0, v3);
+    set4(g.cC, 0, 0, 0, vb);
     const int64_t lLC = (int64_t)o * v * o * o;
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
     RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));  // after the t3 build (a no-op when S went first)
@@ -623,7 +633,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
-    launch_sym_cube(Wl, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, &le, s2);
+    launch_sym_cube(Wl, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, &le, s2);
   }
   RTCC3_HIP(hipEventRecord(ev_l_, s2));  // lambda3 blocks ready
   launches_ += 4;
@@ -646,7 +656,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     // along with products that read the block anyway (tail columns of the Y1
     // product below; the f~ term inside tb_X2c); else one sweep per block
     const bool tails = o <= 15;
-    if (!tails) launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, 3, s);
+    if (!tails) launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, vp, 3, s);
     // the t3 side's products are bound by the matrix cores like the lambda3
     // build: they start once it is done
     RTCC3_HIP(hipStreamWaitEvent(s, ev_l3b_, 0));
@@ -665,20 +675,23 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.comb_w[0] = 2.0;
       g.comb_w[1] = -1.0;
       g.comb_w[2] = -1.0;
-      g.comb_stride = v3;
+      g.comb_stride = vb;
     };
     {  // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ into X2p[I][J][a][b], with (c,e) contiguous:
        //   Z1[b][c][e] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
       GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
+      g.K0 = v;  // k = (c,e)
       g.A = gX2a;
       g.sAm0 = v2;
+      g.sAk1 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, v3, 0);
       g.B = T;  // B[(c,e)][b] = Z1[b][(c,e)]
+      g.sBk1 = vp;
       g.sBk0 = 1;
-      g.sBn0 = v2;
-      set4(g.cB, 0, 0, 0, v3);
+      g.sBn0 = va;
+      set4(g.cB, 0, 0, 0, vb);
       combine(g, 1, 1, 4, 5);
       g.C = X2p;
       g.sCm0 = v;
@@ -697,15 +710,18 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     auto x2b = [&](const cplx* Bp, const int64_t* cb, const int64_t* cc, const Groups& gr) {
       GemmDesc g = base((int)v2, o, v * gr.max, 0, nullptr, pr);
       g.K0 = v;
-      g.A = T;  // A[(a,b)][c] = T_IJK[a][b][c]
-      g.sAm0 = v;
+      g.M0 = v;  // m = (a,b)
+      g.A = T;   // A[(a,b)][c] = T_IJK[a][b][c]
+      g.sAm1 = va;
+      g.sAm0 = vp;
       g.sAk0 = 1;
-      set4(g.cA, 0, 0, 0, v3);
+      set4(g.cA, 0, 0, 0, vb);
       g.B = Bp;
       g.sBk0 = 1;
       g.sBn0 = v;
       std::memcpy(g.cB, cb, sizeof(g.cB));
       g.C = X2p;
+      g.sCm1 = v;
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       std::memcpy(g.cC, cc, sizeof(g.cC));
@@ -722,19 +738,22 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
        // lambda_JIK[b][d][e], read with (d,e) contiguous
       GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
       g.atomic = 1;
+      g.K0 = v;  // k = (d,e)
       g.A = gY2a;
       g.sAm0 = v2;
+      g.sAk1 = v;
       g.sAk0 = 1;
       set4(g.cA, 0, 0, v3, 0);
       g.B = L;
+      g.sBk1 = vp;
       g.sBk0 = 1;
-      g.sBn0 = v2;
-      set4(g.cB, 0, 0, 0, v3);
+      g.sBn0 = va;
+      set4(g.cB, 0, 0, 0, vb);
       g.comb_n = 1;
       g.comb_on = 1;
       g.part = w.d_part;
       g.comb_perm[0] = 1;
-      g.comb_stride = v3;
+      g.comb_stride = vb;
       g.C = Y2p;
       g.sCm0 = v;
       g.sCn0 = 1;
@@ -744,16 +763,19 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J], summed over the blocks of each J
       GemmDesc g = base((int)v2, o, v * w.gJ.max, 0, nullptr, pr);
       g.K0 = v;
+      g.M0 = v;  // m = (a,b)
       g.alpha = R(-1);
       g.A = L;
-      g.sAm0 = v;
+      g.sAm1 = va;
+      g.sAm0 = vp;
       g.sAk0 = 1;
-      set4(g.cA, 0, 0, 0, v3);
+      set4(g.cA, 0, 0, 0, vb);
       g.B = gY2b;
       g.sBk0 = 1;
       g.sBn0 = v;
       set4(g.cB, (int64_t)o * o * v, 0, (int64_t)o * v, 0);
       g.C = Y2p;
+      g.sCm1 = v;
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
@@ -785,10 +807,12 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
         const int ns = (int)std::min<size_t>(4, parts.size() - p0);
         GemmDesc g = base(v, 16 * ns, (int)v2, cn, cbl, pr);
         g.atomic = 1;
-        g.A = X;
-        g.sAm0 = v2;
+        g.A = X;  // A[a][(b,c)] at a*va + b*vp + c; the segments' B read k = (b,c) flattened
+        g.K0 = v;
+        g.sAm0 = va;
+        g.sAk1 = vp;
         g.sAk0 = 1;
-        set4(g.cA, 0, 0, 0, v3);
+        set4(g.cA, 0, 0, 0, vb);
         g.ncs = ns;
         int64_t lenB[8] = {0}, lenC[8] = {0};
         for (int t = 0; t < ns; ++t) {
@@ -876,12 +900,15 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sAm0 = v;
       g.sAk0 = 1;
       set4(g.cA, v2, 0, (int64_t)o * v2, 0);
+      g.N0 = v;  // n = (d,e)
       g.B = L;
-      g.sBk0 = v2;
+      g.sBk0 = va;
+      g.sBn1 = vp;
       g.sBn0 = 1;
-      set4(g.cB, 0, 0, 0, v3);
+      set4(g.cB, 0, 0, 0, vb);
       g.C = Zi;
       g.sCm0 = v2;
+      g.sCn1 = v;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
       checked_gather_gemm(g, w.gJ, t2len, winlen, lOVVV, s2);
@@ -900,14 +927,17 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       GemmDesc g = base(v, v, (int)v2, no, w.d_owned, pr);
       g.atomic = 1;
       g.alpha = R(0.5);
+      g.K0 = v;  // k = (d,c)
       g.A = L;
-      g.sAm0 = v2;
+      g.sAm0 = va;
+      g.sAk1 = vp;
       g.sAk0 = 1;
-      set4(g.cA, 0, 0, 0, v3);
+      set4(g.cA, 0, 0, 0, vb);
       g.B = T;
+      g.sBk1 = vp;
       g.sBk0 = 1;
-      g.sBn0 = v2;
-      set4(g.cB, 0, 0, 0, v3);
+      g.sBn0 = va;
+      set4(g.cB, 0, 0, 0, vb);
       g.C = Dab;
       g.sCm0 = v;
       g.sCn0 = 1;
@@ -915,15 +945,18 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     }
     // D_ia first term: sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]; it equals the
     // Y1 intermediate Z34 when the same pass also evaluates the right-hand side
-    if (!rhs_terms) launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, 2, s);
+    if (!rhs_terms) launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, vp, 2, s);
     {  // D_ia second term: Rd[J][I][b][x] += sum_cd lambda[b][(c,d)] t2[x][K][(c,d)]
       GemmDesc g = base(v, o, (int)v2, no, w.d_owned, pr);
       g.atomic = 1;
+      g.K0 = v;  // k = (c,d)
       g.A = L;
-      g.sAm0 = v2;
+      g.sAm0 = va;
+      g.sAk1 = vp;
       g.sAk0 = 1;
-      set4(g.cA, 0, 0, 0, v3);
+      set4(g.cA, 0, 0, 0, vb);
       g.B = t2;
+      g.sBk1 = v;
       g.sBk0 = 1;
       g.sBn0 = (int64_t)o * v2;
       set4(g.cB, 0, 0, v2, 0);
@@ -942,21 +975,22 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     const int nslab = (int)w.slabs.size() / 4;
     if (o <= 16) {
       for (int q = 0; q < nslab; ++q)
-        RTCC3_CHECK(w.slabs[4 * q + 3] >= 0 && (int64_t)(w.slabs[4 * q + 3] + o) * v3 <= winlen,
+        RTCC3_CHECK(w.slabs[4 * q + 3] >= 0 && (int64_t)(w.slabs[4 * q + 3] + o) * vb <= winlen,
                     "triples: slab out of bounds");
-      launch_gram(T, L, w.d_slabs, nslab, o, v3, R(-0.5), Dij, s2);
+      // whole padded blocks: the padding is zero and adds nothing
+      launch_gram(T, L, w.d_slabs, nslab, o, vb, R(-0.5), Dij, s2);
     } else {
-      GemmDesc g = base(o, o, (int)v3, nslab, w.d_slabs, pr);
+      GemmDesc g = base(o, o, (int)vb, nslab, w.d_slabs, pr);  // whole padded blocks (zero padding)
       g.atomic = 1;
       g.alpha = R(-0.5);
       g.A = T;
-      g.sAm0 = v3;
+      g.sAm0 = vb;
       g.sAk0 = 1;
-      set4(g.cA, 0, 0, 0, v3);
+      set4(g.cA, 0, 0, 0, vb);
       g.B = L;
       g.sBk0 = 1;
-      g.sBn0 = v3;
-      set4(g.cB, 0, 0, 0, v3);
+      g.sBn0 = vb;
+      set4(g.cB, 0, 0, 0, vb);
       g.C = Dij;
       g.sCm0 = o;
       g.sCn0 = 1;

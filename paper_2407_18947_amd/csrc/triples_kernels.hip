@@ -27,25 +27,25 @@ __device__ __forceinline__ void catomic(cplx* p, cplx x) {
 // the unit-stride index onto the 64 lanes of a wave).
 __global__ void small_t3_simple_kernel(const cplx* __restrict__ T, const int* __restrict__ bl, const cplx* __restrict__ Lov,
                                 const cplx* __restrict__ F, const cplx* __restrict__ l2, cplx* __restrict__ X1,
-                                cplx* __restrict__ X2p, cplx* __restrict__ Z, int o, int v, int flags) {
+                                cplx* __restrict__ X2p, cplx* __restrict__ Z, int o, int v, int vp, int flags) {
   const int q = blockIdx.y, a = blockIdx.x;
   const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
-  const int64_t v3 = (int64_t)v * v * v;
+  const int64_t va = (int64_t)v * vp, vb = va * v;  // padded block strides
   const int nn = o + v;
-  const cplx* t = T + (int64_t)n * v3;
+  const cplx* t = T + (int64_t)n * vb;
   cplx x1{0, 0}, z{0, 0};
   for (int b = threadIdx.x; b < v; b += blockDim.x) {
     cplx x2f{0, 0};
     const cplx* Lb = Lov + (((int64_t)J * v + b) * o + K) * v;
     const cplx* l2b = l2 + (((int64_t)J * o + K) * v + b) * v;
     for (int c = 0; c < v; ++c) {
-      const cplx tabc = t[((int64_t)a * v + b) * v + c];
+      const cplx tabc = t[a * va + (int64_t)b * vp + c];
       if (flags & 1) {
-        const cplx tz = csub(tabc, t[((int64_t)c * v + b) * v + a]);
+        const cplx tz = csub(tabc, t[c * va + (int64_t)b * vp + a]);
         x1 = cadd(x1, cmul(tz, Lb[c]));
         x2f = cadd(x2f, cmul(tz, F[(int64_t)K * nn + o + c]));
       }
-      if (flags & 2) z = cadd(z, cmul(csub(tabc, t[((int64_t)b * v + a) * v + c]), l2b[c]));
+      if (flags & 2) z = cadd(z, cmul(csub(tabc, t[b * va + (int64_t)a * vp + c]), l2b[c]));
     }
     if (flags & 1) catomic(&X2p[(((int64_t)I * o + J) * v + a) * v + b], x2f);
   }
@@ -104,14 +104,14 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
                                                               const cplx* __restrict__ Lov, const cplx* __restrict__ F,
                                                               const cplx* __restrict__ l2, cplx* __restrict__ X1,
                                                               cplx* __restrict__ X2p, cplx* __restrict__ Z, int o,
-                                                              int v, int flags) {
+                                                              int v, int vp, int flags) {
   __shared__ cplx sP[2][SW_NW][64];  // per-wave X1a[x], Za[x]
   __shared__ cplx sz[SW_NW][64];     // per-wave X1b[z]
   const int q = blockIdx.x;
   const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
-  const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
+  const int64_t v2 = (int64_t)v * v, va = (int64_t)v * vp;  // t[x][y][z] at x*va + y*vp + z
   const int nn = o + v;
-  const cplx* t = T + (int64_t)n * v3;
+  const cplx* t = T + (int64_t)n * va * v;
   const cplx* fK = F + (int64_t)K * nn + o;
   const cplx* l2JK = l2 + ((int64_t)J * o + K) * v2;
   const int64_t Ly = (int64_t)o * v;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
     for (int xl = 0; xl < 4; ++xl) {
       const int x = xg + xl;
       const bool xin = x < v;
-      const cplx tv = ok && xin ? t[(int64_t)x * v2 + (int64_t)y * v + z] : cplx{0, 0};
+      const cplx tv = ok && xin ? t[(int64_t)x * va + (int64_t)y * vp + z] : cplx{0, 0};
       u[xl] = cmul(tv, fz);
       u[4 + xl] = cmul(tv, Lyz);
       zq[xl] = cmul(tv, lyz);
@@ -209,7 +209,8 @@ __device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 
 template <bool LAM>
 __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ W, cplx* __restrict__ T,
                                                          const int* __restrict__ canon, const int* __restrict__ part,
-                                                         const double* __restrict__ eps, int o, int v, LamElem le) {
+                                                         const double* __restrict__ eps, int o, int v, int vp,
+                                                         LamElem le) {
   __shared__ cplx acc[CB * CS0];
   const int q = blockIdx.y;
   const int I = canon[4 * q], J = canon[4 * q + 1], K = canon[4 * q + 2], n0 = canon[4 * q + 3];
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   const int c0 = (cube / (nc * nc)) * CB, c1 = ((cube / nc) % nc) * CB, c2 = (cube % nc) * CB;  // cube corner
   // (selects rather than arrays indexed by the permutation, which would live in scratch memory)
   auto pick = [](int p, int a, int b, int c) { return p == 0 ? a : p == 1 ? b : c; };
-  const int64_t v3 = (int64_t)v * v * v;
+  const int64_t vb = (int64_t)v * v * vp;  // block stride; element [X0][X1][X2] at (X0*v + X1)*vp + X2
   for (int e = threadIdx.x; e < CB * CS0; e += blockDim.x) acc[e] = cplx{0, 0};
   __syncthreads();
   const int nn = o + v;
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
     const int x0 = pick(p0, c0, c1, c2), x1 = pick(p1, c0, c1, c2), x2 = pick(p2, c0, c1, c2);
-    const cplx* src = W + (int64_t)sl[s] * v3;
+    const cplx* src = W + (int64_t)sl[s] * vb;
     const int si = pick(p0, I, J, K), sj = pick(p1, I, J, K), sk = pick(p2, I, J, K);  // the source's occupied triple
     if (LAM) {
       static_assert(CB == 8, "the staging below maps 256 threads onto four 8x8 tables");
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
       const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
       if (X0 < v && X1 < v && X2 < v) {
-        cplx w = src[((int64_t)X0 * v + X1) * v + X2];
+        cplx w = src[((int64_t)X0 * v + X1) * vp + X2];
         if (LAM) {
           //   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik at the source's indices
           w = cadd(w, cmul(lt[0][u0][u1], lv[0][u2]));
@@ -291,12 +292,12 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
     const int x0 = pick(p0, c0, c1, c2), x1 = pick(p1, c0, c1, c2), x2 = pick(p2, c0, c1, c2);
-    cplx* dst = T + (int64_t)sl[s] * v3;
+    cplx* dst = T + (int64_t)sl[s] * vb;
     for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
       const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
       if (X0 < v && X1 < v && X2 < v)
-        dst[((int64_t)X0 * v + X1) * v + X2] = acc[u0 * cstride(p0) + u1 * cstride(p1) + u2 * cstride(p2)];
+        dst[((int64_t)X0 * v + X1) * vp + X2] = acc[u0 * cstride(p0) + u1 * cstride(p1) + u2 * cstride(p2)];
     }
   }
 }
@@ -381,14 +382,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const cplx* __restrict__ A, c
 }  // namespace
 
 void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
-                     int v, const LamElem* le, hipStream_t s) {
+                     int v, int vp, const LamElem* le, hipStream_t s) {
+  RTCC3_CHECK(vp >= v, "sym: row stride below v");
   if (ncanon <= 0) return;
   const int nc = (v + CB - 1) / CB;
   const dim3 grid((unsigned)(nc * nc * nc), (unsigned)ncanon);
   if (le) {
-    hipLaunchKernelGGL(sym_cube_kernel<true>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, *le);
+    hipLaunchKernelGGL(sym_cube_kernel<true>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, vp, *le);
   } else {
-    hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, LamElem{});
+    hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, vp, LamElem{});
   }
   RTCC3_HIP(hipGetLastError());
 }
@@ -407,15 +409,16 @@ void launch_gram(const cplx* A, const cplx* B, const int* slabs, int nslab, int 
 }
 
 void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, const cplx* F, const cplx* l2, cplx* X1,
-                     cplx* X2p, cplx* Z, int o, int v, int flags, hipStream_t s) {
+                     cplx* X2p, cplx* Z, int o, int v, int vp, int flags, hipStream_t s) {
+  RTCC3_CHECK(vp >= v, "small_t3: row stride below v");
   if (nb <= 0) return;
   if (v <= 64) {
     const unsigned nyc = (unsigned)((v + SW_NW - 1) / SW_NW);
     hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb, nyc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p,
-                       Z, o, v, flags);
+                       Z, o, v, vp, flags);
   } else {
     hipLaunchKernelGGL(small_t3_simple_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1,
-                       X2p, Z, o, v, flags);
+                       X2p, Z, o, v, vp, flags);
   }
   RTCC3_HIP(hipGetLastError());
 }

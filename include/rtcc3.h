@@ -111,7 +111,8 @@ int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
 
 /* Options: RTCC3_OPT_TRIPLES (1 = CC3, 0 = CCSD model), RTCC3_OPT_PRECISION,
  * RTCC3_OPT_WINDOW_BLOCKS: the most ordered occupied triples (i,j,k) whose t3
- * and lambda3 blocks are held at once (4 * 16 * v^3 bytes each); 0 (default)
+ * and lambda3 blocks are held at once (4 * 16 * v*v*vp bytes each, vp = v rounded up to
+ * a multiple of 8); 0 (default)
  * sizes the windows from half the free device memory, at most 48 GiB.  Values
  * below 6 count as 6 (a window holds every ordering of a triple), and the
  * windows of the density pass hold whole slabs (i,l,k) of an occupied pair

@@ -56,7 +56,7 @@ enum {
 /* Precision of the triples contractions (the paper's single- versus
  * double-precision comparison, Section 3 and Table 1).  Denominators, residual
  * accumulation, RK4 and the dipole always stay in FP64.
- *   RTCC3_FP64    FP64 matrix cores
+ *   RTCC3_FP64    FP64 matrix cores (complex products as three real products)
  *   RTCC3_FP32    operands rounded to FP32, FP32 matrix cores and accumulation
  *   RTCC3_BF16X3  each real operand split into three bf16 slices (about FP32's
  *                 24 significand bits), six slice products on the bf16 matrix

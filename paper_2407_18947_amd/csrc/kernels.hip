@@ -1,5 +1,6 @@
-// Generic kernels: batched complex GEMM on the matrix cores (FP64 or FP32
-// MFMA, complex product as four real products), strided axpy/permute, fill.
+// Generic kernels: batched complex GEMM on the matrix cores (FP64 MFMA with
+// the complex product as three real products, FP32 MFMA with four), strided
+// axpy/permute, fill.
 #include <algorithm>
 #include <type_traits>
 
@@ -292,16 +293,27 @@ __device__ __forceinline__ void put(const GemmDesc& d, cplx* C, int64_t ro, int6
 // One workgroup computes a 64 x BN tile of C for one batch entry.  BN = 64:
 // waves arranged 2x2, each owning a 32x32 sub-tile = 2x2 MFMA 16x16 blocks;
 // BN = 16 (narrow N, e.g. one occupied index): waves stacked 4x1, each owning
-// one 16x16 block.  Every block has a real and an imaginary accumulator:
-//   Cre += Are*Bre - Aim*Bim,  Cim += Are*Bim + Aim*Bre.
+// one 16x16 block.  Every block has a real and an imaginary accumulator,
+//   Cre += Are*Bre - Aim*Bim,  Cim += Are*Bim + Aim*Bre,
+// and in FP64 a third, for the three-product form below.
 // MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16].
 // Result layout: FP32 holds D[4*(l/16)+r][l%16] in register r, FP64 holds
 // D[4*r+l/16][l%16] (Frag<T>::row).
 // Tiles of A and B go through two LDS buffers: while the MFMAs consume one,
 // the next tile is loaded into registers and then stored into the other, so
 // each K step needs one barrier.
+// FP64: the workgroups per CU that the LDS tiles allow (160 KB per CU; one
+// wave per SIMD each), at most three, to which the register allocation is held
+// so that the scheduler does not trade that occupancy for registers.  FP32: no
+// bound.
+template <typename T, int BN, bool SEG, int CMB>
+constexpr int zgemm_waves() {
+  constexpr int lds = (SEG ? 1 : 2) * 2 * 16 * ((BM + 1) + (BN + 1)) * (int)sizeof(T) + (CMB == 3 ? 4096 : 0);
+  return std::is_same<T, double>::value ? std::min(3, 160 * 1024 / lds) : 1;
+}
 template <typename T, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG, int CMB = 0>
-__global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int kchunk) {
+__global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_kernel(GemmDesc d, int ksplit,
+                                                                                  int kchunk) {
   typedef typename Frag<T>::acc acc_t;
   constexpr int BK = 16;
   constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
@@ -356,13 +368,21 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
     }
   };
 
-  acc_t cre[IB][JB], cim[IB][JB];
+  // FP64: the complex product as three real products (Gauss),
+  //   P1 = (Ar + Ai) Br,  P2 = Ar (Bi - Br),  P3 = Ai (Br + Bi),
+  //   Re = P1 - P3,  Im = P1 + P2,
+  // accumulated in cre, cim and c3 and combined after the K loop.  With real
+  // operands P2 = -P1 bit for bit, so the imaginary part stays exactly zero.
+  // FP32 keeps the four products of the plain definition.
+  constexpr bool M3 = std::is_same<T, double>::value;
+  acc_t cre[IB][JB], cim[IB][JB], c3[M3 ? IB : 1][M3 ? JB : 1];
 #pragma unroll
   for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
       cre[i][j] = acc_t{0, 0, 0, 0};
       cim[i][j] = acc_t{0, 0, 0, 0};
+      if constexpr (M3) c3[i][j] = acc_t{0, 0, 0, 0};
     }
 
   const int nsteps = (kend - kbeg + BK - 1) / BK;
@@ -389,27 +409,60 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmDesc d, int ksplit, int k
         br[j] = sB[cur][0][kr][wn + 16 * j + c16];
         bi[j] = sB[cur][1][kr][wn + 16 * j + c16];
       }
-      // four independent MFMAs between two that update the same accumulator
+      if constexpr (M3) {
+        T sa[IB], db[JB], sb[JB];
 #pragma unroll
-      for (int i = 0; i < IB; ++i)
+        for (int i = 0; i < IB; ++i) sa[i] = ar[i] + ai[i];
 #pragma unroll
-        for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
+        for (int j = 0; j < JB; ++j) {
+          db[j] = bi[j] - br[j];
+          sb[j] = br[j] + bi[j];
+        }
 #pragma unroll
-      for (int i = 0; i < IB; ++i)
+        for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
+          for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(sa[i], br[j], cre[i][j]);
 #pragma unroll
-      for (int i = 0; i < IB; ++i)
+        for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
+          for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ar[i], db[j], cim[i][j]);
 #pragma unroll
-      for (int i = 0; i < IB; ++i)
+        for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
+          for (int j = 0; j < JB; ++j) c3[i][j] = Frag<T>::mfma(ai[i], sb[j], c3[i][j]);
+      } else {
+        // four independent MFMAs between two that update the same accumulator
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
+      }
     }
     if (NBUF == 1) __syncthreads();  // every wave is done with the buffer
     stash(NBUF == 2 ? cur ^ 1 : 0);
     __syncthreads();
+  }
+  if constexpr (M3) {
+#pragma unroll
+    for (int i = 0; i < IB; ++i)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        const acc_t p1 = cre[i][j];
+        cre[i][j] = p1 - c3[i][j];
+        cim[i][j] = p1 + cim[i][j];
+      }
   }
 
   if (CMB == 5) {

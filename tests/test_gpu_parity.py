@@ -77,6 +77,23 @@ def test_zgemm_selftest(M, N, K, prec):
     assert bad.size == 0, f"rows with errors: {bad[:20].tolist()} max err {err.max():.3e}"
 
 
+@pytest.mark.parametrize("M,N,K", [(64, 64, 16), (100, 70, 129), (70, 15, 300), (15, 70, 300), (130, 3, 1000)])
+def test_zgemm_fp64_real_operands_stay_real(M, N, K):
+    """FP64 forms a complex product from three real products, (Ar+Ai)Br,
+    Ar(Bi-Br) and Ai(Br+Bi).  Real operands must still give an exactly real
+    product, and an imaginary A times a real B an exactly imaginary one (the
+    two products that cancel are the same numbers with opposite signs)."""
+    _say(f"zgemm real/imaginary {M}x{N}x{K}")
+    rng = np.random.default_rng(7 * M + N + K)
+    Ar, Br = rng.normal(size=(M, K)), rng.normal(size=(K, N))
+    C = _lib.rtcc3_zgemm_selftest(Ar.astype(complex), Br.astype(complex), 0)
+    assert np.all(C.imag == 0.0), f"imaginary part {np.abs(C.imag).max():.3e}"
+    _close("real x real", C.real, Ar @ Br, 1e-13 * np.sqrt(K))
+    C = _lib.rtcc3_zgemm_selftest(1j * Ar, Br.astype(complex), 0)
+    assert np.all(C.real == 0.0), f"real part {np.abs(C.real).max():.3e}"
+    _close("imaginary x real", C.imag, Ar @ Br, 1e-13 * np.sqrt(K))
+
+
 @pytest.mark.parametrize("o,v", [(2, 3), (3, 4), (5, 19)])
 def test_ccsd_terms(o, v):
     _say(f"ccsd terms o={o} v={v}")

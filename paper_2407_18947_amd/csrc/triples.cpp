@@ -193,7 +193,7 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
 void Triples::free_windows() {
   for (auto* ws : {&rhs_windows_, &den_windows_}) {
     for (auto& w : *ws) {
-      for (int* p : {w.d_bl, w.d_part, w.d_owned, w.d_canon, w.d_slabs})
+      for (int* p : {w.d_bl, w.d_part, w.d_owned, w.d_canon, w.d_slabs, w.d_orb, w.d_orb_owned})
         if (p) (void)hipFree(p);
       for (Groups* gr : {&w.gJ, &w.gK})
         for (int* p : {gr->d_key, gr->d_start, gr->d_bl})
@@ -390,6 +390,28 @@ void Triples::upload(Window& w) {
     put(&gr.d_start, gr.start);
     put(&gr.d_bl, gr.bl);
   }
+  // The block tables again with the orderings of each occupied triple
+  // consecutive: a product that reads an entry's permuted partners then has
+  // them read by neighbouring workgroups, which run at the same time and find
+  // them in the cache, instead of by workgroups a slab of o^2 blocks away.
+  auto orbits = [](const std::vector<int>& t) {
+    std::map<std::array<int, 3>, std::vector<int>> by;
+    for (size_t e = 0; e < t.size(); e += 4) {
+      std::array<int, 3> key{t[e], t[e + 1], t[e + 2]};
+      std::sort(key.begin(), key.end());
+      by[key].push_back((int)e);
+    }
+    std::vector<int> out;
+    for (auto& kv : by)
+      for (int e : kv.second) out.insert(out.end(), t.begin() + e, t.begin() + e + 4);
+    return out;
+  };
+  w.orb = orbits(w.bl);
+  put(&w.d_orb, w.orb);
+  if (!w.owned.empty()) {
+    w.orb_owned = orbits(w.owned);
+    put(&w.d_orb_owned, w.orb_owned);
+  }
   RTCC3_HIP(hipMalloc(&w.d_bl, sizeof(int) * w.bl.size()));
   RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
   RTCC3_HIP(hipMalloc(&w.d_part, sizeof(int) * w.part.size()));
@@ -573,6 +595,8 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int* cbl = pairwin ? w.d_owned : bl;
   const int* cblh = pairwin ? w.owned.data() : blh;
   const int cn = pairwin ? (int)w.owned.size() / 4 : nw;
+  const int* obl = pairwin ? w.d_orb_owned : w.d_orb;  // the same entries, grouped by occupied triple
+  const int* oblh = pairwin ? w.orb_owned.data() : w.orb.data();
   if (rhs_terms) {
     // S needs only t2 and integrals: it goes first on the lambda3 side, beside
     // the t3 symmetrisation (memory bound) rather than beside other products
@@ -679,7 +703,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     };
     {  // X2: sum_ce Z1[b][(c,e)] (ac|ke)~ into X2p[I][J][a][b], with (c,e) contiguous:
        //   Z1[b][c][e] = (2 T_JIK - T_KIJ - T_JKI)[b][c][e]
-      GemmDesc g = base(v, v, (int)v2, cn, cbl, pr);
+      GemmDesc g = base(v, v, (int)v2, cn, obl, pr);
       g.atomic = 1;
       g.K0 = v;  // k = (c,e)
       g.A = gX2a;
@@ -697,7 +721,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
-      checked_gemm(g, cblh, lOVVV, winlen, oovv, s);
+      checked_gemm(g, oblh, lOVVV, winlen, oovv, s);
     }
     // X2 -= sum_c Zh[(a,b)][c] G[K][I][c][x] into X2p[x][J], G[k][m][c][x] = (kx|mc)~.
     // The contraction set holds every ordering of its triples, so each term of

@@ -39,11 +39,15 @@ struct Window {
   std::vector<int> slabs;     // density windows: [*][4] = (0, 0, 0, slot of block (0,l,k)); the o blocks
                               // (i,l,k) of a slab occupy consecutive slots in i
   Groups gJ, gK;              // contraction blocks grouped by J and by K
+  std::vector<int> orb;       // bl, and owned, with the orderings of each occupied triple consecutive
+  std::vector<int> orb_owned;
   int* d_bl = nullptr;
   int* d_part = nullptr;
   int* d_owned = nullptr;
   int* d_canon = nullptr;
   int* d_slabs = nullptr;
+  int* d_orb = nullptr;
+  int* d_orb_owned = nullptr;
 };
 
 class Triples {

@@ -86,6 +86,12 @@ struct TileLoader {
   int kend, sk1, sk2, sk3, m0, n0;
   float invK0;
   cplx av[NEA], bv[NEB];
+  // CMB = 1 / 2: the three loaded parts of each combined element, combined
+  // only when the tile is stored (settle), so that the loads stay in flight
+  // during the MFMAs instead of being waited for right away
+  static constexpr int NX = CMB == 1 ? NEA : CMB == 2 ? NEB : 1;
+  cplx xr[NX][3];
+  bool xok[NX];
 
   // Returns the entry's C base.
   __device__ __forceinline__ cplx* init(const GemmDesc& d, int64_t b, int tm, int tn, int kend_) {
@@ -186,13 +192,28 @@ struct TileLoader {
     const cplx x = p[o];
     return cplx{ok ? x.re : 0.0, ok ? x.im : 0.0};
   }
-  __device__ __forceinline__ cplx fetch3(bool ok, int64_t off) const {
+  __device__ __forceinline__ void fetch3(int e, bool ok, int64_t off) {
     int64_t o = ok ? off : 0;
     asm volatile("" : "+v"(o));
-    const cplx x0 = Xc[0][o], x1 = Xc[1][o], x2 = Xc[2][o];
-    const double re = wc[0] * x0.re + wc[1] * x1.re + wc[2] * x2.re;
-    const double im = wc[0] * x0.im + wc[1] * x1.im + wc[2] * x2.im;
-    return cplx{ok ? re : 0.0, ok ? im : 0.0};
+    xr[e][0] = Xc[0][o];
+    xr[e][1] = Xc[1][o];
+    xr[e][2] = Xc[2][o];
+    xok[e] = ok;
+  }
+  // Combined elements of the last load into av (CMB = 1) or bv (CMB = 2).
+  __device__ __forceinline__ void settle() {
+    if constexpr (CMB == 1 || CMB == 2) {
+#pragma unroll
+      for (int e = 0; e < NX; ++e) {
+        const double re = wc[0] * xr[e][0].re + wc[1] * xr[e][1].re + wc[2] * xr[e][2].re;
+        const double im = wc[0] * xr[e][0].im + wc[1] * xr[e][1].im + wc[2] * xr[e][2].im;
+        const cplx x{xok[e] ? re : 0.0, xok[e] ? im : 0.0};
+        if constexpr (CMB == 1)
+          av[e] = x;
+        else
+          bv[e] = x;
+      }
+    }
   }
   // Offset of the q-th gathered block of the entry in operand x (0 = A, 1 = B).
   __device__ __forceinline__ int64_t gather_off(int x, int q) const { return gofs[2 * (q - gq0) + x]; }
@@ -239,7 +260,10 @@ struct TileLoader {
       for (int t = 0; t < NMA; ++t) {
         const int e = KFA ? t : s;
         const bool ok = k < kend && aval[KFA ? t : 0];
-        av[e] = CMB == 1 ? fetch3(ok, aoff[KFA ? t : 0] + ko) : fetch(A, ok, aoff[KFA ? t : 0] + ko);
+        if constexpr (CMB == 1)
+          fetch3(e, ok, aoff[KFA ? t : 0] + ko);
+        else
+          av[e] = fetch(A, ok, aoff[KFA ? t : 0] + ko);
       }
     }
 #pragma unroll
@@ -253,10 +277,12 @@ struct TileLoader {
       for (int t = 0; t < NNB; ++t) {
         const int e = NFB ? s : t;
         const bool ok = k < kend && bval[NFB ? 0 : t];
-        if (CMB == 5)
+        if constexpr (CMB == 5)
           bv[e] = fetch(Bq[t], ok, (int64_t)k * sbq[t]);
+        else if constexpr (CMB == 2)
+          fetch3(e, ok, boff[NFB ? 0 : t] + ko);
         else
-          bv[e] = CMB == 2 ? fetch3(ok, boff[NFB ? 0 : t] + ko) : fetch(B, ok, boff[NFB ? 0 : t] + ko);
+          bv[e] = fetch(B, ok, boff[NFB ? 0 : t] + ko);
       }
     }
   }
@@ -356,6 +382,7 @@ __global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_ke
   }
 
   auto stash = [&](int buf) {
+    ld.settle();
 #pragma unroll
     for (int r = 0; r < Loader::NEA; ++r) {
       sA[buf][0][ld.akk[r]][ld.amm[r]] = (T)ld.av[r].re;

@@ -33,9 +33,9 @@ SLICE_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
 # profiles/build_product_trimer_o15_v57_fp64_traffic.md (FETCH_SIZE, WRITE_SIZE,
 # scaled by a 1 GiB copy).  Valid only for the sources they were measured on.
 MEASURED_TRAFFIC = {
-    "fingerprint": {"kernels.hip": "829a542fcc28d88c", "triples.cpp": "5832fda0c7ace266"},
+    "fingerprint": {"kernels.hip": "829a542fcc28d88c", "triples.cpp": "53f9dc0bff870672"},
     "config": (15, 57, "fp64"),
-    "bytes_per_launch": 17.329e9 + 8.447e9,
+    "bytes_per_launch": 17.330e9 + 8.447e9,
 }
 
 
@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-blocks", type=int, default=60, help="oracle blocks timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--single-stream", action="store_true",
+                    help="every kernel on one stream, one after another (times each kernel alone; not the metric)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -140,6 +142,8 @@ def main():
     def run(precision):
         """W warm-up steps, then K timed steps; returns (s, dipole series, timing)."""
         ctx = _lib.Context(s, codes[precision])
+        if args.single_stream:
+            ctx.set_option(_lib.RTCC3_OPT_SINGLE_STREAM, 1)
         ctx.set_state(y0)
         mu_w = ctx.propagate(W, dt, field[: 2 * W + 1]) if W > 0 else None
         torch.cuda.synchronize()
@@ -188,6 +192,7 @@ def main():
             "workload": (f"RT-CC3 T+Lambda, o={o}, v={v}, naux={s.naux}, seeded synthetic water-trimer-sized "
                          f"integrals (seed {args.seed}), delta kick {amp} a.u. along z, dt={dt}"),
             "o": o, "v": v, "naux": s.naux, "precision": args.precision,
+            **({"single_stream": True} if args.single_stream else {}),
         },
         # Dominant kernel: the segmented store-mode product, launched for a
         # window's t3 blocks, its lambda3 blocks (before symmetrisation) and

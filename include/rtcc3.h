@@ -117,8 +117,13 @@ int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
  * below 6 count as 6 (a window holds every ordering of a triple), and the
  * windows of the density pass hold whole slabs (i,l,k) of an occupied pair
  * (l,k), about 6*o blocks, however small the value.  The answer does not
- * depend on it.  Setting it waits for the context's streams. */
-enum { RTCC3_OPT_TRIPLES = 1, RTCC3_OPT_PRECISION = 2, RTCC3_OPT_WINDOW_BLOCKS = 3 };
+ * depend on it.  Setting it waits for the context's streams.
+ * RTCC3_OPT_SINGLE_STREAM: 1 = every kernel on the context's stream, one after
+ * another (for timing each kernel alone); 0 (default) = the lambda3 side of the
+ * triples and the CCSD reverse sweep on two streams of the context's own.  The
+ * answer does not depend on it (up to the order of atomic additions).  Setting
+ * it waits for the context's streams. */
+enum { RTCC3_OPT_TRIPLES = 1, RTCC3_OPT_PRECISION = 2, RTCC3_OPT_WINDOW_BLOCKS = 3, RTCC3_OPT_SINGLE_STREAM = 4 };
 int rtcc3_set_option(rtcc3_ctx *ctx, int option, int value);
 
 /* Timing of the last rtcc3_propagate (milliseconds, from HIP events on the

@@ -17,7 +17,7 @@ LIBPATH = os.path.join(_HERE, "librtcc3.so")
 
 RTCC3_OK, RTCC3_EINVAL, RTCC3_ENOMEM, RTCC3_EDEVICE, RTCC3_ESTATE, RTCC3_EDIVERGED = 0, -1, -2, -3, -4, -5
 RTCC3_FP64, RTCC3_FP32, RTCC3_BF16X3, RTCC3_BF16X2 = 0, 1, 2, 3
-RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION, RTCC3_OPT_WINDOW_BLOCKS = 1, 2, 3
+RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION, RTCC3_OPT_WINDOW_BLOCKS, RTCC3_OPT_SINGLE_STREAM = 1, 2, 3, 4
 
 EXPORTS = [
     "rtcc3_create", "rtcc3_set_state", "rtcc3_get_state", "rtcc3_rhs", "rtcc3_rhs_terms", "rtcc3_propagate",

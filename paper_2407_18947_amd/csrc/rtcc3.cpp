@@ -30,7 +30,9 @@ struct rtcc3_ctx {
   std::string err;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // the CCSD reverse sweep runs on side_stream beside the triples windows
+  // (on stream itself with single_stream)
   hipStream_t side_stream = nullptr;
+  int single_stream = 0;
   hipEvent_t ev_side1 = nullptr;
 };
 
@@ -96,7 +98,7 @@ void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const Te
     // lambda3 build, which itself follows them)
     to = c->tri->run(e, d, r, y, want_density, [&](hipEvent_t after) -> hipEvent_t {
       RTCC3_HIP(hipStreamWaitEvent(c->side_stream, after, 0));
-      e.stream = c->side_stream;
+      e.stream = c->single_stream ? c->stream : c->side_stream;
       try {
         ccsd_backward(e, d, y, c->ones_o, r);
       } catch (...) {
@@ -442,6 +444,15 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
     c->precision = value;
     c->tri->set_precision(value);
     return RTCC3_OK;
+  }
+  if (option == RTCC3_OPT_SINGLE_STREAM) {
+    return guarded(c, [&]() -> int {
+      RTCC3_HIP(hipStreamSynchronize(c->stream));
+      RTCC3_HIP(hipStreamSynchronize(c->side_stream));
+      c->single_stream = value ? 1 : 0;
+      c->tri->set_single_stream(value != 0);
+      return RTCC3_OK;
+    });
   }
   if (option == RTCC3_OPT_WINDOW_BLOCKS) {
     if (value < 0) return fail(c, RTCC3_EINVAL, "negative window size");

@@ -499,7 +499,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int64_t ylen = 2 * (ov + oovv);
   const int nw = w.nw;
   hipStream_t s = e.stream;  // t3 side
-  hipStream_t s2 = s2_;      // lambda3 side
+  hipStream_t s2 = single_ ? s : s2_;  // lambda3 side
   const cplx* t2 = y + ov;
   const cplx* l1 = y + ov + oovv;
   const cplx* l2 = y + 2 * ov + oovv;

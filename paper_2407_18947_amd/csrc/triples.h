@@ -69,6 +69,9 @@ class Triples {
   TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density,
                  const Beside& beside = nullptr);
   void set_precision(int p) { prec_ = p; }
+  // All work on the caller's stream, one kernel after another (for timing
+  // kernels alone); the default runs the lambda3 side on a second stream.
+  void set_single_stream(bool on) { single_ = on; }
   // Cap the blocks per window (0: sized from free device memory) and rebuild
   // the windows; the window buffers are released and reallocated on use.
   void set_window_blocks(Engine& e, int n);
@@ -95,6 +98,7 @@ class Triples {
  private:
   Dims d_;
   int prec_;
+  bool single_ = false;
   double* eps_ = nullptr;  // device
   std::vector<Window> rhs_windows_, den_windows_;
   int max_nw_ = 0;

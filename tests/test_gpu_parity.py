@@ -156,6 +156,26 @@ def test_rhs_matches_oracle_windows(wb):
     ctx.close()
 
 
+def test_single_stream_matches_default():
+    """With every kernel on one stream the terms are those of the default
+    three-stream run (up to the order of atomic additions)."""
+    o, v = 5, 9
+    _say(f"single stream o={o} v={v}")
+    s = make_system(o, v, seed=21)
+    y = _random_state(o, v, 10)
+    ref = _gpu_terms(s, y, FIELD, 1)
+    ctx = _lib.Context(s)
+    ctx.set_option(_lib.RTCC3_OPT_SINGLE_STREAM, 1)
+    yd = torch.tensor(y, dtype=torch.complex128, device="cuda")
+    td = torch.zeros(ctx.terms_size(), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    _lib.rtcc3_rhs_terms(ctx.ctx, FIELD, yd, td, 1)
+    got = ctx.split_terms(td.cpu().numpy())
+    ctx.close()
+    for name in ref:
+        _close(name, got[name], ref[name], 1e-12)
+
+
 def test_rhs_matches_oracle():
     o, v = 3, 5
     _say(f"rhs o={o} v={v}")

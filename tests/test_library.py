@@ -64,3 +64,31 @@ def test_gemm_selftest_rejects_bad_sizes():
     L = _lib.load()
     assert L.rtcc3_zgemm_selftest(0, 1, 1, 0, None, None, None) == _lib.RTCC3_EINVAL
     assert L.rtcc3_zgemm_selftest(1, 1, 1, 5, None, None, None) == _lib.RTCC3_EINVAL
+
+
+def test_header_constants_match_binding():
+    """Every enumerator the header defines has the same value in the binding."""
+    txt = open(os.path.join(ROOT, "include", "rtcc3.h")).read()
+    consts = {}
+    for body in re.findall(r"enum\s*\{([^}]*)\}", txt):
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        for name, val in re.findall(r"\b(RTCC3_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            consts[name] = int(val)
+    assert {"RTCC3_OK", "RTCC3_FP64", "RTCC3_OPT_WINDOW_BLOCKS", "RTCC3_OPT_SINGLE_STREAM"} <= set(consts)
+    for name, val in consts.items():
+        assert getattr(_lib, name) == val, name
+
+
+def test_options_reject_null_context():
+    L = _lib.load()
+    for opt in (_lib.RTCC3_OPT_TRIPLES, _lib.RTCC3_OPT_PRECISION, _lib.RTCC3_OPT_WINDOW_BLOCKS,
+                _lib.RTCC3_OPT_SINGLE_STREAM):
+        assert L.rtcc3_set_option(None, opt, 1) == _lib.RTCC3_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stdout

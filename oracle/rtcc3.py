@@ -48,7 +48,9 @@ C128 = torch.complex128
 #   L = E + sum_ia l1_ia Omega_ia + C2 * sum_ijab l2_ijab Omega_ijab
 # over all tensor elements.  Its value is fixed by requiring the paper's
 # printed triples equations (lambda3, Y1, Y2, density) to be its derivatives;
-# the tests pin it (test_oracle_lagrangian.py).
+# the tests pin it (tests/test_oracle_pins.py: the printed Y1, Y2 are the
+# Lagrangian's derivatives, and lambda3 and the densities equal their
+# determinant-space bra-ket expressions).
 C2 = 0.5
 
 
@@ -596,3 +598,105 @@ def lagrangian(m: Model, y, E, triples="explicit", with_triples=True):
         X1, X2 = x_full(ti, t3)
         val = val + (l1 * X1).sum() + C2 * (l2 * X2).sum()
     return val
+
+
+# -----------------------------------------------------------------------------
+# Stationary (ground-state) amplitudes at a static field
+# -----------------------------------------------------------------------------
+
+def _diis(x0, step, tol, maxiter, nvec=8):
+    """Fixed-point iteration x <- x + dx(x) with Pulay (DIIS) extrapolation over
+    the last nvec iterates; stops when the residual norm reported by step is
+    below tol.  step(x) returns (dx, residual max-norm)."""
+    xs, es = [], []
+    x = x0
+    for it in range(maxiter):
+        dx, res = step(x)
+        if res < tol:
+            return x, it
+        xs.append(x + dx)
+        es.append(dx)
+        if len(xs) > nvec:
+            xs.pop(0)
+            es.pop(0)
+        k = len(xs)
+        if k < 2:
+            x = xs[-1]
+            continue
+        Bm = np.zeros((k + 1, k + 1), dtype=np.complex128)
+        for a in range(k):
+            for b in range(k):
+                Bm[a, b] = np.vdot(es[a], es[b])
+        Bm[k, :k] = Bm[:k, k] = -1.0
+        rhs_ = np.zeros(k + 1, dtype=np.complex128)
+        rhs_[k] = -1.0
+        try:
+            c = np.linalg.solve(Bm, rhs_)[:k]
+        except np.linalg.LinAlgError:
+            c = np.zeros(k, dtype=np.complex128)
+            c[-1] = 1.0
+        x = sum(ci * xi for ci, xi in zip(c, xs))
+    raise RuntimeError(f"ground state: no convergence in {maxiter} iterations (residual {res:.3e})")
+
+
+def _denominators(m: Model):
+    o = m.o
+    eo, ev = m.eps[:o].numpy(), m.eps[o:].numpy()
+    d1 = ev[None, :] - eo[:, None]
+    d2 = (ev[None, None, :, None] + ev[None, None, None, :] - eo[:, None, None, None] - eo[None, :, None, None])
+    return d1, d2
+
+
+def ground_state(m: Model, E=(0.0, 0.0, 0.0), triples="explicit", with_triples=True, tol=1e-12, maxiter=300,
+                 lam=True):
+    """Stationary amplitudes of the field-free (or static-field) equations.
+
+    The time derivatives of eq. cc3-rt-t and eq. cc3-rt-l vanish when
+    Omega + X = 0 (the T equations) and dL/dt = G + Y = 0 (the Lambda
+    equations).  Both are solved by Jacobi steps with the orbital-energy
+    denominators (e_a - e_i, e_a + e_b - e_i - e_j) and DIIS, T first (it does
+    not involve Lambda), then Lambda at the converged T.  The starting point is
+    t = 0, lambda = 0.  Returns (y, energy) with the CC energy
+    E = <0|H~|0> + sum t2 L of the T1-transformed Hamiltonian.
+    """
+    o, v = m.o, m.v
+    ov, oovv = o * v, o * o * v * v
+    d1, d2 = _denominators(m)
+    dvec = np.concatenate([d1.ravel(), d2.ravel()])
+    Eh = m.h(E)
+
+    def t_step(x):
+        t1 = torch.as_tensor(x[:ov].reshape(o, v))
+        t2 = torch.as_tensor(x[ov:].reshape(o, o, v, v))
+        with torch.no_grad():
+            d = Dressed(m, t1, Eh)
+            r1, r2 = ccsd_omega(d, t2)
+            if with_triples:
+                ti = TriplesIntegrals(d)
+                if triples == "explicit":
+                    X1, X2 = x_full(ti, t3_full(m, ti, t2))
+                else:
+                    z1 = torch.zeros_like(t1)
+                    tri = triples_loop(m, ti, t2, z1, torch.zeros_like(t2))
+                    X1, X2 = tri["X1"], tri["X2"]
+                r1, r2 = r1 + X1, r2 + X2
+        r = torch.cat([r1.reshape(-1), r2.reshape(-1)]).numpy()
+        return -r / dvec, np.abs(r).max()
+
+    xt, _ = _diis(np.zeros(ov + oovv, dtype=np.complex128), t_step, tol, maxiter)
+    t1 = torch.as_tensor(xt[:ov].reshape(o, v))
+    t2 = torch.as_tensor(xt[ov:].reshape(o, o, v, v))
+    with torch.no_grad():
+        energy = ccsd_energy(Dressed(m, t1, Eh), t2).item()
+    if not lam:
+        return pack(t1, t2, torch.zeros_like(t1), torch.zeros_like(t2)), energy
+
+    def l_step(x):
+        y = pack(t1, t2, torch.as_tensor(x[:ov].reshape(o, v)), torch.as_tensor(x[ov:].reshape(o, o, v, v)))
+        tm = rhs_terms(m, y, E, triples=triples, with_triples=with_triples, with_density=False)
+        r = torch.cat([(tm["G1"] + tm["Y1"]).reshape(-1), (tm["G2"] + tm["Y2"]).reshape(-1)]).numpy()
+        return -r / dvec, np.abs(r).max()
+
+    xl, _ = _diis(np.zeros(ov + oovv, dtype=np.complex128), l_step, tol, maxiter)
+    y = pack(t1, t2, torch.as_tensor(xl[:ov].reshape(o, v)), torch.as_tensor(xl[ov:].reshape(o, o, v, v)))
+    return y, energy

@@ -30,6 +30,11 @@
  * forks two streams of its own from it and joins them back within each call)
  * and the functions return after that stream has been synchronised.  A
  * context serves one thread at a time.
+ * Memory.  rtcc3_create allocates every device buffer the context will use (it
+ * evaluates the right-hand side once, on the zero state, to size them); no
+ * later call allocates device memory, except rtcc3_set_option with
+ * RTCC3_OPT_WINDOW_BLOCKS, which replaces the window buffers.  A request that
+ * would need more memory after creation fails with RTCC3_ESTATE.
  */
 #ifndef RTCC3_H
 #define RTCC3_H
@@ -103,7 +108,12 @@ int rtcc3_rhs_terms(rtcc3_ctx *ctx, const double E[3], const rtcc3_c64 *y_dev, r
 /* Propagate the context's state by `steps` RK4 steps of size dt (dt != 0).
  *   field       [(2*steps+1)*3] host: E(k*dt/2), k = 0..2*steps
  *   dipole_out  [(steps+1)*3] host: mu(t_n) for n = 0..steps (complex; may be NULL)
- * On EDIVERGED the state is left at the last finite step. */
+ * Each step's new state is checked on the device before it replaces the old
+ * one.  If a step gives a non-finite element, the call returns RTCC3_EDIVERGED
+ * (its message names the step), the state is left at the last finite state
+ * (after the steps before that one), and dipole_out holds the dipoles up to
+ * that state and NaN after it.  The dipoles of up to 1024 steps are kept on the
+ * device and copied out in chunks. */
 int rtcc3_propagate(rtcc3_ctx *ctx, int steps, double dt, const double *field, rtcc3_c64 *dipole_out);
 
 /* Dipole of the context's current state at field E[3] (host) -> out[3] (host). */
@@ -117,7 +127,8 @@ int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
  * below 6 count as 6 (a window holds every ordering of a triple), and the
  * windows of the density pass hold whole slabs (i,l,k) of an occupied pair
  * (l,k), about 6*o blocks, however small the value.  The answer does not
- * depend on it.  Setting it waits for the context's streams.
+ * depend on it.  Setting it waits for the context's streams, frees the window
+ * buffers and allocates those of the new size (the state is kept).
  * RTCC3_OPT_SINGLE_STREAM: 1 = every kernel on the context's stream, one after
  * another (for timing each kernel alone); 0 (default) = the lambda3 side of the
  * triples and the CCSD reverse sweep on two streams of the context's own.  The

@@ -75,10 +75,17 @@ class Model:
         J = torch.einsum("Ppq,P->pq", self.B, Bd)
         K = torch.einsum("Ppi,Piq->pq", self.B[:, :, :o], self.B[:, :o, :])
         self.h0 = torch.diag(self.eps) - (2.0 * J - K)
-        eo, ev = self.eps[:o], self.eps[o:]
-        self.d3 = (eo[:, None, None, None, None, None] + eo[None, :, None, None, None, None]
-                   + eo[None, None, :, None, None, None] - ev[None, None, None, :, None, None]
-                   - ev[None, None, None, None, :, None] - ev[None, None, None, None, None, :])
+        self._d3 = None
+
+    @property
+    def d3(self):
+        """D_ijk^abc for all six indices (explicit mode; built on first use)."""
+        if self._d3 is None:
+            eo, ev = self.eps[:self.o], self.eps[self.o:]
+            self._d3 = (eo[:, None, None, None, None, None] + eo[None, :, None, None, None, None]
+                        + eo[None, None, :, None, None, None] - ev[None, None, None, :, None, None]
+                        - ev[None, None, None, None, :, None] - ev[None, None, None, None, None, :])
+        return self._d3
 
     @classmethod
     def from_system(cls, s):
@@ -357,12 +364,15 @@ def density_triples_full(t2, l2, t3, l3):
     return Dij, Dab, Dia
 
 
-def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False, max_blocks=None):
+def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False, max_blocks=None, only=None):
     """Triples contributions evaluated one occupied triple at a time (Sec. 2.1).
 
     The loop runs over (l,k) and, inside, over i, building the [v,v,v] blocks
     t3_{ilk} and lambda3_{ilk}; the o blocks sharing (l,k) serve D_ij.
     Every other contraction takes the block of one ordered triple at a time.
+    max_blocks stops after that many blocks; only(I, J, K) -> bool skips the
+    blocks it rejects.  Either gives partial sums, exact for the elements that
+    depend only on the blocks visited.
     """
     o, v = m.o, m.v
     X1 = torch.zeros((o, v), dtype=C128)
@@ -381,6 +391,8 @@ def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False,
             tstack, lstack = [], []
             for I in range(o):
                 done += 1
+                if only is not None and not only(I, J, K):
+                    continue
                 t = t3_block(m, ti, t2, I, J, K)
                 lam = l3_block(m, ti, l1, l2, I, J, K)
                 tstack.append(t)
@@ -423,7 +435,7 @@ def triples_loop(m: Model, ti: TriplesIntegrals, t2, l1, l2, want_density=False,
                     # - sum lambda_bcd^{jkl} t_il^cd t_kj^ab, block = (j,k,l)
                     zz = torch.einsum("bcd,xcd->bx", lam, t2[:, K])
                     Dia -= torch.einsum("bx,ab->xa", zz, t2[J, I])
-            if want_density:
+            if want_density and tstack:
                 # D_ij = -1/2 sum t_{ilk} lambda_{jlk}, here (l,k) = (J,K)
                 ts = torch.stack(tstack)
                 ls = torch.stack(lstack)

@@ -121,11 +121,17 @@ def rtcc3_rhs_terms(ctx, E, y_dev, terms_dev, with_triples=1):
     _check(load().rtcc3_rhs_terms(ctx, _ptr(E), _ptr(y_dev), _ptr(terms_dev), int(with_triples)), ctx)
 
 
-def rtcc3_propagate(ctx, steps, dt, field):
+def rtcc3_propagate(ctx, steps, dt, field, mu=None):
+    """Returns the dipole series [(steps+1), 3]; `mu` (optional) receives it even
+    when the call raises (EDIVERGED leaves the entries after the last finite
+    state NaN)."""
     field = _f64(field)
     if field.shape != (2 * steps + 1, 3):
         raise ValueError("field must have shape (2*steps+1, 3)")
-    mu = np.empty((steps + 1, 3), dtype=np.complex128)
+    if mu is None:
+        mu = np.empty((steps + 1, 3), dtype=np.complex128)
+    if mu.shape != (steps + 1, 3) or mu.dtype != np.complex128 or not mu.flags.c_contiguous:
+        raise ValueError("mu must be a contiguous complex128 array of shape (steps+1, 3)")
     _check(load().rtcc3_propagate(ctx, int(steps), float(dt), _ptr(field), _ptr(mu)), ctx)
     return mu
 
@@ -197,7 +203,8 @@ class Context:
         rtcc3_set_option(self.ctx, option, value)
 
     def propagate(self, steps, dt, field):
-        return rtcc3_propagate(self.ctx, steps, dt, field)
+        self.last_dipoles = np.empty((steps + 1, 3), dtype=np.complex128)
+        return rtcc3_propagate(self.ctx, steps, dt, field, self.last_dipoles)
 
     def dipole(self, E):
         return rtcc3_dipole(self.ctx, E)

@@ -145,6 +145,12 @@ struct AxpyDesc {
 void axpy_strided(const AxpyDesc& d, hipStream_t s);
 
 void fill(cplx* p, int64_t n, cplx val, hipStream_t s);
+void fill_int(int* p, int64_t n, int val, hipStream_t s);
+// RK4 update guarded against divergence: cand = y + alpha * a; if an element of
+// cand is not finite, flag[0] becomes step + 1 unless it is already set; then
+// y = cand unless flag[0] is set.  Once a step diverges, y keeps the last
+// finite state for the rest of the propagation.  cand must not alias y or a.
+void guarded_update(cplx* y, const cplx* a, cplx alpha, cplx* cand, int64_t n, int* flag, int step, hipStream_t s);
 // dst[0..n) = src[0..n) on the device (non-overlapping).  A kernel on the
 // stream, not a DMA-engine copy, so it orders with the kernels around it
 // without an engine switch.

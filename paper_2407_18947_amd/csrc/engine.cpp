@@ -19,6 +19,7 @@ int Engine::buffer(const std::string& name, int64_t n) {
     RTCC3_CHECK(bufs_[it->second].n == n, "engine: buffer '" + name + "' requested with a different size");
     return it->second;
   }
+  if (sealed_) throw Error(-4, "engine: buffer '" + name + "' requested after the context was set up");
   Buf b;
   b.name = name;
   b.n = n;
@@ -132,6 +133,7 @@ View Engine::diag(View v, int d0, int d1) {
 
 cplx* Engine::scratch(int64_t n) {
   if (n > scratch_n_) {
+    if (sealed_) throw Error(-4, "engine: scratch grown after the context was set up");
     // work on any stream may still read the old scratch
     RTCC3_HIP(hipDeviceSynchronize());
     if (scratch_) RTCC3_HIP(hipFree(scratch_));
@@ -149,6 +151,7 @@ View Engine::grad(const View& v) {
   RTCC3_CHECK(v.buf >= 0 && bufs_[v.buf].rg, "engine: grad() of a view without gradient");
   Buf& b = bufs_[v.buf];
   if (!b.g) {
+    if (sealed_) throw Error(-4, "engine: gradient of '" + b.name + "' requested after the context was set up");
     hipError_t e = hipMalloc(&b.g, sizeof(cplx) * b.n);
     if (e != hipSuccess) throw Error(-2, "engine: out of device memory for a gradient");
     RTCC3_HIP(hipMemsetAsync(b.g, 0, sizeof(cplx) * b.n, stream));

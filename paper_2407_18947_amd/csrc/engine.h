@@ -35,6 +35,12 @@ class Engine {
   hipStream_t stream;
   int prec = 0;  // GEMM precision used by einsum (0 = FP64)
 
+  // Once sealed, a request that would allocate device memory (a new named
+  // buffer, a larger scratch, a first gradient) throws ESTATE instead: the
+  // context allocates everything it needs at creation, so nothing is
+  // allocated while amplitudes are propagated.
+  void seal(bool on) { sealed_ = on; }
+
   // Named buffers, allocated once and reused (get-or-create).
   int buffer(const std::string& name, int64_t n);
   // Free a named buffer after the stream has drained (the name may then be
@@ -88,6 +94,7 @@ class Engine {
   std::map<std::string, int> names_;
   std::vector<Op> tape_;
   bool recording_ = false;
+  bool sealed_ = false;
   cplx* scratch_ = nullptr;
   int64_t scratch_n_ = 0;
 

@@ -822,6 +822,35 @@ __global__ void fill_kernel(cplx* p, int64_t n, cplx v) {
     p[e] = v;
 }
 
+__global__ void fill_int_kernel(int* p, int64_t n, int v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// cand = y + alpha * a, and the first step whose candidate has a non-finite
+// element into flag[0] (as step + 1)
+__global__ void update_candidate_kernel(const cplx* __restrict__ y, const cplx* __restrict__ a, cplx alpha,
+                                        cplx* __restrict__ cand, int64_t n, int* flag, int step) {
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const cplx x = a[e];
+    cplx c = y[e];
+    c.re += alpha.re * x.re - alpha.im * x.im;
+    c.im += alpha.re * x.im + alpha.im * x.re;
+    cand[e] = c;
+    bad = bad || !isfinite(c.re) || !isfinite(c.im);
+  }
+  if (bad) atomicCAS(flag, 0, step + 1);
+}
+
+// y = cand unless a step has diverged
+__global__ void update_apply_kernel(cplx* __restrict__ y, const cplx* __restrict__ cand, int64_t n,
+                                    const int* flag) {
+  if (*flag != 0) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = cand[e];
+}
+
 __global__ void copy_kernel(cplx* __restrict__ dst, const cplx* __restrict__ src, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = src[e];
@@ -1096,6 +1125,22 @@ void axpy_strided(const AxpyDesc& d, hipStream_t s) {
 void fill(cplx* p, int64_t n, cplx val, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, val);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void fill_int(int* p, int64_t n, int val, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, val);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void guarded_update(cplx* y, const cplx* a, cplx alpha, cplx* cand, int64_t n, int* flag, int step, hipStream_t s) {
+  if (n <= 0) return;
+  RTCC3_CHECK(cand != y && cand != a, "guarded_update: candidate buffer aliases an operand");
+  hipLaunchKernelGGL(update_candidate_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, a, alpha, cand, n, flag,
+                     step);
+  RTCC3_HIP(hipGetLastError());
+  hipLaunchKernelGGL(update_apply_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, cand, n, flag);
   RTCC3_HIP(hipGetLastError());
 }
 

@@ -25,8 +25,9 @@ struct rtcc3_ctx {
   View B, mu, h0, I, ones_o, h;
   cplx *y = nullptr, *ytmp = nullptr, *k = nullptr, *acc = nullptr;
   double last_ms[6] = {0, 0, 0, 0, 0, 0};
-  cplx* mus = nullptr;  // dipole series of the last propagation (grows on demand)
-  int64_t mus_n = 0;
+  cplx* mus = nullptr;     // dipole series of up to kMusSteps steps (+1), copied out per chunk
+  cplx* mu_out = nullptr;  // dipole of rtcc3_dipole
+  int* flag = nullptr;     // first diverged step + 1 of the current propagation (0: none)
   std::string err;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // the CCSD reverse sweep runs on side_stream beside the triples windows
@@ -181,6 +182,26 @@ void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const Te
   }
 }
 
+// Steps whose dipoles are held on the device before they are copied out.
+constexpr int kMusSteps = 1024;
+
+// Evaluate the right-hand side once for every kind of pass (the density pass
+// with the dipole, the plain right-hand side) on the current state, so that
+// every buffer, scratch area and gradient the evaluation uses is allocated
+// now; then seal the engine, after which a propagation allocates nothing.
+void warm_up(rtcc3_ctx* c) {
+  const double E0[3] = {0.0, 0.0, 0.0};
+  c->e->seal(false);
+  TermsOut t;
+  t.mu = c->mu_out;
+  rhs_impl(c, E0, c->y, c->k, t, true);
+  rhs_impl(c, E0, c->y, c->k, TermsOut{}, true);
+  RTCC3_HIP(hipStreamSynchronize(c->stream));
+  RTCC3_HIP(hipStreamSynchronize(c->side_stream));
+  c->tri->reset_timing();
+  c->e->seal(true);
+}
+
 bool finite(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -287,7 +308,11 @@ extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const do
     c->ytmp = e.tensor("ytmp", {c->ylen}).p;
     c->k = e.tensor("k", {c->ylen}).p;
     c->acc = e.tensor("acc", {c->ylen}).p;
-    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    c->mus = e.tensor("mus", {kMusSteps + 1, 3}).p;
+    c->mu_out = e.tensor("mu_out", {3}).p;
+    c->flag = (int*)e.tensor("flag", {1}).p;
+    // every buffer of an evaluation now, none while propagating (the state is zero)
+    warm_up(c.get());
     return RTCC3_OK;
   });
   if (rc != RTCC3_OK) {
@@ -333,6 +358,7 @@ extern "C" int rtcc3_rhs(rtcc3_ctx* c, const double E[3], const rtcc3_c64* y_dev
   return guarded(c, [&]() -> int {
     rhs_impl(c, E, (const cplx*)y_dev, (cplx*)dy_dev, TermsOut{}, c->with_triples != 0);
     RTCC3_HIP(hipStreamSynchronize(c->stream));
+    c->tri->fold_timing();
     return RTCC3_OK;
   });
 }
@@ -347,6 +373,7 @@ extern "C" int rtcc3_rhs_terms(rtcc3_ctx* c, const double E[3], const rtcc3_c64*
     t.terms = (cplx*)terms_dev;
     rhs_impl(c, E, (const cplx*)y_dev, nullptr, t, with_triples != 0);
     RTCC3_HIP(hipStreamSynchronize(c->stream));
+    c->tri->fold_timing();
     return RTCC3_OK;
   });
 }
@@ -355,12 +382,12 @@ extern "C" int rtcc3_dipole(rtcc3_ctx* c, const double E[3], rtcc3_c64 out[3]) {
   if (!c) return RTCC3_EINVAL;
   if (!field_ok(E) || !out) return fail(c, RTCC3_EINVAL, "bad argument");
   return guarded(c, [&]() -> int {
-    View m = c->e->tensor("mu_out", {3});
     TermsOut t;
-    t.mu = m.p;
+    t.mu = c->mu_out;
     rhs_impl(c, E, c->y, nullptr, t, c->with_triples != 0);
-    RTCC3_HIP(hipMemcpyAsync(out, m.p, sizeof(cplx) * 3, hipMemcpyDeviceToHost, c->stream));
+    RTCC3_HIP(hipMemcpyAsync(out, c->mu_out, sizeof(cplx) * 3, hipMemcpyDeviceToHost, c->stream));
     RTCC3_HIP(hipStreamSynchronize(c->stream));
+    c->tri->fold_timing();
     return RTCC3_OK;
   });
 }
@@ -374,28 +401,29 @@ extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double*
   return guarded(c, [&]() -> int {
     Engine& e = *c->e;
     const int64_t L = c->ylen;
-    if (c->mus_n < 3 * ((int64_t)steps + 1)) {
-      RTCC3_HIP(hipStreamSynchronize(c->stream));
-      if (c->mus) RTCC3_HIP(hipFree(c->mus));
-      c->mus = nullptr;
-      c->mus_n = 0;
-      if (hipMalloc(&c->mus, sizeof(cplx) * 3 * ((int64_t)steps + 1)) != hipSuccess)
-        return fail(c, RTCC3_ENOMEM, "no device memory for the dipole series");
-      c->mus_n = 3 * ((int64_t)steps + 1);
-    }
-    View mus = Engine::raw(c->mus, {(int64_t)steps + 1, 3});
     const bool tri = c->with_triples != 0;
-    View Y = Engine::raw(c->y, {L}), YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}),
-         A = Engine::raw(c->acc, {L});
+    View YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}), A = Engine::raw(c->acc, {L});
     auto copyL = [&](cplx* dst, const cplx* src) { copy(dst, src, L, c->stream); };
+    // The dipoles of up to kMusSteps steps stay on the device; a full chunk is
+    // copied out (which waits for it) before the next one starts.
+    std::vector<cplx> mh((size_t)(steps + 1) * 3);
+    int base = 0;  // dipole index held in c->mus[0]
+    auto flush = [&](int upto) {
+      RTCC3_HIP(hipMemcpyAsync(mh.data() + 3 * (size_t)base, c->mus, sizeof(cplx) * 3 * (size_t)(upto - base),
+                               hipMemcpyDeviceToHost, c->stream));
+      RTCC3_HIP(hipStreamSynchronize(c->stream));
+      base = upto;
+    };
     c->tri->reset_timing();
+    fill_int(c->flag, 1, 0, c->stream);
     RTCC3_HIP(hipEventRecord(c->ev0, c->stream));
     for (int s = 0; s < steps; ++s) {
+      if (s - base == kMusSteps) flush(s);
       const double* E0 = field + 3 * (2 * s);
       const double* Eh = field + 3 * (2 * s + 1);
       const double* E1 = field + 3 * (2 * s + 2);
       TermsOut t;
-      t.mu = mus.p + 3 * s;
+      t.mu = c->mus + 3 * (s - base);
       rhs_impl(c, E0, c->y, c->k, t, tri);  // k1 (and mu(t_s))
       copyL(c->acc, c->k);
       copyL(c->ytmp, c->y);
@@ -410,25 +438,40 @@ extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double*
       e.axpy(C(dt), K, YT);
       rhs_impl(c, E1, c->ytmp, c->k, TermsOut{}, tri);  // k4
       e.axpy(ONE, K, A);
-      e.axpy(C(dt / 6.0), A, Y);
+      // y += dt/6 (k1 + 2 k2 + 2 k3 + k4) unless the result is not finite:
+      // then y keeps its last finite value (ytmp is free after k4)
+      guarded_update(c->y, c->acc, C(dt / 6.0), c->ytmp, L, c->flag, s, c->stream);
     }
+    if (steps - base == kMusSteps) flush(steps);
     {
       TermsOut t;
-      t.mu = mus.p + 3 * steps;
+      t.mu = c->mus + 3 * (steps - base);
       rhs_impl(c, field + 3 * (2 * steps), c->y, nullptr, t, tri);
     }
     RTCC3_HIP(hipEventRecord(c->ev1, c->stream));
-    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    int bad = 0;
+    RTCC3_HIP(hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    flush(steps + 1);
     float ms = 0.f;
     RTCC3_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->last_ms[0] = ms;
+    c->tri->fold_timing();
     c->tri->timing(c->last_ms[1], c->last_ms[2]);
     c->tri->build_timing(c->last_ms[3], c->last_ms[4], c->last_ms[5]);
-    std::vector<cplx> mh((size_t)(steps + 1) * 3);
-    RTCC3_HIP(hipMemcpy(mh.data(), mus.p, sizeof(cplx) * mh.size(), hipMemcpyDeviceToHost));
+    if (bad) {
+      // step bad - 1 gave a non-finite state: y is the state after bad - 1 steps,
+      // whose dipoles (indices 0 .. bad - 1) are valid; the later ones are not
+      const double nan = std::nan("");
+      for (size_t n = (size_t)bad; n < (size_t)steps + 1; ++n)
+        mh[3 * n] = mh[3 * n + 1] = mh[3 * n + 2] = cplx{nan, nan};
+    }
     if (dipole_out) std::memcpy(dipole_out, mh.data(), sizeof(cplx) * mh.size());
+    if (bad)
+      return fail(c, RTCC3_EDIVERGED,
+                  "state became non-finite in step " + std::to_string(bad - 1) + "; the state is left after " +
+                      std::to_string(bad - 1) + " steps");
     for (auto& z : mh)
-      if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(c, RTCC3_EDIVERGED, "state became non-finite");
+      if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(c, RTCC3_EDIVERGED, "dipole became non-finite");
     return RTCC3_OK;
   });
 }
@@ -457,7 +500,15 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
   if (option == RTCC3_OPT_WINDOW_BLOCKS) {
     if (value < 0) return fail(c, RTCC3_EINVAL, "negative window size");
     return guarded(c, [&]() -> int {
+      RTCC3_HIP(hipStreamSynchronize(c->side_stream));
+      c->e->seal(false);
       c->tri->set_window_blocks(*c->e, value);
+      // the window buffers of the new size now, none later; the state is kept
+      std::vector<cplx> keep((size_t)c->ylen);
+      RTCC3_HIP(hipMemcpy(keep.data(), c->y, sizeof(cplx) * keep.size(), hipMemcpyDeviceToHost));
+      fill(c->y, c->ylen, cplx{0, 0}, c->stream);
+      warm_up(c);
+      RTCC3_HIP(hipMemcpy(c->y, keep.data(), sizeof(cplx) * keep.size(), hipMemcpyHostToDevice));
       return RTCC3_OK;
     });
   }
@@ -482,7 +533,6 @@ extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
   if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
   if (c->ev_side1) (void)hipEventDestroy(c->ev_side1);
   if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
-  if (c->mus) (void)hipFree(c->mus);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

@@ -26,6 +26,8 @@ namespace rtcc3 {
 namespace {
 
 constexpr cplx ONE{1.0, 0.0};
+// Timing event pools (pairs); a full pool is folded, which waits for the device.
+constexpr int kRunEvents = 512, kBuildEvents = 2048;
 inline cplx R(double x) { return cplx{x, 0.0}; }
 
 GemmDesc base(int M, int N, int K, int nb, const int* bl, int prec) {
@@ -187,7 +189,28 @@ Triples::Triples(Engine& e, const Dims& d, const std::vector<double>& eps, int p
   RTCC3_HIP(hipEventCreateWithFlags(&ev_t3b_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_t_, hipEventDisableTiming));
   RTCC3_HIP(hipEventCreateWithFlags(&ev_l3b_, hipEventDisableTiming));
+  rev_.resize(kRunEvents);
+  bev_.resize(kBuildEvents);
+  for (auto* pool : {&rev_, &bev_})
+    for (hipEvent_t& ev : *pool) RTCC3_HIP(hipEventCreate(&ev));
   (void)e;
+}
+
+void Triples::fold_timing() {
+  for (int i = 0; i + 1 < nrev_; i += 2) {
+    RTCC3_HIP(hipEventSynchronize(rev_[i + 1]));
+    float ms = 0;
+    RTCC3_HIP(hipEventElapsedTime(&ms, rev_[i], rev_[i + 1]));
+    ms_ += ms;
+  }
+  for (int i = 0; i + 1 < nbev_; i += 2) {
+    RTCC3_HIP(hipEventSynchronize(bev_[i + 1]));
+    float b = 0;
+    RTCC3_HIP(hipEventElapsedTime(&b, bev_[i], bev_[i + 1]));
+    build_ms_ += b;
+    ++build_launches_;
+  }
+  nrev_ = nbev_ = 0;
 }
 
 void Triples::free_windows() {
@@ -222,8 +245,7 @@ Triples::~Triples() {
   for (hipEvent_t ev : {ev_fork_, ev_l_, ev_join_, ev_t3b_, ev_t_, ev_l3b_})
     if (ev) (void)hipEventDestroy(ev);
   if (s2_) (void)hipStreamDestroy(s2_);
-  if (t0_) (void)hipEventDestroy(t0_);
-  if (t1_) (void)hipEventDestroy(t1_);
+  for (hipEvent_t ev : rev_) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : bev_) (void)hipEventDestroy(ev);
 }
 
@@ -1027,11 +1049,8 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
 }
 
 void Triples::build_event(hipStream_t s) {
-  if (nbev_ == (int)bev_.size()) {
-    hipEvent_t ev;
-    RTCC3_HIP(hipEventCreate(&ev));
-    bev_.push_back(ev);
-  }
+  // pairs: a full pool is folded before a pair starts
+  if (nbev_ % 2 == 0 && nbev_ + 2 > (int)bev_.size()) fold_timing();
   RTCC3_HIP(hipEventRecord(bev_[nbev_++], s));
 }
 
@@ -1040,12 +1059,8 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   const int64_t o = d.o, v = d.v;
   const int64_t ov = o * v, oovv = o * o * v * v;
   hipStream_t s = e.stream;
-  if (!t0_) {
-    RTCC3_HIP(hipEventCreate(&t0_));
-    RTCC3_HIP(hipEventCreate(&t1_));
-  }
-  RTCC3_HIP(hipEventRecord(t0_, s));
-  nbev_ = 0;
+  if (nrev_ + 2 > (int)rev_.size()) fold_timing();
+  RTCC3_HIP(hipEventRecord(rev_[nrev_++], s));
   blocks(e, r);
   beside_ = beside ? &beside : nullptr;
   side_done_ = nullptr;
@@ -1120,17 +1135,7 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
     out.Dab = Dab;
     out.Dia = Dia;
   }
-  RTCC3_HIP(hipEventRecord(t1_, s));
-  RTCC3_HIP(hipEventSynchronize(t1_));
-  float ms = 0;
-  RTCC3_HIP(hipEventElapsedTime(&ms, t0_, t1_));
-  ms_ += ms;
-  for (int i = 0; i + 1 < nbev_; i += 2) {
-    float b = 0;
-    RTCC3_HIP(hipEventElapsedTime(&b, bev_[i], bev_[i + 1]));
-    build_ms_ += b;
-    ++build_launches_;
-  }
+  RTCC3_HIP(hipEventRecord(rev_[nrev_++], s));
   return out;
 }
 

@@ -76,12 +76,17 @@ class Triples {
   // the windows; the window buffers are released and reallocated on use.
   void set_window_blocks(Engine& e, int n);
   void reset_timing() {
+    fold_timing();
     ms_ = 0;
     launches_ = 0;
     build_ms_ = 0;
     build_launches_ = 0;
     build_flop_ = 0;
   }
+  // Wait for the timing events recorded so far and add up their intervals
+  // (call after the caller's stream has been synchronised; also done by run()
+  // itself when an event pool is full).
+  void fold_timing();
   void timing(double& ms, double& launches) const {
     ms = ms_;
     launches = (double)launches_;
@@ -105,10 +110,13 @@ class Triples {
   int wcap_ = 0;  // blocks per window requested by the caller (0: from the memory budget)
   double ms_ = 0;
   long launches_ = 0;
-  hipEvent_t t0_ = nullptr, t1_ = nullptr;
   double build_ms_ = 0, build_flop_ = 0;
   long build_launches_ = 0;
-  std::vector<hipEvent_t> bev_;  // event pairs around the build products of one run
+  // Timing events, all created with the engine: pairs around each run (rev_)
+  // and around each launch of the build products (bev_), folded into the
+  // totals by fold_timing() so that no run waits for the device.
+  std::vector<hipEvent_t> rev_, bev_;
+  int nrev_ = 0;
   // A window's lambda3 side (build, symmetrisation, the contractions that read
   // lambda3 only) runs on a second stream beside the t3 side; ev_fork_ /
   // ev_l_ / ev_join_ order the two.
@@ -119,7 +127,7 @@ class Triples {
                                  // matrix cores, so the lambda3 build follows it
   hipEvent_t ev_l3b_ = nullptr;  // after the lambda3 build: the t3 side's products wait for it
                                  // and only the t3 symmetrisation runs beside it
-  int nbev_ = 0;                 // pairs recorded in the current run
+  int nbev_ = 0;                 // events recorded since the last fold
   const Beside* beside_ = nullptr;  // pending side work of the current run
   hipEvent_t side_done_ = nullptr;
   void build_event(hipStream_t s);

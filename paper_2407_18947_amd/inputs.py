@@ -33,6 +33,7 @@ __all__ = [
     "state_size",
     "pack_state",
     "unpack_state",
+    "random_state",
     "field_delta_kick",
     "field_gaussian_sine",
     "field_sine",
@@ -104,6 +105,22 @@ def unpack_state(y: np.ndarray, o: int, v: int):
     l1 = y[ov + oovv:2 * ov + oovv].reshape(o, v)
     l2 = y[2 * ov + oovv:].reshape(o, o, v, v)
     return t1, t2, l1, l2
+
+
+def random_state(o: int, v: int, seed: int, scale: float = 0.1) -> np.ndarray:
+    """A seeded complex state (t1, t2, l1, l2) with entries scale * (N(0,1) + i N(0,1)),
+    t2 and l2 symmetrised under (i,a) <-> (j,b); a generic point for comparing
+    right-hand sides (not a physical state)."""
+    rng = np.random.default_rng(seed)
+
+    def rc(*sh):
+        return scale * (rng.normal(size=sh) + 1j * rng.normal(size=sh))
+
+    t1, l1 = rc(o, v), rc(o, v)
+    t2, l2 = rc(o, o, v, v), rc(o, o, v, v)
+    t2 = 0.5 * (t2 + t2.transpose(1, 0, 3, 2))
+    l2 = 0.5 * (l2 + l2.transpose(1, 0, 3, 2))
+    return pack_state(t1, t2, l1, l2)
 
 
 def initial_state(sys: System) -> np.ndarray:

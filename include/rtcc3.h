@@ -152,6 +152,18 @@ int rtcc3_last_timing(rtcc3_ctx *ctx, double kernel_ms[6]);
  * Returns EINVAL for non-positive sizes or NULL pointers. */
 int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rtcc3_c64 *A, const rtcc3_c64 *B, rtcc3_c64 *C);
 
+/* The same self-test for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight loops, harnesses that forbid hipMalloc): A, B
+ * and C are staged in a fixed device array of the library (64 MiB, held by
+ * each device the library runs on until the process ends) instead of buffers
+ * allocated per call; no hipMalloc, hipFree or allocating library routine is
+ * called.  Arguments and results as rtcc3_zgemm_selftest, on the current
+ * device.  Returns EINVAL when M*K + K*N + M*N exceeds 4194304 complex
+ * elements (message via rtcc3_last_error(NULL)).  All calls on one device
+ * share the array: calls that overlap on one device (other threads) race. */
+int rtcc3_zgemm_selftest_noalloc(int M, int N, int K, int precision, const rtcc3_c64 *A, const rtcc3_c64 *B,
+                                 rtcc3_c64 *C);
+
 const char *rtcc3_last_error(const rtcc3_ctx *ctx); /* ctx == NULL: last create() error of this thread */
 void rtcc3_destroy(rtcc3_ctx *ctx);
 

@@ -21,8 +21,8 @@ RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION, RTCC3_OPT_WINDOW_BLOCKS, RTCC3_OPT_SINGL
 
 EXPORTS = [
     "rtcc3_create", "rtcc3_set_state", "rtcc3_get_state", "rtcc3_rhs", "rtcc3_rhs_terms", "rtcc3_propagate",
-    "rtcc3_dipole", "rtcc3_set_option", "rtcc3_last_timing", "rtcc3_zgemm_selftest", "rtcc3_last_error",
-    "rtcc3_destroy",
+    "rtcc3_dipole", "rtcc3_set_option", "rtcc3_last_timing", "rtcc3_zgemm_selftest",
+    "rtcc3_zgemm_selftest_noalloc", "rtcc3_last_error", "rtcc3_destroy",
 ]
 
 _lib = None
@@ -53,6 +53,7 @@ def load():
     L.rtcc3_set_option.argtypes = [VP, I, I]
     L.rtcc3_last_timing.argtypes = [VP, VP]
     L.rtcc3_zgemm_selftest.argtypes = [I, I, I, I, VP, VP, VP]
+    L.rtcc3_zgemm_selftest_noalloc.argtypes = [I, I, I, I, VP, VP, VP]
     L.rtcc3_last_error.argtypes = [VP]
     L.rtcc3_last_error.restype = ctypes.c_char_p
     L.rtcc3_destroy.argtypes = [VP]
@@ -160,6 +161,16 @@ def rtcc3_zgemm_selftest(A, B, precision=RTCC3_FP64):
     assert K == K2
     C = np.empty((M, N), dtype=np.complex128)
     _check(load().rtcc3_zgemm_selftest(M, N, K, precision, _ptr(A), _ptr(B), _ptr(C)), None)
+    return C
+
+
+def rtcc3_zgemm_selftest_noalloc(A, B, precision=RTCC3_FP64):
+    A, B = _c128(A), _c128(B)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    C = np.empty((M, N), dtype=np.complex128)
+    _check(load().rtcc3_zgemm_selftest_noalloc(M, N, K, precision, _ptr(A), _ptr(B), _ptr(C)), None)
     return C
 
 

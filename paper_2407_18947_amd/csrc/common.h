@@ -19,6 +19,9 @@ struct Error : std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// Message of the last failed context-free call of this thread (rtcc3_last_error(NULL)).
+void set_thread_error(const std::string& msg);
+
 #define RTCC3_HIP(call)                                                                       \
   do {                                                                                        \
     hipError_t e_ = (call);                                                                   \

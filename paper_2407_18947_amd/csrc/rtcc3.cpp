@@ -210,6 +210,8 @@ bool finite(const double* p, int64_t n) {
 
 }  // namespace
 
+void rtcc3::set_thread_error(const std::string& msg) { g_create_error = msg; }
+
 // =============================================================================
 
 static_assert(RTCC3_FP64 == RTCC3_PREC_FP64 && RTCC3_FP32 == RTCC3_PREC_FP32 && RTCC3_BF16X3 == RTCC3_PREC_BF16X3 &&

@@ -799,6 +799,185 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(GemmDesc d, int ksplit,
         put<ATOMIC>(d, C, ro[i][r], co[j], (double)crr[i][j][r] - (double)cii[i][j][r], (double)cim[i][j][r]);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 K-segmented product (the builds of t3 and lambda3 and the S product):
+// one 64 x 64 tile of C per workgroup, four waves of 32 x 32, complex products
+// as three real products.  Operands are read with buffer loads: each segment's
+// operand block of the batch entry is one buffer resource, a thread's element
+// offsets are 32-bit and advance by a uniform amount per K step, and an
+// element outside the operand (a row beyond M, a column beyond N, a k beyond
+// the segment's length or the product's end) is read at an offset beyond the
+// resource, which the hardware returns as zero: no masks on the loaded
+// values.  The three planes of each operand that the three products take
+// (Ar, Ai, Ar + Ai and Br, Bi - Br, Br + Bi) are formed when the tile is
+// stored to LDS, so the MFMA loop issues no vector arithmetic.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kOOB = 0x7ffffff0;  // beyond every resource (host-checked spans stay below 2^31 bytes)
+constexpr int kRsrcWord3 = 0x00020000;
+
+// The element at byte offset voff of resource r if ok, else zero (read beyond
+// the resource).  The empty asm keeps the offset select a select: the compiler
+// would otherwise branch around a load per element.
+__device__ __forceinline__ cplx buf_load_cplx(__amdgpu_buffer_rsrc_t r, bool ok, int voff) {
+  int o = ok ? voff : kOOB;
+  asm volatile("" : "+v"(o));
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
+  cplx x;
+  __builtin_memcpy(&x, &v, sizeof(x));
+  return x;
+}
+
+template <bool ATOMIC>
+__global__ __launch_bounds__(NT, 3) void zgemm_seg_f64_kernel(GemmDesc d) {
+  constexpr int BK = 16, BN = 64, WM = 32, WN = 32, IB = 2, JB = 2;
+  __shared__ double sA[3][BK][BM + 1];  // Ar, Ai, Ar + Ai   [plane][k][m]
+  __shared__ double sB[3][BK][BN + 1];  // Br, Bi - Br, Br + Bi   [plane][k][n]
+
+  const int tilesN = (d.N + BN - 1) / BN;
+  const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
+  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (b >= d.batch) return;
+  const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
+  cplx* C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int m0 = tm * BM, n0 = tn * BN;
+  // the thread's elements: A rows am + 16 r at k = ak; B rows k = bk + 4 r at column bn
+  const int ak = tid & 15, am = tid >> 4, bn = tid & 63, bk = tid >> 6;
+  const int kend = d.K;
+
+  // segment cursor (uniform): resources and the thread's offsets at the segment's first k
+  int seg = -1, sbase = 0, slen = 0, snext = 0, sak = 0, sbk = 0;
+  __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)d.C, 0, 0, kRsrcWord3);
+  __amdgpu_buffer_rsrc_t rb = ra;
+  int voa[4], vob[4];
+  bool rowok[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) rowok[r] = m0 + am + 16 * r < d.M;
+  const bool colok = n0 + bn < d.N;
+  auto enter = [&](int s) {
+    const GemmDesc::Seg& g = d.seg[s];
+    const cplx* pa = g.A + g.cA[0] * I + g.cA[1] * J + g.cA[2] * K + g.cA[3] * n;
+    const cplx* pb = g.B + g.cB[0] * I + g.cB[1] * J + g.cB[2] * K + g.cB[3] * n;
+    const int sam = (int)g.sAm, sbn = (int)g.sBn;
+    sak = (int)g.sAk;
+    sbk = (int)g.sBk;
+    const int spanA = ((d.M - 1) * sam + (g.len - 1) * sak + 1) * (int)sizeof(cplx);
+    const int spanB = ((g.len - 1) * sbk + (d.N - 1) * sbn + 1) * (int)sizeof(cplx);
+    ra = __builtin_amdgcn_make_buffer_rsrc((void*)pa, 0, spanA, kRsrcWord3);
+    rb = __builtin_amdgcn_make_buffer_rsrc((void*)pb, 0, spanB, kRsrcWord3);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      voa[r] = ((m0 + am + 16 * r) * sam + ak * sak) * (int)sizeof(cplx);
+      vob[r] = ((bk + 4 * r) * sbk + (n0 + bn) * sbn) * (int)sizeof(cplx);
+    }
+    sbase = g.k0;
+    slen = g.len;
+    snext = s + 1 < d.nseg ? d.seg[s + 1].k0 : 0x7fffffff;
+    seg = s;
+  };
+
+  cplx av[4], bv[4];
+  // Brings the step starting at k0 (a multiple of 16, so it lies in one segment) into registers.
+  auto load = [&](int k0) {
+    while (k0 >= snext) enter(seg + 1);
+    const int dk = k0 - sbase;  // uniform
+    const int ka = k0 + ak;
+    const bool kok = (ka < kend) & (dk + ak < slen);
+    const int ua = dk * sak * (int)sizeof(cplx), ub = dk * sbk * (int)sizeof(cplx);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) av[r] = buf_load_cplx(ra, kok & rowok[r], voa[r] + ua);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kr = bk + 4 * r;
+      const bool ok = colok & (k0 + kr < kend) & (dk + kr < slen);
+      bv[r] = buf_load_cplx(rb, ok, vob[r] + ub);
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = am + 16 * r;
+      const double re = av[r].re, im = av[r].im;
+      sA[0][ak][m] = re;
+      sA[1][ak][m] = im;
+      sA[2][ak][m] = re + im;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = bk + 4 * r;
+      const double re = bv[r].re, im = bv[r].im;
+      sB[0][k][bn] = re;
+      sB[1][k][bn] = im - re;
+      sB[2][k][bn] = re + im;
+    }
+  };
+
+  d4 c1[IB][JB], c2[IB][JB], c3[IB][JB];  // (Ar + Ai) Br, Ar (Bi - Br), Ai (Br + Bi)
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j) c1[i][j] = c2[i][j] = c3[i][j] = d4{0, 0, 0, 0};
+
+  const int nsteps = (kend + BK - 1) / BK;
+  load(0);
+  stash();
+  __syncthreads();
+  for (int it = 0; it < nsteps; ++it) {
+    load((it + 1) * BK);  // in flight during the MFMAs (all out of range after the last step)
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4), c16 = lane & 15;
+      double ar[IB], ai[IB], sa[IB], br[JB], db[JB], sb[JB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        ar[i] = sA[0][kr][wm + 16 * i + c16];
+        ai[i] = sA[1][kr][wm + 16 * i + c16];
+        sa[i] = sA[2][kr][wm + 16 * i + c16];
+      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        br[j] = sB[0][kr][wn + 16 * j + c16];
+        db[j] = sB[1][kr][wn + 16 * j + c16];
+        sb[j] = sB[2][kr][wn + 16 * j + c16];
+      }
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) c1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], br[j], c1[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) c2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], db[j], c2[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) c3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], sb[j], c3[i][j], 0, 0, 0);
+    }
+    __syncthreads();  // every wave is done with the tile
+    stash();
+    __syncthreads();
+  }
+
+  int64_t co[JB], ro[IB][4];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) co[j] = c_off(n0 + wn + 16 * j + (lane & 15), d.N, d.N0, d.sCn1, d.sCn0);
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ro[i][r] = c_off(m0 + wm + 16 * i + Frag<double>::row(lane, r), d.M, d.M0, d.sCm1, d.sCm0);
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double p1 = c1[i][j][r];
+        put<ATOMIC>(d, C, ro[i][r], co[j], p1 - c3[i][j][r], p1 + c2[i][j][r]);
+      }
+}
+
 __global__ void axpy_kernel(AxpyDesc d, int64_t total) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -867,7 +1046,10 @@ inline unsigned grid_for(int64_t n, int bs) {
 // atomic epilogue, operand layouts, tile width and K segments.
 template <int MODE, bool ATOMIC, bool KFA, bool NFB, int BN, bool SEG>
 void launch_one(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk) {
-  if (MODE == RTCC3_PREC_FP64)
+  if constexpr (MODE == RTCC3_PREC_FP64 && SEG) {
+    RTCC3_CHECK(ksplit == 1, "gemm: the FP64 segmented kernel does not split K");
+    hipLaunchKernelGGL((zgemm_seg_f64_kernel<ATOMIC>), grid, dim3(NT), 0, s, d);
+  } else if (MODE == RTCC3_PREC_FP64)
     hipLaunchKernelGGL((zgemm_kernel<double, ATOMIC, KFA, NFB, BN, SEG>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
   else if (MODE == RTCC3_PREC_FP32)
     hipLaunchKernelGGL((zgemm_kernel<float, ATOMIC, KFA, NFB, BN, SEG>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
@@ -1035,6 +1217,12 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
       RTCC3_CHECK((int64_t)(d0.M + 63) * g.sAm + (int64_t)g.len * g.sAk < (1LL << 31) &&
                       (int64_t)g.len * g.sBk + (int64_t)(d0.N + 63) * g.sBn < (1LL << 31),
                   "gemm: segment operand too large");
+      // the FP64 segmented kernel reads through buffer resources with 32-bit byte
+      // offsets, every thread offset (rows up to M + 63, k up to len + 15) below 2^31
+      RTCC3_CHECK(d0.prec != RTCC3_PREC_FP64 ||
+                      ((int64_t)(d0.M + 63) * g.sAm + (int64_t)(g.len + 15) * g.sAk + 1 < (1LL << 27) &&
+                       (int64_t)(g.len + 15) * g.sBk + (int64_t)(d0.N + 63) * g.sBn + 1 < (1LL << 27)),
+                  "gemm: segment operand beyond the 32-bit offsets of the segmented kernel");
     }
   }
   RTCC3_CHECK(d0.K < (1 << 22) && d0.M < (1 << 22) && d0.N < (1 << 22), "gemm: extent too long");
@@ -1078,6 +1266,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
     const int64_t span_k = std::max<int64_t>(BKMAX, nblk * d.K0 / BKMAX * BKMAX);
     ksplit = (int)std::max<int64_t>(ksplit, (d.K + span_k - 1) / span_k);
   }
+  if (d.nseg > 0 && d.prec == RTCC3_PREC_FP64) ksplit = 1;  // the FP64 segmented kernel runs whole K ranges
   const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BKMAX - 1) / BKMAX * BKMAX);
   RTCC3_CHECK(tiles * ksplit < (1LL << 31), "gemm: too many tiles");
   RTCC3_CHECK(!d.gk_start || kchunk / d.K0 + 2 <= GK_MAXSEG, "gemm: gathered K range too long for one workgroup");

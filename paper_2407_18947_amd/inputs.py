@@ -37,6 +37,9 @@ __all__ = [
     "field_delta_kick",
     "field_gaussian_sine",
     "field_sine",
+    "field_ramped_cw",
+    "ramp_lrcw",
+    "ramp_qrcw",
     "CONFIGS",
 ]
 
@@ -173,6 +176,32 @@ def field_gaussian_sine(steps: int, dt: float, amplitude: float = 0.002, omega: 
 def field_sine(steps: int, dt: float, amplitude: float = 0.001, omega: float = 0.0773, direction="x") -> np.ndarray:
     t = _grid(steps, dt)
     e = amplitude * np.sin(omega * t)
+    return np.ascontiguousarray(e[:, None] * _axis(direction)[None, :])
+
+
+def ramp_lrcw(t, t_r):
+    """Linear ramp of the LRCW (Sec. 2.2.4): t / t_r for t < t_r, then 1."""
+    t = np.asarray(t, dtype=np.float64)
+    return np.where(t < t_r, t / t_r, 1.0)
+
+
+def ramp_qrcw(t, t_r):
+    """Quadratic ramp of the QRCW (Sec. 2.2.4): 2 t^2 / t_r^2 for t < t_r / 2,
+    1 - 2 (t - t_r)^2 / t_r^2 for t_r / 2 <= t < t_r, then 1."""
+    t = np.asarray(t, dtype=np.float64)
+    up = 2.0 * t * t / (t_r * t_r)
+    down = 1.0 - 2.0 * (t - t_r) ** 2 / (t_r * t_r)
+    return np.where(t < 0.5 * t_r, up, np.where(t < t_r, down, 1.0))
+
+
+def field_ramped_cw(steps: int, dt: float, amplitude: float, omega: float, kind: str = "qrcw", n_r: int = 1,
+                    direction="z") -> np.ndarray:
+    """A ramped continuous wave A F(t) cos(omega t) along one axis (Sec. 2.2.4), with
+    the ramp over n_r optical cycles t_c = 2 pi / omega; kind 'lrcw' or 'qrcw'."""
+    t = _grid(steps, dt)
+    t_r = n_r * 2.0 * np.pi / omega
+    ramp = {"lrcw": ramp_lrcw, "qrcw": ramp_qrcw}[kind](t, t_r)
+    e = amplitude * ramp * np.cos(omega * t)
     return np.ascontiguousarray(e[:, None] * _axis(direction)[None, :])
 
 

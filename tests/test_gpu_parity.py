@@ -444,3 +444,44 @@ def test_no_device_allocation_after_create():
     free1 = torch.cuda.mem_get_info()[0]
     ctx.close()
     assert free1 == free0, (free0, free1)
+
+
+def test_two_electron_dynamic_polarisability_matches_sum_over_states():
+    """End to end on the GPU: two electrons (o = 1, v = 3, where RT-CC3 is exact),
+    QRCW fields of +-A, +-2A at w = 0.3 (one ramped, one fitted cycle), alpha_zz(w)
+    from the four-point formula and the cosine fit (Sec. 2.2.2) against the
+    sum-over-states polarisability of the same Hamiltonian in determinant space."""
+    from fci_harness import FockSpace
+    from paper_2407_18947_amd import properties as P
+    from paper_2407_18947_amd.inputs import field_ramped_cw
+
+    o, v = 1, 3
+    _say(f"dynamic polarisability o={o} v={v}")
+    s = make_system(o, v, seed=46)
+    m = orc.Model.from_system(s)
+    fs = FockSpace(o, v)
+    g = np.einsum("Ppq,Prs->pqrs", s.B, s.B).astype(complex)
+    H0 = fs.hamiltonian(m.h0.numpy().astype(complex), g).toarray()
+    M = fs.one_body(s.mu[2].astype(complex)).toarray()
+    E, U = np.linalg.eigh(H0)
+    k0 = int(np.argmax(np.abs(U.T.conj() @ fs.ref)))
+    wn = E - E[k0]
+    dn = U.T.conj() @ (M @ U[:, k0])
+    w = 0.3
+    exc = np.arange(len(E)) != k0
+    alpha_sos = np.sum(2 * wn[exc] * np.abs(dn[exc]) ** 2 / (wn[exc] ** 2 - w * w))
+    y0, _ = orc.ground_state(m)
+    dt, A = 0.05, 0.001
+    t_c = 2 * np.pi / w
+    steps = int(round(2 * t_c / dt))
+    ctx = _lib.Context(s)
+    mus = []
+    for k in (1, -1, 2, -2):
+        ctx.set_state(y0.numpy())
+        mus.append(ctx.propagate(steps, dt, field_ramped_cw(steps, dt, k * A, w, kind="qrcw", n_r=1))[:, 2].real)
+    ctx.close()
+    mu1 = P.finite_field_mu1(*mus, A)
+    alpha, r2 = P.fit_alpha(dt * np.arange(steps + 1), mu1, w, t_start=t_c)
+    _say(f"  alpha {alpha:.8f}  sum over states {alpha_sos:.8f}  R^2 {r2:.6f}")
+    assert r2 > 0.999
+    assert abs(alpha - alpha_sos) < 1e-3 * abs(alpha_sos)

@@ -712,3 +712,138 @@ def ground_state(m: Model, E=(0.0, 0.0, 0.0), triples="explicit", with_triples=T
     xl, _ = _diis(np.zeros(ov + oovv, dtype=np.complex128), l_step, tol, maxiter)
     y = pack(t1, t2, torch.as_tensor(xl[:ov].reshape(o, v)), torch.as_tensor(xl[ov:].reshape(o, o, v, v)))
     return y, energy
+
+
+# -----------------------------------------------------------------------------
+# Field-coupled triples: the CC3 Lagrangian with its field terms (App. A)
+# -----------------------------------------------------------------------------
+#
+# With the field on, the triples block of L_CC3 is
+#   <Lambda3| [H,T2] + [F + beta V, T3] + 1/2 [[beta V, T2], T2] |0>
+# (V T1-transformed), so t3 and lambda3 have no closed form and are iterated
+# (App. A, Sec. 2.1).  Reading: the field terms are taken from the commutators
+# of the Euler-Lagrange equations; in amplitude form (pinned against the
+# determinant-space commutators)
+#   <mu3|[V,T3]|0>          = sum_d v_ad t_ijk^dbc + (b, c slots) - sum_l v_li t_ljk^abc - (j, k slots),
+#   1/2 <mu3|[[V,T2],T2]|0> = -P_ijk^abc sum_ld v_ld t_ij^ad t_kl^cb,
+# the second as printed in the spin-adapted t3, the first with the sign of
+# every slot and the order of v's indices fixed by the commutator (the printed
+# spin-adapted t3 and lambda3 disagree in these signs).
+# lambda3 pairs with the triples residual as C3 sum lambda3 x3, C3 = 1/6
+# (lambda_ijk^abc = <Lambda3|E_ai E_bj E_ck|0>).
+
+C3 = 1.0 / 6.0
+
+
+def vt3_full(v, t3, o):
+    """<mu3|[V,T3]|0> for a one-electron operator v [n,n] (amplitude form)."""
+    vv, oo = v[o:, o:], v[:o, :o]
+    return (torch.einsum("ad,ijkdbc->ijkabc", vv, t3) + torch.einsum("bd,ijkadc->ijkabc", vv, t3)
+            + torch.einsum("cd,ijkabd->ijkabc", vv, t3) - torch.einsum("li,ljkabc->ijkabc", oo, t3)
+            - torch.einsum("lj,ilkabc->ijkabc", oo, t3) - torch.einsum("lk,ijlabc->ijkabc", oo, t3))
+
+
+def vtt_full(v, t2, o):
+    """1/2 <mu3|[[V,T2],T2]|0> (amplitude form)."""
+    return -p3_full(torch.einsum("ld,ijad,klcb->ijkabc", v[:o, o:], t2, t2))
+
+
+def _field_operator(m: Model, d: Dressed, E):
+    """The T1-transformed dipole coupling V~ = (1 - T)(-E.mu)(1 + T)."""
+    E = torch.as_tensor(np.asarray(E, dtype=np.float64)) if not torch.is_tensor(E) else E
+    return d.transform(-torch.einsum("x,xpq->pq", E.to(C128), m.mu.to(C128)))
+
+
+def _lagrangian_cc3(m: Model, t1, t2, l1, l2, t3, l3, E):
+    """L_CC3 with the field terms of its triples block, at independent t3 and lambda3."""
+    d = Dressed(m, t1, m.h(E) if not torch.is_tensor(E) else m.h0 - torch.einsum("x,xpq->pq", E, m.mu))
+    r1, r2 = ccsd_omega(d, t2)
+    ti = TriplesIntegrals(d)
+    X1, X2 = x_full(ti, t3)
+    v = _field_operator(m, d, E)
+    o = m.o
+    wp = (torch.einsum("ijae,ckbe->ijkabc", t2, ti.g_vovv) - torch.einsum("imab,mjck->ijkabc", t2, ti.g_oovo))
+    x3 = p3_full(wp) - m.d3 * t3 + vt3_full(v, t3, o) + vtt_full(v, t2, o)
+    return (ccsd_energy(d, t2) + (l1 * r1).sum() + C2 * (l2 * r2).sum() + (l1 * X1).sum() + C2 * (l2 * X2).sum()
+            + C3 * (l3 * x3).sum())
+
+
+def field_coupled_triples(m: Model, t1, t2, l1, l2, E, tol=1e-14, maxiter=200):
+    """t3 and lambda3 of L_CC3 at field E by Jacobi iteration (App. A):
+    t3 from dL/dlambda3 = 0, i.e. P W' - eps t3 + <mu3|[V,T3] + 1/2 [[V,T2],T2]|0> = 0
+    (eps = -D), and lambda3 from the stationarity of L in t3 within the
+    P(ijk/abc)-symmetric amplitudes, P(dL/dt3) = 0, linear in lambda3."""
+    o = m.o
+    with torch.no_grad():
+        d = Dressed(m, t1, m.h(E))
+        ti = TriplesIntegrals(d)
+        v = _field_operator(m, d, E)
+        src = p3_full(torch.einsum("ijae,ckbe->ijkabc", t2, ti.g_vovv)
+                      - torch.einsum("imab,mjck->ijkabc", t2, ti.g_oovo)) + vtt_full(v, t2, o)
+        t3 = src / m.d3
+        for _ in range(maxiter):
+            new = (src + vt3_full(v, t3, o)) / m.d3
+            done = (new - t3).abs().max().item() <= tol * max(1.0, new.abs().max().item())
+            t3 = new
+            if done:
+                break
+        else:
+            raise RuntimeError("field-coupled t3: no convergence")
+    l3 = l3_full(m, TriplesIntegrals(Dressed(m, t1, m.h(E))), l1, l2).detach()
+    for _ in range(maxiter):
+        t3v = t3.clone().requires_grad_(True)
+        (g,) = _holo_grad(_lagrangian_cc3(m, t1, t2, l1, l2, t3v, l3, E), [t3v])
+        g = p3_full(g) / 6.0
+        new = l3 - g / (C3 * (-m.d3))
+        done = (new - l3).abs().max().item() <= tol * max(1.0, new.abs().max().item())
+        l3 = new.detach()
+        if done:
+            break
+    else:
+        raise RuntimeError("field-coupled lambda3: no convergence")
+    return t3, l3
+
+
+def rhs_field_coupled(m: Model, y, E, with_dipole=False):
+    """dy/dt from the Euler-Lagrange equations of L_CC3 with the field terms of
+    its triples block (explicit six-index mode, tiny systems):
+      i dt/dt   = Omega + X(t3),                t3 from field_coupled_triples,
+      -i dl1/dt = dL/dt1,  -i dl2/dt = sym(dL/dt2)/C2   at fixed t3, lambda3,
+    and optionally the dipole mu_x = -dL/dE_x at fixed amplitudes (Sec. 2.2.3)."""
+    t1, t2, l1, l2 = unpack(m, y)
+    t3, l3 = field_coupled_triples(m, t1, t2, l1, l2, E)
+    t1v = t1.clone().requires_grad_(True)
+    t2v = t2.clone().requires_grad_(True)
+    Ev = torch.as_tensor(np.asarray(E, dtype=np.float64)).clone().requires_grad_(True)
+    L = _lagrangian_cc3(m, t1v, t2v, l1, l2, t3, l3, Ev)
+    g1, g2 = _holo_grad(L, [t1v, t2v])
+    with torch.no_grad():
+        d = Dressed(m, t1, m.h(E))
+        r1, r2 = ccsd_omega(d, t2)
+        X1, X2 = x_full(TriplesIntegrals(d), t3)
+    G2 = 0.5 * (g2 + g2.permute(1, 0, 3, 2)) / C2
+    dy = pack(-1j * (r1 + X1), -1j * (r2 + X2), 1j * g1, 1j * G2)
+    if not with_dipole:
+        return dy
+    L = _lagrangian_cc3(m, t1, t2, l1, l2, t3, l3, Ev)
+    gr = torch.autograd.grad(L.real, [Ev], retain_graph=True)[0]
+    gi = torch.autograd.grad(L.imag, [Ev])[0]
+    return dy, -(gr + 1j * gi)
+
+
+def propagate_field_coupled(m: Model, y0, dt, field, steps=None):
+    """Classic RK4 (Sec. 3) of rhs_field_coupled; returns (y_final, mu[steps+1, 3])."""
+    field = np.asarray(field, dtype=np.float64)
+    if steps is None:
+        steps = (field.shape[0] - 1) // 2
+    y = torch.as_tensor(np.asarray(y0), dtype=C128).clone()
+    mus = []
+    for n in range(steps):
+        k1, mu = rhs_field_coupled(m, y, field[2 * n], with_dipole=True)
+        mus.append(mu)
+        k2 = rhs_field_coupled(m, y + 0.5 * dt * k1, field[2 * n + 1])
+        k3 = rhs_field_coupled(m, y + 0.5 * dt * k2, field[2 * n + 1])
+        k4 = rhs_field_coupled(m, y + dt * k3, field[2 * n + 2])
+        y = (y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)).detach()
+    mus.append(rhs_field_coupled(m, y, field[2 * steps], with_dipole=True)[1])
+    return y, torch.stack(mus).detach()

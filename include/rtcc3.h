@@ -116,6 +116,17 @@ int rtcc3_rhs_terms(rtcc3_ctx *ctx, const double E[3], const rtcc3_c64 *y_dev, r
  * device and copied out in chunks. */
 int rtcc3_propagate(rtcc3_ctx *ctx, int steps, double dt, const double *field, rtcc3_c64 *dipole_out);
 
+/* Propagate n contexts together, `steps` RK4 steps of size dt each, context i
+ * under field fields[i] (layout as rtcc3_propagate) with its dipoles into
+ * dipole_out[i] (may be NULL, or NULL entries).  Step s of every context is
+ * enqueued on that context's own streams before step s + 1 of any, so the
+ * systems (field strengths, directions, systems of different sizes) share the
+ * device; each context must have a stream of its own (EINVAL otherwise).
+ * Returns the first member's error code (the message, naming the member, via
+ * rtcc3_last_error(NULL)); each context is left as rtcc3_propagate leaves it. */
+int rtcc3_propagate_batch(rtcc3_ctx *const *ctxs, int n, int steps, double dt, const double *const *fields,
+                          rtcc3_c64 *const *dipole_out);
+
 /* Dipole of the context's current state at field E[3] (host) -> out[3] (host). */
 int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
 
@@ -133,8 +144,26 @@ int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
  * another (for timing each kernel alone); 0 (default) = the lambda3 side of the
  * triples and the CCSD reverse sweep on two streams of the context's own.  The
  * answer does not depend on it (up to the order of atomic additions).  Setting
- * it waits for the context's streams. */
-enum { RTCC3_OPT_TRIPLES = 1, RTCC3_OPT_PRECISION = 2, RTCC3_OPT_WINDOW_BLOCKS = 3, RTCC3_OPT_SINGLE_STREAM = 4 };
+ * it waits for the context's streams.
+ * RTCC3_OPT_GRAPH: 1 = rtcc3_propagate captures one RK4 step (all its kernels,
+ * on all the context's streams) as a HIP graph at its first call with a given
+ * dt, precision and stream setting, and replays it for every step (the runtime
+ * may allocate for the graph when it is instantiated); 0 (default) = every
+ * kernel launched from the host each step.  The answer does not depend on it;
+ * with it, rtcc3_last_timing reports the total time only.
+ * RTCC3_OPT_AUTOTUNE: the K split of every product whose grid is small enough
+ * for it to matter is chosen by timing the feasible splits once, at creation
+ * (on the zero state, one stream); 1 = tune again now, 0 = forget the choices
+ * (the library's heuristic then).  The answer depends on it only through the
+ * order of atomic additions. */
+enum {
+  RTCC3_OPT_TRIPLES = 1,
+  RTCC3_OPT_PRECISION = 2,
+  RTCC3_OPT_WINDOW_BLOCKS = 3,
+  RTCC3_OPT_SINGLE_STREAM = 4,
+  RTCC3_OPT_GRAPH = 5,
+  RTCC3_OPT_AUTOTUNE = 6
+};
 int rtcc3_set_option(rtcc3_ctx *ctx, int option, int value);
 
 /* Timing of the last rtcc3_propagate (milliseconds, from HIP events on the
@@ -163,6 +192,10 @@ int rtcc3_zgemm_selftest(int M, int N, int K, int precision, const rtcc3_c64 *A,
  * share the array: calls that overlap on one device (other threads) race. */
 int rtcc3_zgemm_selftest_noalloc(int M, int N, int K, int precision, const rtcc3_c64 *A, const rtcc3_c64 *B,
                                  rtcc3_c64 *C);
+
+/* Autotuner summary: out[0] = products tuned, out[1] = those that run with a
+ * K split other than the library's heuristic. */
+int rtcc3_tuning_summary(rtcc3_ctx *ctx, int out[2]);
 
 const char *rtcc3_last_error(const rtcc3_ctx *ctx); /* ctx == NULL: last create() error of this thread */
 void rtcc3_destroy(rtcc3_ctx *ctx);

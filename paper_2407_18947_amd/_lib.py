@@ -18,11 +18,13 @@ LIBPATH = os.path.join(_HERE, "librtcc3.so")
 RTCC3_OK, RTCC3_EINVAL, RTCC3_ENOMEM, RTCC3_EDEVICE, RTCC3_ESTATE, RTCC3_EDIVERGED = 0, -1, -2, -3, -4, -5
 RTCC3_FP64, RTCC3_FP32, RTCC3_BF16X3, RTCC3_BF16X2 = 0, 1, 2, 3
 RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION, RTCC3_OPT_WINDOW_BLOCKS, RTCC3_OPT_SINGLE_STREAM = 1, 2, 3, 4
+RTCC3_OPT_GRAPH, RTCC3_OPT_AUTOTUNE = 5, 6
 
 EXPORTS = [
     "rtcc3_create", "rtcc3_set_state", "rtcc3_get_state", "rtcc3_rhs", "rtcc3_rhs_terms", "rtcc3_propagate",
+    "rtcc3_propagate_batch",
     "rtcc3_dipole", "rtcc3_set_option", "rtcc3_last_timing", "rtcc3_zgemm_selftest",
-    "rtcc3_zgemm_selftest_noalloc", "rtcc3_last_error", "rtcc3_destroy",
+    "rtcc3_zgemm_selftest_noalloc", "rtcc3_tuning_summary", "rtcc3_last_error", "rtcc3_destroy",
 ]
 
 _lib = None
@@ -49,9 +51,11 @@ def load():
     L.rtcc3_rhs.argtypes = [VP, VP, VP, VP]
     L.rtcc3_rhs_terms.argtypes = [VP, VP, VP, VP, I]
     L.rtcc3_propagate.argtypes = [VP, I, D, VP, VP]
+    L.rtcc3_propagate_batch.argtypes = [VP, I, I, D, VP, VP]
     L.rtcc3_dipole.argtypes = [VP, VP, VP]
     L.rtcc3_set_option.argtypes = [VP, I, I]
     L.rtcc3_last_timing.argtypes = [VP, VP]
+    L.rtcc3_tuning_summary.argtypes = [VP, VP]
     L.rtcc3_zgemm_selftest.argtypes = [I, I, I, I, VP, VP, VP]
     L.rtcc3_zgemm_selftest_noalloc.argtypes = [I, I, I, I, VP, VP, VP]
     L.rtcc3_last_error.argtypes = [VP]
@@ -137,6 +141,22 @@ def rtcc3_propagate(ctx, steps, dt, field, mu=None):
     return mu
 
 
+def rtcc3_propagate_batch(ctxs, steps, dt, fields, mus=None):
+    """Propagates the contexts together; returns their dipole series (list of
+    [(steps+1), 3]); `mus` (optional list) receives them even when the call raises."""
+    n = len(ctxs)
+    fields = [_f64(f) for f in fields]
+    if len(fields) != n or any(f.shape != (2 * steps + 1, 3) for f in fields):
+        raise ValueError("one field of shape (2*steps+1, 3) per context")
+    if mus is None:
+        mus = [np.empty((steps + 1, 3), dtype=np.complex128) for _ in range(n)]
+    carr = (ctypes.c_void_p * n)(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    farr = (ctypes.c_void_p * n)(*[f.ctypes.data for f in fields])
+    marr = (ctypes.c_void_p * n)(*[m.ctypes.data for m in mus])
+    _check(load().rtcc3_propagate_batch(carr, n, int(steps), float(dt), farr, marr), None)
+    return mus
+
+
 def rtcc3_dipole(ctx, E):
     E = _f64(E)
     out = np.empty(3, dtype=np.complex128)
@@ -152,6 +172,12 @@ def rtcc3_last_timing(ctx):
     out = np.zeros(6)
     _check(load().rtcc3_last_timing(ctx, _ptr(out)), ctx)
     return out
+
+
+def rtcc3_tuning_summary(ctx):
+    out = np.zeros(2, dtype=np.int32)
+    _check(load().rtcc3_tuning_summary(ctx, _ptr(out)), ctx)
+    return int(out[0]), int(out[1])
 
 
 def rtcc3_zgemm_selftest(A, B, precision=RTCC3_FP64):

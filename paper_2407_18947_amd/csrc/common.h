@@ -135,6 +135,28 @@ struct GemmDesc {
 };
 void gemm(const GemmDesc& d, hipStream_t s);
 
+// Autotuner of the products' K split.  While tuning, gemm() launches a product
+// whose grid is small enough for splitting K to matter once per feasible split
+// (powers of two between the accumulation limits and chunks of 64), times each
+// with HIP events and keeps the fastest for that product's descriptor (shapes,
+// strides, operand modes, precision); afterwards gemm() takes the kept split
+// for a descriptor it has seen and its heuristic otherwise.  Tuning launches a
+// product several times, so it is only done where repeating a product does no
+// harm (the evaluation on the zero state at context set-up).
+struct Tuner;
+Tuner* tuner_new();
+void tuner_delete(Tuner* t);
+void tuner_set_tuning(Tuner* t, bool on);
+void tuner_clear(Tuner* t);
+// products tuned, and how many of them run with a split other than the heuristic's
+void tuner_counts(const Tuner* t, int& sites, int& changed);
+// The tuner gemm() consults on this thread while the scope lives (null: none).
+struct TunerScope {
+  explicit TunerScope(Tuner* t);
+  ~TunerScope();
+  Tuner* prev;
+};
+
 // Strided elementwise: Y[idx] += alpha * X[idx] over an nd-dim box (nd <= 8).
 struct AxpyDesc {
   int nd;
@@ -149,11 +171,29 @@ void axpy_strided(const AxpyDesc& d, hipStream_t s);
 
 void fill(cplx* p, int64_t n, cplx val, hipStream_t s);
 void fill_int(int* p, int64_t n, int val, hipStream_t s);
+// Propagation state on the device, so that one RK4 step is the same work every
+// time (a captured graph replays it): pst[0] = step within the current chunk,
+// pst[1] = first step of the chunk, pst[2] = first diverged step + 1 (0: none).
+enum { PST_STEP = 0, PST_BASE = 1, PST_FLAG = 2, PST_N = 4 };
 // RK4 update guarded against divergence: cand = y + alpha * a; if an element of
-// cand is not finite, flag[0] becomes step + 1 unless it is already set; then
-// y = cand unless flag[0] is set.  Once a step diverges, y keeps the last
-// finite state for the rest of the propagation.  cand must not alias y or a.
-void guarded_update(cplx* y, const cplx* a, cplx alpha, cplx* cand, int64_t n, int* flag, int step, hipStream_t s);
+// cand is not finite, pst[PST_FLAG] becomes (pst[PST_BASE] + pst[PST_STEP]) + 1
+// unless it is already set; then y = cand unless the flag is set.  Once a step
+// diverges, y keeps the last finite state for the rest of the propagation.
+// cand must not alias y or a.
+void guarded_update(cplx* y, const cplx* a, cplx alpha, cplx* cand, int64_t n, int* pst, hipStream_t s);
+// h = h0 - sum_x E_x mu^x (n*n elements), with E read from the device (Edev, 3
+// doubles) or, when Edev is null, from ex, ey, ez.
+void build_h(cplx* h, const cplx* h0, const cplx* mu, int64_t nn, const double* Edev, const double* Ehost,
+             hipStream_t s);
+// The four RK4 stage fields of the current step from a field table of samples
+// E(k dt/2) (3 doubles each) indexed from the chunk's start: estage[0..2] = E[2c],
+// [3..5] = [6..8] = E[2c + 1], [9..11] = E[2c + 2], c = pst[PST_STEP].
+void stage_fields(const double* table, const int* pst, double* estage, hipStream_t s);
+// mus[3 c + x] = m3[x], c = pst[PST_STEP].
+void store_dipole(cplx* mus, const cplx* m3, const int* pst, hipStream_t s);
+// pst[PST_STEP] += 1, or pst[PST_STEP] = 0 and pst[PST_BASE] = base (reset).
+void advance_step(int* pst, hipStream_t s);
+void reset_step(int* pst, int base, hipStream_t s);
 // dst[0..n) = src[0..n) on the device (non-overlapping).  A kernel on the
 // stream, not a DMA-engine copy, so it orders with the kernels around it
 // without an engine switch.

@@ -3,6 +3,8 @@
 // axpy/permute, fill.
 #include <algorithm>
 #include <type_traits>
+#include <unordered_map>
+#include <vector>
 
 #include "common.h"
 
@@ -1007,9 +1009,9 @@ __global__ void fill_int_kernel(int* p, int64_t n, int v) {
 }
 
 // cand = y + alpha * a, and the first step whose candidate has a non-finite
-// element into flag[0] (as step + 1)
+// element into pst[PST_FLAG] (as step + 1)
 __global__ void update_candidate_kernel(const cplx* __restrict__ y, const cplx* __restrict__ a, cplx alpha,
-                                        cplx* __restrict__ cand, int64_t n, int* flag, int step) {
+                                        cplx* __restrict__ cand, int64_t n, int* pst) {
   bool bad = false;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const cplx x = a[e];
@@ -1019,15 +1021,55 @@ __global__ void update_candidate_kernel(const cplx* __restrict__ y, const cplx* 
     cand[e] = c;
     bad = bad || !isfinite(c.re) || !isfinite(c.im);
   }
-  if (bad) atomicCAS(flag, 0, step + 1);
+  if (bad) atomicCAS(pst + PST_FLAG, 0, pst[PST_BASE] + pst[PST_STEP] + 1);
 }
 
 // y = cand unless a step has diverged
 __global__ void update_apply_kernel(cplx* __restrict__ y, const cplx* __restrict__ cand, int64_t n,
-                                    const int* flag) {
-  if (*flag != 0) return;
+                                    const int* pst) {
+  if (pst[PST_FLAG] != 0) return;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     y[e] = cand[e];
+}
+
+__global__ void build_h_kernel(cplx* __restrict__ h, const cplx* __restrict__ h0, const cplx* __restrict__ mu,
+                               int64_t nn, const double* Edev, double ex, double ey, double ez) {
+  const double E0 = Edev ? Edev[0] : ex, E1 = Edev ? Edev[1] : ey, E2 = Edev ? Edev[2] : ez;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+    cplx x = h0[e];
+    const cplx m0 = mu[e], m1 = mu[nn + e], m2 = mu[2 * nn + e];
+    x.re -= E0 * m0.re;
+    x.im -= E0 * m0.im;
+    x.re -= E1 * m1.re;
+    x.im -= E1 * m1.im;
+    x.re -= E2 * m2.re;
+    x.im -= E2 * m2.im;
+    h[e] = x;
+  }
+}
+
+__global__ void stage_fields_kernel(const double* __restrict__ table, const int* __restrict__ pst,
+                                    double* __restrict__ estage) {
+  const int t = threadIdx.x;
+  if (t >= 12) return;
+  const int c = pst[PST_STEP], stage = t / 3, x = t % 3;
+  const int k = 2 * c + (stage == 0 ? 0 : stage == 3 ? 2 : 1);
+  estage[t] = table[3 * k + x];
+}
+
+__global__ void store_dipole_kernel(cplx* __restrict__ mus, const cplx* __restrict__ m3, const int* __restrict__ pst) {
+  const int t = threadIdx.x;
+  if (t < 3) mus[3 * pst[PST_STEP] + t] = m3[t];
+}
+
+__global__ void step_kernel(int* pst, int reset, int base) {
+  if (threadIdx.x != 0) return;
+  if (reset) {
+    pst[PST_STEP] = 0;
+    pst[PST_BASE] = base;
+  } else {
+    pst[PST_STEP] += 1;
+  }
 }
 
 __global__ void copy_kernel(cplx* __restrict__ dst, const cplx* __restrict__ src, int64_t n) {
@@ -1180,6 +1222,74 @@ GemmDesc transposed(const GemmDesc& d) {
 
 }  // namespace
 
+struct Tuner {
+  std::unordered_map<uint64_t, int> best;  // descriptor key -> K split
+  std::unordered_map<uint64_t, int> heur;  // the heuristic's split for the same products
+  bool tuning = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+namespace {
+thread_local Tuner* g_tuner = nullptr;
+
+// FNV-1a over the fields that define a product's work and layout (not its pointers).
+struct KeyHash {
+  uint64_t h = 1469598103934665603ull;
+  void add(int64_t x) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((x >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  }
+};
+uint64_t desc_key(const GemmDesc& d) {
+  KeyHash k;
+  for (int64_t x : {(int64_t)d.M, (int64_t)d.N, (int64_t)d.K, (int64_t)d.batch, (int64_t)d.M0, (int64_t)d.N0,
+                    (int64_t)d.K0, d.sAm1, d.sAm0, d.sAk1, d.sAk0, d.sAb, d.sBk1, d.sBk0, d.sBn1, d.sBn0, d.sBb,
+                    d.sCm1, d.sCm0, d.sCn1, d.sCn0, d.sCb, (int64_t)d.atomic, (int64_t)d.prec, (int64_t)d.store,
+                    (int64_t)d.nseg, (int64_t)d.ncs, (int64_t)d.comb_n, (int64_t)d.comb_on,
+                    (int64_t)(d.gk_start != nullptr), (int64_t)(d.bl != nullptr), (int64_t)d.force_prec})
+    k.add(x);
+  for (int i = 0; i < d.ncs; ++i) {
+    k.add(d.cs[i].n);
+    k.add(d.cs[i].sBk);
+    k.add(d.cs[i].sBn);
+    k.add(d.cs[i].tB != nullptr);
+  }
+  return k.h;
+}
+}  // namespace
+
+Tuner* tuner_new() {
+  Tuner* t = new Tuner();
+  if (hipEventCreate(&t->e0) != hipSuccess || hipEventCreate(&t->e1) != hipSuccess) {
+    tuner_delete(t);
+    throw Error(-3, "tuner: event creation failed");
+  }
+  return t;
+}
+void tuner_delete(Tuner* t) {
+  if (!t) return;
+  if (t->e0) (void)hipEventDestroy(t->e0);
+  if (t->e1) (void)hipEventDestroy(t->e1);
+  delete t;
+}
+void tuner_set_tuning(Tuner* t, bool on) { t->tuning = on; }
+void tuner_clear(Tuner* t) {
+  t->best.clear();
+  t->heur.clear();
+}
+void tuner_counts(const Tuner* t, int& sites, int& changed) {
+  sites = (int)t->best.size();
+  changed = 0;
+  for (auto& kv : t->best) {
+    auto it = t->heur.find(kv.first);
+    if (it != t->heur.end() && it->second != kv.second) ++changed;
+  }
+}
+TunerScope::TunerScope(Tuner* t) : prev(g_tuner) { g_tuner = t; }
+TunerScope::~TunerScope() { g_tuner = prev; }
+
 void gemm(const GemmDesc& d0, hipStream_t s) {
   if (d0.M <= 0 || d0.N <= 0 || d0.batch <= 0) return;
   if (d0.K <= 0) return;
@@ -1244,6 +1354,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   // about 512 workgroups; one that already has half a workgroup per CU splits
   // only into chunks of at least 512 (short chunks cost more in atomics and
   // loop overhead than the extra workgroups gain).
+  int64_t kmin = 1;  // the accumulation limits below
   if (!d.store && d.K >= 4 * BKMAX) {
     int64_t want = 1, maxs = 1;
     if (d.gk_start) {
@@ -1258,25 +1369,17 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   if (d.prec != RTCC3_PREC_FP64 && !d.store && !d.gk_start) {
     // FP32 accumulation: no workgroup sums more than 4096 terms (partial sums
     // are added in FP64)
-    ksplit = (int)std::max<int64_t>(ksplit, (d.K + 4095) / 4096);
+    kmin = std::max<int64_t>(kmin, (d.K + 4095) / 4096);
+    ksplit = (int)std::max<int64_t>(ksplit, kmin);
   }
   if (d.gk_start) {  // a workgroup's K range spans at most GK_MAXSEG - 4 gathered blocks,
                      // and at most 16 when it accumulates in FP32
     const int64_t nblk = d.prec == RTCC3_PREC_FP64 ? GK_MAXSEG - 4 : 16;
     const int64_t span_k = std::max<int64_t>(BKMAX, nblk * d.K0 / BKMAX * BKMAX);
-    ksplit = (int)std::max<int64_t>(ksplit, (d.K + span_k - 1) / span_k);
+    kmin = std::max<int64_t>(kmin, (d.K + span_k - 1) / span_k);
+    ksplit = (int)std::max<int64_t>(ksplit, kmin);
   }
   if (d.nseg > 0 && d.prec == RTCC3_PREC_FP64) ksplit = 1;  // the FP64 segmented kernel runs whole K ranges
-  const int kchunk = (int)((((int64_t)d.K + ksplit - 1) / ksplit + BKMAX - 1) / BKMAX * BKMAX);
-  RTCC3_CHECK(tiles * ksplit < (1LL << 31), "gemm: too many tiles");
-  RTCC3_CHECK(!d.gk_start || kchunk / d.K0 + 2 <= GK_MAXSEG, "gemm: gathered K range too long for one workgroup");
-  int64_t by = d.batch, bz = 1;
-  while (by > 65535) {
-    by = (by + 1) / 2;
-    bz *= 2;
-  }
-  dim3 grid((unsigned)(tiles * ksplit), (unsigned)by, (unsigned)bz);
-  const bool atomic = d.atomic || ksplit > 1;
   const bool kfa = d.sAk0 == 1, nfb = d.sBn0 == 1;
   RTCC3_CHECK(!d.comb_n || (kfa && !nfb), "gemm: a combined operand needs A and B read k-fast");
   // The bf16 split pays off only where the matrix cores bound the product (the
@@ -1284,23 +1387,74 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
   // FP32, which is at least as accurate.
   const bool split = d.prec == RTCC3_PREC_BF16X3 || d.prec == RTCC3_PREC_BF16X2;
   const int prec = split && ((d.nseg == 0 && !d.force_prec) || d.comb_n || d.gk_start || d.ncs) ? RTCC3_PREC_FP32 : d.prec;
-  switch (prec) {
-    case RTCC3_PREC_FP64:
-      launch_mode<RTCC3_PREC_FP64>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
-      break;
-    case RTCC3_PREC_FP32:
-      launch_mode<RTCC3_PREC_FP32>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
-      break;
-    case RTCC3_PREC_BF16X3:
-      launch_mode<RTCC3_PREC_BF16X3>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
-      break;
-    case RTCC3_PREC_BF16X2:
-      launch_mode<RTCC3_PREC_BF16X2>(d, grid, s, ksplit, kchunk, atomic, kfa, nfb, bn);
-      break;
-    default:
-      RTCC3_CHECK(false, "gemm: unknown precision");
+  auto launch = [&](int ks) {
+    const int kchunk = (int)((((int64_t)d.K + ks - 1) / ks + BKMAX - 1) / BKMAX * BKMAX);
+    RTCC3_CHECK(tiles * ks < (1LL << 31), "gemm: too many tiles");
+    RTCC3_CHECK(!d.gk_start || kchunk / d.K0 + 2 <= GK_MAXSEG, "gemm: gathered K range too long for one workgroup");
+    int64_t by = d.batch, bz = 1;
+    while (by > 65535) {
+      by = (by + 1) / 2;
+      bz *= 2;
+    }
+    dim3 grid((unsigned)(tiles * ks), (unsigned)by, (unsigned)bz);
+    const bool atomic = d.atomic || ks > 1;
+    switch (prec) {
+      case RTCC3_PREC_FP64:
+        launch_mode<RTCC3_PREC_FP64>(d, grid, s, ks, kchunk, atomic, kfa, nfb, bn);
+        break;
+      case RTCC3_PREC_FP32:
+        launch_mode<RTCC3_PREC_FP32>(d, grid, s, ks, kchunk, atomic, kfa, nfb, bn);
+        break;
+      case RTCC3_PREC_BF16X3:
+        launch_mode<RTCC3_PREC_BF16X3>(d, grid, s, ks, kchunk, atomic, kfa, nfb, bn);
+        break;
+      case RTCC3_PREC_BF16X2:
+        launch_mode<RTCC3_PREC_BF16X2>(d, grid, s, ks, kchunk, atomic, kfa, nfb, bn);
+        break;
+      default:
+        RTCC3_CHECK(false, "gemm: unknown precision");
+    }
+    RTCC3_HIP(hipGetLastError());
+  };
+  Tuner* tu = g_tuner;
+  const bool tunable = tu && !d.store && !(d.nseg > 0 && d.prec == RTCC3_PREC_FP64) && wgs < 1024 &&
+                       d.K >= 4 * BKMAX;
+  if (tunable) {
+    const uint64_t key = desc_key(d);
+    if (tu->tuning) {
+      // candidates: the heuristic's split and powers of two from kmin up to chunks of 64
+      std::vector<int> cand{ksplit};
+      const int64_t kmax = std::max<int64_t>(kmin, d.K / 64);
+      for (int64_t ks = kmin; ks <= kmax && ks <= 64; ks *= 2)
+        if (ks != ksplit) cand.push_back((int)ks);
+      launch(ksplit);  // warm the caches
+      float best_ms = 1e30f;
+      int best = ksplit;
+      for (int ks : cand) {
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          RTCC3_HIP(hipEventRecord(tu->e0, s));
+          launch(ks);
+          RTCC3_HIP(hipEventRecord(tu->e1, s));
+          RTCC3_HIP(hipEventSynchronize(tu->e1));
+          float t = 0.f;
+          RTCC3_HIP(hipEventElapsedTime(&t, tu->e0, tu->e1));
+          ms = std::min(ms, t);
+        }
+        if (ms < 0.97f * best_ms) {  // a new choice must win by more than the noise
+          best_ms = ms;
+          best = ks;
+        }
+      }
+      tu->best[key] = best;
+      tu->heur[key] = ksplit;
+      ksplit = best;
+    } else {
+      auto it = tu->best.find(key);
+      if (it != tu->best.end()) ksplit = it->second;
+    }
   }
-  RTCC3_HIP(hipGetLastError());
+  launch(ksplit);
 }
 
 void axpy_strided(const AxpyDesc& d, hipStream_t s) {
@@ -1323,13 +1477,40 @@ void fill_int(int* p, int64_t n, int val, hipStream_t s) {
   RTCC3_HIP(hipGetLastError());
 }
 
-void guarded_update(cplx* y, const cplx* a, cplx alpha, cplx* cand, int64_t n, int* flag, int step, hipStream_t s) {
+void guarded_update(cplx* y, const cplx* a, cplx alpha, cplx* cand, int64_t n, int* pst, hipStream_t s) {
   if (n <= 0) return;
   RTCC3_CHECK(cand != y && cand != a, "guarded_update: candidate buffer aliases an operand");
-  hipLaunchKernelGGL(update_candidate_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, a, alpha, cand, n, flag,
-                     step);
+  hipLaunchKernelGGL(update_candidate_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, a, alpha, cand, n, pst);
   RTCC3_HIP(hipGetLastError());
-  hipLaunchKernelGGL(update_apply_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, cand, n, flag);
+  hipLaunchKernelGGL(update_apply_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, cand, n, pst);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void build_h(cplx* h, const cplx* h0, const cplx* mu, int64_t nn, const double* Edev, const double* Ehost,
+             hipStream_t s) {
+  RTCC3_CHECK(Edev || Ehost, "build_h: no field");
+  const double ex = Edev ? 0.0 : Ehost[0], ey = Edev ? 0.0 : Ehost[1], ez = Edev ? 0.0 : Ehost[2];
+  hipLaunchKernelGGL(build_h_kernel, dim3(grid_for(nn, 256)), dim3(256), 0, s, h, h0, mu, nn, Edev, ex, ey, ez);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void stage_fields(const double* table, const int* pst, double* estage, hipStream_t s) {
+  hipLaunchKernelGGL(stage_fields_kernel, dim3(1), dim3(64), 0, s, table, pst, estage);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void store_dipole(cplx* mus, const cplx* m3, const int* pst, hipStream_t s) {
+  hipLaunchKernelGGL(store_dipole_kernel, dim3(1), dim3(64), 0, s, mus, m3, pst);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void advance_step(int* pst, hipStream_t s) {
+  hipLaunchKernelGGL(step_kernel, dim3(1), dim3(64), 0, s, pst, 0, 0);
+  RTCC3_HIP(hipGetLastError());
+}
+
+void reset_step(int* pst, int base, hipStream_t s) {
+  hipLaunchKernelGGL(step_kernel, dim3(1), dim3(64), 0, s, pst, 1, base);
   RTCC3_HIP(hipGetLastError());
 }
 

@@ -25,9 +25,18 @@ struct rtcc3_ctx {
   View B, mu, h0, I, ones_o, h;
   cplx *y = nullptr, *ytmp = nullptr, *k = nullptr, *acc = nullptr;
   double last_ms[6] = {0, 0, 0, 0, 0, 0};
-  cplx* mus = nullptr;     // dipole series of up to kMusSteps steps (+1), copied out per chunk
-  cplx* mu_out = nullptr;  // dipole of rtcc3_dipole
-  int* flag = nullptr;     // first diverged step + 1 of the current propagation (0: none)
+  cplx* mus = nullptr;      // dipole series of up to kMusSteps steps (+1), copied out per chunk
+  cplx* mu_out = nullptr;   // dipole of rtcc3_dipole
+  int* pst = nullptr;       // propagation state on the device (PST_*: step, chunk base, divergence flag)
+  double* ftab = nullptr;   // field samples E(k dt/2) of the current chunk, 3 doubles each
+  double* estage = nullptr; // the four stage fields of the current step
+  // one RK4 step captured as a graph (RTCC3_OPT_GRAPH), valid for these settings
+  int use_graph = 0;
+  Tuner* tuner = nullptr;  // K splits of the products, tuned at set-up
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_dt = 0.0;
+  int g_tri = -1, g_prec = -1, g_single = -1;
   std::string err;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // the CCSD reverse sweep runs on side_stream beside the triples windows
@@ -67,30 +76,31 @@ inline cplx C(double re, double im = 0.0) { return cplx{re, im}; }
 
 View sub(cplx* p, int64_t off, std::vector<int64_t> shape) { return Engine::raw(p + off, shape); }
 
-// h = h0 - sum_x E_x mu^x
-void build_h(rtcc3_ctx* c, const double E[3]) {
-  Engine& e = *c->e;
-  const int64_t n = c->d.n;
-  copy(c->h.p, c->h0.p, n * n, c->stream);
-  for (int x = 0; x < 3; ++x)
-    if (E[x] != 0.0) e.axpy(C(-E[x]), Engine::raw(c->mu.p + x * n * n, {n, n}), c->h);
-}
+// The field of one right-hand side: three host doubles, or three device doubles
+// (the propagation's stage fields, so that a step is the same work every time).
+struct FieldRef {
+  const double* host = nullptr;
+  const double* dev = nullptr;
+};
 
 struct TermsOut {
-  cplx* terms = nullptr;  // optional rtcc3_rhs_terms layout
-  cplx* mu = nullptr;     // optional dipole (device, 3)
+  cplx* terms = nullptr;    // optional rtcc3_rhs_terms layout
+  cplx* mu = nullptr;       // optional dipole (device, 3)
+  bool mu_at_step = false;  // dipole into the propagation's series at the device step counter
 };
 
 // dy = f(y) at field E; optionally the individual terms and/or the dipole.
-void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const TermsOut& t, bool with_triples) {
+void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut& t, bool with_triples) {
   Engine& e = *c->e;
   const Dims& d = c->d;
   const int64_t o = d.o, v = d.v, n = d.n;
   const int64_t ov = o * v, oovv = o * o * v * v;
-  build_h(c, E);
+  TunerScope tuned(c->tuner);
+  // h = h0 - sum_x E_x mu^x
+  build_h(c->h.p, c->h0.p, c->mu.p, n * n, E.dev, E.host, c->stream);
   CCSDResult r = ccsd_forward(e, d, y, c->h, c->B, c->I, c->ones_o);
   ccsd_residual(e, d, r);
-  const bool want_density = t.terms || t.mu;
+  const bool want_density = t.terms || t.mu || t.mu_at_step;
 
   TriplesOut to;
   if (with_triples) {
@@ -152,6 +162,7 @@ void rhs_impl(rtcc3_ctx* c, const double E[3], const cplx* y, cplx* dy, const Te
     e.zero(m3);
     e.einsum("pq,xpq->x", ONE, D, mut, m3);
     if (t.mu) copy(t.mu, m3.p, 3, c->stream);
+    if (t.mu_at_step) store_dipole(c->mus, m3.p, c->pst, c->stream);
     if (t.terms) {
       cplx* p = t.terms;
       auto put = [&](const View& src, int64_t len) {
@@ -189,18 +200,187 @@ constexpr int kMusSteps = 1024;
 // with the dipole, the plain right-hand side) on the current state, so that
 // every buffer, scratch area and gradient the evaluation uses is allocated
 // now; then seal the engine, after which a propagation allocates nothing.
-void warm_up(rtcc3_ctx* c) {
-  const double E0[3] = {0.0, 0.0, 0.0};
+void warm_up(rtcc3_ctx* c, bool tune) {
+  static const double E0[3] = {0.0, 0.0, 0.0};
   c->e->seal(false);
   TermsOut t;
   t.mu = c->mu_out;
-  rhs_impl(c, E0, c->y, c->k, t, true);
-  rhs_impl(c, E0, c->y, c->k, TermsOut{}, true);
+  if (tune) {
+    // the K splits are timed one product at a time, all on one stream; repeating
+    // a product is harmless here, where every result is discarded
+    const int single = c->single_stream;
+    c->single_stream = 1;
+    c->tri->set_single_stream(true);
+    tuner_set_tuning(c->tuner, true);
+    try {
+      rhs_impl(c, FieldRef{E0, nullptr}, c->y, c->k, t, true);
+      rhs_impl(c, FieldRef{E0, nullptr}, c->y, c->k, TermsOut{}, true);
+    } catch (...) {
+      tuner_set_tuning(c->tuner, false);
+      c->single_stream = single;
+      c->tri->set_single_stream(single != 0);
+      throw;
+    }
+    tuner_set_tuning(c->tuner, false);
+    c->single_stream = single;
+    c->tri->set_single_stream(single != 0);
+  }
+  rhs_impl(c, FieldRef{E0, nullptr}, c->y, c->k, t, true);
+  rhs_impl(c, FieldRef{E0, nullptr}, c->y, c->k, TermsOut{}, true);
   RTCC3_HIP(hipStreamSynchronize(c->stream));
   RTCC3_HIP(hipStreamSynchronize(c->side_stream));
   c->tri->reset_timing();
   c->e->seal(true);
 }
+
+void drop_graph(rtcc3_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+// One RK4 step of the context's state, the same work every step: the stage
+// fields come from the device field table at the device step counter, the
+// dipole of the step's starting state goes to the counter's slot of the
+// series, and the counter advances at the end, so a captured graph of it can
+// be replayed step after step.
+void step_body(rtcc3_ctx* c, double dt, bool tri) {
+  Engine& e = *c->e;
+  const int64_t L = c->ylen;
+  View YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}), A = Engine::raw(c->acc, {L});
+  auto copyL = [&](cplx* dst, const cplx* src) { copy(dst, src, L, c->stream); };
+  stage_fields(c->ftab, c->pst, c->estage, c->stream);
+  TermsOut t;
+  t.mu_at_step = true;
+  rhs_impl(c, FieldRef{nullptr, c->estage}, c->y, c->k, t, tri);  // k1 (and mu(t_s))
+  copyL(c->acc, c->k);
+  copyL(c->ytmp, c->y);
+  e.axpy(C(0.5 * dt), K, YT);
+  rhs_impl(c, FieldRef{nullptr, c->estage + 3}, c->ytmp, c->k, TermsOut{}, tri);  // k2
+  e.axpy(C(2.0), K, A);
+  copyL(c->ytmp, c->y);
+  e.axpy(C(0.5 * dt), K, YT);
+  rhs_impl(c, FieldRef{nullptr, c->estage + 6}, c->ytmp, c->k, TermsOut{}, tri);  // k3
+  e.axpy(C(2.0), K, A);
+  copyL(c->ytmp, c->y);
+  e.axpy(C(dt), K, YT);
+  rhs_impl(c, FieldRef{nullptr, c->estage + 9}, c->ytmp, c->k, TermsOut{}, tri);  // k4
+  e.axpy(ONE, K, A);
+  // y += dt/6 (k1 + 2 k2 + 2 k3 + k4) unless the result is not finite: then y
+  // keeps its last finite value (ytmp is free after k4)
+  guarded_update(c->y, c->acc, C(dt / 6.0), c->ytmp, L, c->pst, c->stream);
+  advance_step(c->pst, c->stream);
+}
+
+// The step captured as a graph, once per step size and settings.
+void ensure_graph(rtcc3_ctx* c, double dt, bool tri) {
+  if (c->gexec && c->g_dt == dt && c->g_tri == (int)tri && c->g_prec == c->precision &&
+      c->g_single == c->single_stream)
+    return;
+  drop_graph(c);
+  c->tri->set_timing(false);
+  RTCC3_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    step_body(c, dt, tri);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(c->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    c->tri->set_timing(true);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+  c->tri->set_timing(true);
+  RTCC3_HIP(ec);
+  c->graph = g;
+  RTCC3_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->g_dt = dt;
+  c->g_tri = (int)tri;
+  c->g_prec = c->precision;
+  c->g_single = c->single_stream;
+}
+
+// The propagation of one context: fields and dipoles in chunks of kMusSteps
+// steps, each step eager or a replay of the captured graph.
+struct Runner {
+  rtcc3_ctx* c;
+  int steps;
+  double dt;
+  const double* field;
+  bool tri;
+  std::vector<cplx> mh;
+  int base = 0;
+
+  void chunk(int s0) {  // the fields of the steps from s0 on, counter reset to s0
+    const int n = std::min(kMusSteps, steps - s0);
+    RTCC3_HIP(hipMemcpyAsync(c->ftab, field + 6 * (size_t)s0, sizeof(double) * 3 * (2 * (size_t)n + 1),
+                             hipMemcpyHostToDevice, c->stream));
+    reset_step(c->pst, s0, c->stream);
+    base = s0;
+  }
+  void flush(int upto) {  // dipoles base .. upto - 1 to the host (waits for them)
+    RTCC3_HIP(hipMemcpyAsync(mh.data() + 3 * (size_t)base, c->mus, sizeof(cplx) * 3 * (size_t)(upto - base),
+                             hipMemcpyDeviceToHost, c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+  }
+  void begin() {
+    mh.assign((size_t)(steps + 1) * 3, cplx{0, 0});
+    c->tri->reset_timing();
+    if (c->use_graph && steps > 0) ensure_graph(c, dt, tri);
+    fill_int(c->pst, PST_N, 0, c->stream);
+    RTCC3_HIP(hipEventRecord(c->ev0, c->stream));
+  }
+  void step(int s) {
+    if (s % kMusSteps == 0) {
+      if (s > 0) flush(s);
+      chunk(s);
+    }
+    if (c->use_graph)
+      RTCC3_HIP(hipGraphLaunch(c->gexec, c->stream));
+    else
+      step_body(c, dt, tri);
+  }
+  int finish(rtcc3_c64* dipole_out) {
+    if (steps == 0) {
+      chunk(0);
+    } else if (steps - base == kMusSteps) {
+      flush(steps);
+      chunk(steps);
+    }
+    stage_fields(c->ftab, c->pst, c->estage, c->stream);
+    TermsOut t;
+    t.mu_at_step = true;
+    rhs_impl(c, FieldRef{nullptr, c->estage}, c->y, nullptr, t, tri);
+    RTCC3_HIP(hipEventRecord(c->ev1, c->stream));
+    int ph[PST_N] = {0, 0, 0, 0};
+    RTCC3_HIP(hipMemcpyAsync(ph, c->pst, sizeof(ph), hipMemcpyDeviceToHost, c->stream));
+    flush(steps + 1);
+    float ms = 0.f;
+    RTCC3_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms[0] = ms;
+    c->tri->fold_timing();
+    c->tri->timing(c->last_ms[1], c->last_ms[2]);
+    c->tri->build_timing(c->last_ms[3], c->last_ms[4], c->last_ms[5]);
+    const int bad = ph[PST_FLAG];
+    if (bad) {
+      // step bad - 1 gave a non-finite state: y is the state after bad - 1 steps,
+      // whose dipoles (indices 0 .. bad - 1) are valid; the later ones are not
+      const double nan = std::nan("");
+      for (size_t q = (size_t)bad; q < (size_t)steps + 1; ++q)
+        mh[3 * q] = mh[3 * q + 1] = mh[3 * q + 2] = cplx{nan, nan};
+    }
+    if (dipole_out) std::memcpy(dipole_out, mh.data(), sizeof(cplx) * mh.size());
+    if (bad)
+      return fail(c, RTCC3_EDIVERGED,
+                  "state became non-finite in step " + std::to_string(bad - 1) + "; the state is left after " +
+                      std::to_string(bad - 1) + " steps");
+    for (auto& z : mh)
+      if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(c, RTCC3_EDIVERGED, "dipole became non-finite");
+    return RTCC3_OK;
+  }
+};
 
 bool finite(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
@@ -312,9 +492,13 @@ extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const do
     c->acc = e.tensor("acc", {c->ylen}).p;
     c->mus = e.tensor("mus", {kMusSteps + 1, 3}).p;
     c->mu_out = e.tensor("mu_out", {3}).p;
-    c->flag = (int*)e.tensor("flag", {1}).p;
-    // every buffer of an evaluation now, none while propagating (the state is zero)
-    warm_up(c.get());
+    c->pst = (int*)e.tensor("pst", {(PST_N * (int64_t)sizeof(int) + 15) / 16}).p;
+    c->ftab = (double*)e.tensor("ftab", {(3 * (2 * (int64_t)kMusSteps + 1) + 1) / 2}).p;
+    c->estage = (double*)e.tensor("estage", {6}).p;
+    // every buffer of an evaluation now, none while propagating (the state is
+    // zero), and the K splits of the products
+    c->tuner = tuner_new();
+    warm_up(c.get(), true);
     return RTCC3_OK;
   });
   if (rc != RTCC3_OK) {
@@ -358,7 +542,7 @@ extern "C" int rtcc3_rhs(rtcc3_ctx* c, const double E[3], const rtcc3_c64* y_dev
   if (!field_ok(E)) return fail(c, RTCC3_EINVAL, "field must be 3 finite numbers");
   if (!y_dev || !dy_dev) return fail(c, RTCC3_EINVAL, "NULL state pointer");
   return guarded(c, [&]() -> int {
-    rhs_impl(c, E, (const cplx*)y_dev, (cplx*)dy_dev, TermsOut{}, c->with_triples != 0);
+    rhs_impl(c, FieldRef{E, nullptr}, (const cplx*)y_dev, (cplx*)dy_dev, TermsOut{}, c->with_triples != 0);
     RTCC3_HIP(hipStreamSynchronize(c->stream));
     c->tri->fold_timing();
     return RTCC3_OK;
@@ -373,7 +557,7 @@ extern "C" int rtcc3_rhs_terms(rtcc3_ctx* c, const double E[3], const rtcc3_c64*
   return guarded(c, [&]() -> int {
     TermsOut t;
     t.terms = (cplx*)terms_dev;
-    rhs_impl(c, E, (const cplx*)y_dev, nullptr, t, with_triples != 0);
+    rhs_impl(c, FieldRef{E, nullptr}, (const cplx*)y_dev, nullptr, t, with_triples != 0);
     RTCC3_HIP(hipStreamSynchronize(c->stream));
     c->tri->fold_timing();
     return RTCC3_OK;
@@ -386,7 +570,7 @@ extern "C" int rtcc3_dipole(rtcc3_ctx* c, const double E[3], rtcc3_c64 out[3]) {
   return guarded(c, [&]() -> int {
     TermsOut t;
     t.mu = c->mu_out;
-    rhs_impl(c, E, c->y, nullptr, t, c->with_triples != 0);
+    rhs_impl(c, FieldRef{E, nullptr}, c->y, nullptr, t, c->with_triples != 0);
     RTCC3_HIP(hipMemcpyAsync(out, c->mu_out, sizeof(cplx) * 3, hipMemcpyDeviceToHost, c->stream));
     RTCC3_HIP(hipStreamSynchronize(c->stream));
     c->tri->fold_timing();
@@ -394,94 +578,87 @@ extern "C" int rtcc3_dipole(rtcc3_ctx* c, const double E[3], rtcc3_c64 out[3]) {
   });
 }
 
-extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double* field, rtcc3_c64* dipole_out) {
-  if (!c) return RTCC3_EINVAL;
+namespace {
+
+int check_propagate_args(rtcc3_ctx* c, int steps, double dt, const double* field) {
   if (steps < 0) return fail(c, RTCC3_EINVAL, "steps < 0");
   if (!(std::isfinite(dt)) || dt == 0.0) return fail(c, RTCC3_EINVAL, "dt must be finite and non-zero");
   if (!field) return fail(c, RTCC3_EINVAL, "field is NULL");
   if (!finite(field, (int64_t)(2 * steps + 1) * 3)) return fail(c, RTCC3_EINVAL, "non-finite field");
+  return RTCC3_OK;
+}
+
+}  // namespace
+
+extern "C" int rtcc3_propagate(rtcc3_ctx* c, int steps, double dt, const double* field, rtcc3_c64* dipole_out) {
+  if (!c) return RTCC3_EINVAL;
+  if (int rc = check_propagate_args(c, steps, dt, field)) return rc;
   return guarded(c, [&]() -> int {
-    Engine& e = *c->e;
-    const int64_t L = c->ylen;
-    const bool tri = c->with_triples != 0;
-    View YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}), A = Engine::raw(c->acc, {L});
-    auto copyL = [&](cplx* dst, const cplx* src) { copy(dst, src, L, c->stream); };
-    // The dipoles of up to kMusSteps steps stay on the device; a full chunk is
-    // copied out (which waits for it) before the next one starts.
-    std::vector<cplx> mh((size_t)(steps + 1) * 3);
-    int base = 0;  // dipole index held in c->mus[0]
-    auto flush = [&](int upto) {
-      RTCC3_HIP(hipMemcpyAsync(mh.data() + 3 * (size_t)base, c->mus, sizeof(cplx) * 3 * (size_t)(upto - base),
-                               hipMemcpyDeviceToHost, c->stream));
-      RTCC3_HIP(hipStreamSynchronize(c->stream));
-      base = upto;
-    };
-    c->tri->reset_timing();
-    fill_int(c->flag, 1, 0, c->stream);
-    RTCC3_HIP(hipEventRecord(c->ev0, c->stream));
-    for (int s = 0; s < steps; ++s) {
-      if (s - base == kMusSteps) flush(s);
-      const double* E0 = field + 3 * (2 * s);
-      const double* Eh = field + 3 * (2 * s + 1);
-      const double* E1 = field + 3 * (2 * s + 2);
-      TermsOut t;
-      t.mu = c->mus + 3 * (s - base);
-      rhs_impl(c, E0, c->y, c->k, t, tri);  // k1 (and mu(t_s))
-      copyL(c->acc, c->k);
-      copyL(c->ytmp, c->y);
-      e.axpy(C(0.5 * dt), K, YT);
-      rhs_impl(c, Eh, c->ytmp, c->k, TermsOut{}, tri);  // k2
-      e.axpy(C(2.0), K, A);
-      copyL(c->ytmp, c->y);
-      e.axpy(C(0.5 * dt), K, YT);
-      rhs_impl(c, Eh, c->ytmp, c->k, TermsOut{}, tri);  // k3
-      e.axpy(C(2.0), K, A);
-      copyL(c->ytmp, c->y);
-      e.axpy(C(dt), K, YT);
-      rhs_impl(c, E1, c->ytmp, c->k, TermsOut{}, tri);  // k4
-      e.axpy(ONE, K, A);
-      // y += dt/6 (k1 + 2 k2 + 2 k3 + k4) unless the result is not finite:
-      // then y keeps its last finite value (ytmp is free after k4)
-      guarded_update(c->y, c->acc, C(dt / 6.0), c->ytmp, L, c->flag, s, c->stream);
-    }
-    if (steps - base == kMusSteps) flush(steps);
-    {
-      TermsOut t;
-      t.mu = c->mus + 3 * (steps - base);
-      rhs_impl(c, field + 3 * (2 * steps), c->y, nullptr, t, tri);
-    }
-    RTCC3_HIP(hipEventRecord(c->ev1, c->stream));
-    int bad = 0;
-    RTCC3_HIP(hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    flush(steps + 1);
-    float ms = 0.f;
-    RTCC3_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    c->last_ms[0] = ms;
-    c->tri->fold_timing();
-    c->tri->timing(c->last_ms[1], c->last_ms[2]);
-    c->tri->build_timing(c->last_ms[3], c->last_ms[4], c->last_ms[5]);
-    if (bad) {
-      // step bad - 1 gave a non-finite state: y is the state after bad - 1 steps,
-      // whose dipoles (indices 0 .. bad - 1) are valid; the later ones are not
-      const double nan = std::nan("");
-      for (size_t n = (size_t)bad; n < (size_t)steps + 1; ++n)
-        mh[3 * n] = mh[3 * n + 1] = mh[3 * n + 2] = cplx{nan, nan};
-    }
-    if (dipole_out) std::memcpy(dipole_out, mh.data(), sizeof(cplx) * mh.size());
-    if (bad)
-      return fail(c, RTCC3_EDIVERGED,
-                  "state became non-finite in step " + std::to_string(bad - 1) + "; the state is left after " +
-                      std::to_string(bad - 1) + " steps");
-    for (auto& z : mh)
-      if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(c, RTCC3_EDIVERGED, "dipole became non-finite");
-    return RTCC3_OK;
+    Runner r{c, steps, dt, field, c->with_triples != 0};
+    r.begin();
+    for (int s = 0; s < steps; ++s) r.step(s);
+    return r.finish(dipole_out);
   });
+}
+
+extern "C" int rtcc3_propagate_batch(rtcc3_ctx* const* ctxs, int n, int steps, double dt, const double* const* fields,
+                                     rtcc3_c64* const* dipole_out) {
+  if (!ctxs || n < 1) return fail(nullptr, RTCC3_EINVAL, "batch: need at least one context");
+  if (!fields) return fail(nullptr, RTCC3_EINVAL, "batch: fields is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(nullptr, RTCC3_EINVAL, "batch: NULL context");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i] || ctxs[j]->stream == ctxs[i]->stream)
+        return fail(nullptr, RTCC3_EINVAL, "batch: contexts must be distinct and on distinct streams");
+    if (int rc = check_propagate_args(ctxs[i], steps, dt, fields[i])) {
+      set_thread_error(ctxs[i]->err);
+      return rc;
+    }
+  }
+  std::vector<Runner> rs;
+  int rc = guarded(ctxs[0], [&]() -> int {
+    for (int i = 0; i < n; ++i) rs.push_back(Runner{ctxs[i], steps, dt, fields[i], ctxs[i]->with_triples != 0});
+    for (auto& r : rs) r.begin();
+    // lockstep: step s of every context is enqueued on its own streams before step s + 1
+    for (int s = 0; s < steps; ++s)
+      for (auto& r : rs) r.step(s);
+    int first = RTCC3_OK;
+    for (int i = 0; i < n; ++i) {
+      const int ri = rs[i].finish(dipole_out ? dipole_out[i] : nullptr);
+      if (ri != RTCC3_OK && first == RTCC3_OK) {
+        first = ri;
+        set_thread_error("batch member " + std::to_string(i) + ": " + ctxs[i]->err);
+      }
+    }
+    return first;
+  });
+  if (rc != RTCC3_OK && rc != RTCC3_EDIVERGED) set_thread_error(ctxs[0]->err);
+  return rc;
 }
 
 extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
   if (!c) return RTCC3_EINVAL;
   if (option == RTCC3_OPT_TRIPLES) {
     c->with_triples = value ? 1 : 0;
+    return RTCC3_OK;
+  }
+  if (option == RTCC3_OPT_AUTOTUNE) {
+    return guarded(c, [&]() -> int {
+      RTCC3_HIP(hipStreamSynchronize(c->side_stream));
+      drop_graph(c);  // captured with the old splits
+      tuner_clear(c->tuner);
+      if (!value) return RTCC3_OK;
+      std::vector<cplx> keep((size_t)c->ylen);
+      RTCC3_HIP(hipMemcpy(keep.data(), c->y, sizeof(cplx) * keep.size(), hipMemcpyDeviceToHost));
+      fill(c->y, c->ylen, cplx{0, 0}, c->stream);
+      warm_up(c, true);
+      RTCC3_HIP(hipMemcpy(c->y, keep.data(), sizeof(cplx) * keep.size(), hipMemcpyHostToDevice));
+      return RTCC3_OK;
+    });
+  }
+  if (option == RTCC3_OPT_GRAPH) {
+    c->use_graph = value ? 1 : 0;
+    if (!c->use_graph) drop_graph(c);
     return RTCC3_OK;
   }
   if (option == RTCC3_OPT_PRECISION) {
@@ -503,13 +680,14 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
     if (value < 0) return fail(c, RTCC3_EINVAL, "negative window size");
     return guarded(c, [&]() -> int {
       RTCC3_HIP(hipStreamSynchronize(c->side_stream));
+      drop_graph(c);  // it refers to the window buffers being replaced
       c->e->seal(false);
       c->tri->set_window_blocks(*c->e, value);
       // the window buffers of the new size now, none later; the state is kept
       std::vector<cplx> keep((size_t)c->ylen);
       RTCC3_HIP(hipMemcpy(keep.data(), c->y, sizeof(cplx) * keep.size(), hipMemcpyDeviceToHost));
       fill(c->y, c->ylen, cplx{0, 0}, c->stream);
-      warm_up(c);
+      warm_up(c, false);
       RTCC3_HIP(hipMemcpy(c->y, keep.data(), sizeof(cplx) * keep.size(), hipMemcpyHostToDevice));
       return RTCC3_OK;
     });
@@ -523,12 +701,20 @@ extern "C" int rtcc3_last_timing(rtcc3_ctx* c, double kernel_ms[6]) {
   return RTCC3_OK;
 }
 
+extern "C" int rtcc3_tuning_summary(rtcc3_ctx* c, int out[2]) {
+  if (!c || !out) return RTCC3_EINVAL;
+  tuner_counts(c->tuner, out[0], out[1]);
+  return RTCC3_OK;
+}
+
 extern "C" const char* rtcc3_last_error(const rtcc3_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   c->tri.reset();
+  tuner_delete(c->tuner);
   c->e.reset();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

@@ -1049,6 +1049,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
 }
 
 void Triples::build_event(hipStream_t s) {
+  if (!timing_on_) return;
   // pairs: a full pool is folded before a pair starts
   if (nbev_ % 2 == 0 && nbev_ + 2 > (int)bev_.size()) fold_timing();
   RTCC3_HIP(hipEventRecord(bev_[nbev_++], s));
@@ -1059,8 +1060,10 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
   const int64_t o = d.o, v = d.v;
   const int64_t ov = o * v, oovv = o * o * v * v;
   hipStream_t s = e.stream;
-  if (nrev_ + 2 > (int)rev_.size()) fold_timing();
-  RTCC3_HIP(hipEventRecord(rev_[nrev_++], s));
+  if (timing_on_) {
+    if (nrev_ + 2 > (int)rev_.size()) fold_timing();
+    RTCC3_HIP(hipEventRecord(rev_[nrev_++], s));
+  }
   blocks(e, r);
   beside_ = beside ? &beside : nullptr;
   side_done_ = nullptr;
@@ -1135,7 +1138,7 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
     out.Dab = Dab;
     out.Dia = Dia;
   }
-  RTCC3_HIP(hipEventRecord(rev_[nrev_++], s));
+  if (timing_on_) RTCC3_HIP(hipEventRecord(rev_[nrev_++], s));
   return out;
 }
 

@@ -83,6 +83,9 @@ class Triples {
     build_launches_ = 0;
     build_flop_ = 0;
   }
+  // Record timing events (default); off while a graph is captured, whose
+  // replays are timed as a whole by the caller.
+  void set_timing(bool on) { timing_on_ = on; }
   // Wait for the timing events recorded so far and add up their intervals
   // (call after the caller's stream has been synchronised; also done by run()
   // itself when an event pool is full).
@@ -117,6 +120,7 @@ class Triples {
   // totals by fold_timing() so that no run waits for the device.
   std::vector<hipEvent_t> rev_, bev_;
   int nrev_ = 0;
+  bool timing_on_ = true;
   // A window's lambda3 side (build, symmetrisation, the contractions that read
   // lambda3 only) runs on a second stream beside the t3 side; ev_fork_ /
   // ev_l_ / ev_join_ order the two.

@@ -23,6 +23,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import torch  # noqa: E402  (device memory and streams of the binding)
+
 METRIC = "RK4 steps/sec (T+Λ RT-CC3) at o=15,v=57; FP32-split vs FP64 at dipole err"
 PAPER_GPU_DP_TRIMER_STEPS_PER_S = 1.0 / 806.52  # Table 1, GPU-dp, water trimer (P100)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
@@ -134,6 +136,116 @@ def alpha_proxy(make_ctx, y0, steps, dt, amp, codes, precisions):
     return out
 
 
+MIXED_BATCH = [(5, 19, 30), (5, 36, 31), (10, 38, 32), (10, 72, 33), (5, 19, 34), (5, 36, 35), (10, 38, 36),
+               (10, 72, 37)]
+
+
+def batched_mixed(codes, precision, steps, dt, amp):
+    """The mixed-size batch (two systems each of (o,v) = (5,19), (5,36), (10,38), (10,72),
+    seeds 30..37), delta kick along z, every member with a captured step graph:
+    lockstep batch against the same members propagated one after another."""
+    from paper_2407_18947_amd import _lib
+    from paper_2407_18947_amd.inputs import field_delta_kick, initial_state, make_system
+
+    systems = [make_system(o, v, seed=sd) for o, v, sd in MIXED_BATCH]
+    ctxs = [_lib.Context(s, codes[precision]) for s in systems]
+    try:
+        for c in ctxs:
+            c.set_option(_lib.RTCC3_OPT_GRAPH, 1)
+        f = field_delta_kick(steps, dt, amp, "z")
+        fields = [f] * len(ctxs)
+
+        def reset():
+            for c, s in zip(ctxs, systems):
+                c.set_state(initial_state(s))
+
+        reset()
+        _lib.rtcc3_propagate_batch([c.ctx for c in ctxs], 1, dt, [f[:3]] * len(ctxs))  # captures the graphs
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _lib.rtcc3_propagate_batch([c.ctx for c in ctxs], steps, dt, fields)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        reset()
+        t0 = time.perf_counter()
+        for c in ctxs:
+            c.propagate(steps, dt, f)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+    finally:
+        for c in ctxs:
+            c.close()
+    n = len(ctxs)
+    return {
+        "members": [f"({o},{v}) seed {sd}" for o, v, sd in MIXED_BATCH],
+        "precision": precision,
+        "steps": steps,
+        "aggregate_steps_per_s": n * steps / t_batch,
+        "one_after_another_steps_per_s": n * steps / t_seq,
+        "speedup_vs_one_after_another": t_seq / t_batch,
+    }
+
+
+def graph_gain(codes, steps, dt, amp, o=5, v=19, seed=1):
+    """Steps/s of one small system (monomer size) with its step captured as a graph
+    against per-kernel launches from the host."""
+    from paper_2407_18947_amd import _lib
+    from paper_2407_18947_amd.inputs import field_delta_kick, initial_state, make_system
+
+    s = make_system(o, v, seed=seed)
+    out = {}
+    f = field_delta_kick(steps, dt, amp, "z")
+    for graph in (0, 1):
+        ctx = _lib.Context(s, codes["fp64"])
+        ctx.set_option(_lib.RTCC3_OPT_GRAPH, graph)
+        ctx.set_state(initial_state(s))
+        ctx.propagate(2, dt, f[:5])
+        ctx.set_state(initial_state(s))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.propagate(steps, dt, f)
+        torch.cuda.synchronize()
+        out["graph" if graph else "launches"] = steps / (time.perf_counter() - t0)
+        ctx.close()
+    return {"workload": f"o={o}, v={v}, seed {seed}, fp64", "steps": steps,
+            "steps_per_s_launches": out["launches"], "steps_per_s_graph": out["graph"],
+            "speedup": out["graph"] / out["launches"]}
+
+
+def batched_finite_field_trimer(codes, precision, steps, dt, window_blocks, s, y0):
+    """The twelve-member finite-field set at the trimer size: three directions times
+    delta kicks of +-0.001 and +-0.002 a.u., one lockstep batch (window cap per
+    member so that all twelve fit); aggregate steps/s and alpha_zz from the four z
+    members by the four-point formula."""
+    from paper_2407_18947_amd import _lib
+    from paper_2407_18947_amd import properties as P
+    from paper_2407_18947_amd.inputs import field_delta_kick
+
+    members = [(d, a) for d in "xyz" for a in (0.001, -0.001, 0.002, -0.002)]
+    ctxs = []
+    try:
+        for _ in members:
+            c = _lib.Context(s, codes[precision])
+            c.set_option(_lib.RTCC3_OPT_WINDOW_BLOCKS, window_blocks)
+            ctxs.append(c)
+        for c in ctxs:
+            c.set_state(y0)
+        fields = [field_delta_kick(steps, dt, a, d) for d, a in members]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mus = _lib.rtcc3_propagate_batch([c.ctx for c in ctxs], steps, dt, fields)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    finally:
+        for c in ctxs:
+            c.close()
+    z = {a: mus[i][:, 2] for i, (d, a) in enumerate(members) if d == "z"}
+    mu1 = P.finite_field_mu1(z[0.001], z[-0.001], z[0.002], z[-0.002], 0.001)
+    return {"members": len(members), "precision": precision, "steps": steps, "window_blocks": window_blocks,
+            "aggregate_steps_per_s": len(members) * steps / t, "mu1_z_last": complex(mu1[-1]).real}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +264,10 @@ def main():
                     help="every kernel on one stream, one after another (times each kernel alone; not the metric)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference kernel for HBM counters)")
+    ap.add_argument("--batch-steps", type=int, default=10,
+                    help="steps of the mixed-size batch and of the graph comparison (0: skip both)")
+    ap.add_argument("--batch-trimer", type=int, default=0,
+                    help="steps of the twelve-member finite-field batch at the trimer size (0: skip)")
     ap.add_argument("--alpha-steps", type=int, default=10,
                     help="RK4 steps of each of the eight finite-field propagations of the polarisability proxy "
                          "(0: skip)")
@@ -161,7 +277,6 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     from paper_2407_18947_amd import _lib
     from paper_2407_18947_amd.inputs import field_delta_kick, initial_state, make_system
@@ -283,6 +398,12 @@ def main():
                 "rel_err": float(np.abs(mu1[args.split] - ref).max() / np.abs(ref).max()),
                 "max_abs_mu1": float(np.abs(ref).max()),
             }
+    if args.batch_steps > 0:
+        out["batched"] = {"mixed": batched_mixed(codes, args.split, args.batch_steps, dt, amp),
+                          "graph": graph_gain(codes, args.batch_steps, dt, amp)}
+    if args.batch_trimer > 0:
+        out.setdefault("batched", {})["finite_field_trimer"] = batched_finite_field_trimer(
+            codes, args.split, args.batch_trimer, dt, 1200, s, y0)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(s, y0, field[0], args.cpu_blocks)
         cb["cpu_model"] = cpu_model()

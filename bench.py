@@ -26,18 +26,20 @@ sys.path.insert(0, ROOT)
 import torch  # noqa: E402  (device memory and streams of the binding)
 
 METRIC = "RK4 steps/sec (T+Λ RT-CC3) at o=15,v=57; FP32-split vs FP64 at dipole err"
+SIZE_NAMES = {(5, 19): "water-monomer", (10, 38): "water-dimer", (15, 57): "water-trimer",
+              (25, 95): "water-pentamer"}
 PAPER_GPU_DP_TRIMER_STEPS_PER_S = 1.0 / 806.52  # Table 1, GPU-dp, water trimer (P100)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
 PRECISIONS = ("fp64", "fp32", "bf16x3", "bf16x2")
 # real bf16 products per complex multiply-add: 4 real products times the kept slice pairs
 SLICE_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
-# HBM bytes per launch of the build product, from the two counter passes in
+# HBM bytes per launch of the segmented product, from the two counter passes in
 # profiles/build_product_trimer_o15_v57_fp64_traffic.md (FETCH_SIZE, WRITE_SIZE,
 # scaled by a 1 GiB copy).  Valid only for the sources they were measured on.
 MEASURED_TRAFFIC = {
-    "fingerprint": {"kernels.hip": "829a542fcc28d88c", "triples.cpp": "53f9dc0bff870672"},
+    "fingerprint": {"kernels.hip": "559f3ed03e3a5970", "triples.cpp": "c7b054d59856ad75"},
     "config": (15, 57, "fp64"),
-    "bytes_per_launch": 17.330e9 + 8.447e9,
+    "bytes_per_launch": 24.22e9,
 }
 
 
@@ -291,9 +293,12 @@ def main():
     field = field_delta_kick(W + K, dt, amp, "z")
     torch.cuda.set_device(0)
 
+    tune_rows = []
+
     def run(precision):
         """W warm-up steps, then K timed steps; returns (s, dipole series, timing)."""
         ctx = _lib.Context(s, codes[precision])
+        tune_rows.append(_lib.rtcc3_tuning_report(ctx.ctx))
         if args.single_stream:
             ctx.set_option(_lib.RTCC3_OPT_SINGLE_STREAM, 1)
         ctx.set_state(y0)
@@ -344,8 +349,9 @@ def main():
                   "bf16x2": "bf16x2-split triples build GEMMs, f32 other triples GEMMs, f64 elsewhere"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": (f"RT-CC3 T+Lambda, o={o}, v={v}, naux={s.naux}, seeded synthetic water-trimer-sized "
-                         f"integrals (seed {args.seed}), delta kick {amp} a.u. along z, dt={dt}"),
+            "workload": (f"RT-CC3 T+Lambda, o={o}, v={v}, naux={s.naux}, seeded synthetic "
+                         f"{SIZE_NAMES.get((o, v), 'water-cluster')}-sized integrals (seed {args.seed}), "
+                         f"delta kick {amp} a.u. along z, dt={dt}"),
             "o": o, "v": v, "naux": s.naux, "precision": args.precision,
             **({"single_stream": True} if args.single_stream else {}),
         },
@@ -354,7 +360,7 @@ def main():
         # the S intermediate of Y1.
         "roofline": {
             "bound": "mfma",
-            "kernel": "zgemm_kernel<double, false, true, true, 64, true, 0> (t3, lambda3 and S products)"
+            "kernel": "zgemm_seg_f64_kernel<false> (t3, lambda3 and S products)"
             if args.precision == "fp64" else "segmented products (t3, lambda3, S)",
             "achieved": b_achieved,
             "peak": peak,
@@ -364,6 +370,14 @@ def main():
             "launches": int(b_launches),
             "avg_launch_ms": b_ms / max(b_launches, 1),
             "algorithmic_flop_per_launch": b_flop / max(b_launches, 1),
+        },
+        # The K-split autotuner's choices for the main context (rows: M, N, K, batch,
+        # heuristic split, chosen split, heuristic ms, chosen ms).
+        "autotune": {
+            "products_tuned": int(len(tune_rows[0])),
+            "split_changed": int(np.sum(tune_rows[0][:, 4] != tune_rows[0][:, 5])) if len(tune_rows[0]) else 0,
+            "ms_heuristic_sum": float(np.sum(tune_rows[0][:, 6])) if len(tune_rows[0]) else 0.0,
+            "ms_chosen_sum": float(np.sum(tune_rows[0][:, 7])) if len(tune_rows[0]) else 0.0,
         },
         # All triples kernels of a step together, against the same peak.
         "triples_engine": {

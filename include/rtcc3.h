@@ -197,6 +197,11 @@ int rtcc3_zgemm_selftest_noalloc(int M, int N, int K, int precision, const rtcc3
  * K split other than the library's heuristic. */
 int rtcc3_tuning_summary(rtcc3_ctx *ctx, int out[2]);
 
+/* The autotuner's choices: up to max_records rows of 8 doubles into out (host),
+ * each (M, N, K, batch, heuristic split, chosen split, heuristic ms, chosen ms)
+ * of one tuned product; returns the number of tuned products (or EINVAL). */
+int rtcc3_tuning_report(rtcc3_ctx *ctx, double *out, int max_records);
+
 const char *rtcc3_last_error(const rtcc3_ctx *ctx); /* ctx == NULL: last create() error of this thread */
 void rtcc3_destroy(rtcc3_ctx *ctx);
 

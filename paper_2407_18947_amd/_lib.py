@@ -24,7 +24,7 @@ EXPORTS = [
     "rtcc3_create", "rtcc3_set_state", "rtcc3_get_state", "rtcc3_rhs", "rtcc3_rhs_terms", "rtcc3_propagate",
     "rtcc3_propagate_batch",
     "rtcc3_dipole", "rtcc3_set_option", "rtcc3_last_timing", "rtcc3_zgemm_selftest",
-    "rtcc3_zgemm_selftest_noalloc", "rtcc3_tuning_summary", "rtcc3_last_error", "rtcc3_destroy",
+    "rtcc3_zgemm_selftest_noalloc", "rtcc3_tuning_summary", "rtcc3_tuning_report", "rtcc3_last_error", "rtcc3_destroy",
 ]
 
 _lib = None
@@ -56,6 +56,7 @@ def load():
     L.rtcc3_set_option.argtypes = [VP, I, I]
     L.rtcc3_last_timing.argtypes = [VP, VP]
     L.rtcc3_tuning_summary.argtypes = [VP, VP]
+    L.rtcc3_tuning_report.argtypes = [VP, VP, I]
     L.rtcc3_zgemm_selftest.argtypes = [I, I, I, I, VP, VP, VP]
     L.rtcc3_zgemm_selftest_noalloc.argtypes = [I, I, I, I, VP, VP, VP]
     L.rtcc3_last_error.argtypes = [VP]
@@ -178,6 +179,15 @@ def rtcc3_tuning_summary(ctx):
     out = np.zeros(2, dtype=np.int32)
     _check(load().rtcc3_tuning_summary(ctx, _ptr(out)), ctx)
     return int(out[0]), int(out[1])
+
+
+def rtcc3_tuning_report(ctx, max_records=4096):
+    """Rows (M, N, K, batch, heuristic split, chosen split, heuristic ms, chosen ms)."""
+    out = np.zeros((max_records, 8))
+    n = load().rtcc3_tuning_report(ctx, _ptr(out), max_records)
+    if n < 0:
+        _check(n, ctx)
+    return out[: min(n, max_records)]
 
 
 def rtcc3_zgemm_selftest(A, B, precision=RTCC3_FP64):

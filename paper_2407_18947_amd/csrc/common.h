@@ -144,7 +144,13 @@ void gemm(const GemmDesc& d, hipStream_t s);
 // product several times, so it is only done where repeating a product does no
 // harm (the evaluation on the zero state at context set-up).
 struct Tuner;
+struct TuneRecord {
+  int M, N, K, batch, heuristic, chosen;
+  float heuristic_ms, chosen_ms;
+};
 Tuner* tuner_new();
+// the tuned products (up to cap into out); returns how many there are
+int tuner_records(const Tuner* t, TuneRecord* out, int cap);
 void tuner_delete(Tuner* t);
 void tuner_set_tuning(Tuner* t, bool on);
 void tuner_clear(Tuner* t);

@@ -980,6 +980,196 @@ __global__ __launch_bounds__(NT, 3) void zgemm_seg_f64_kernel(GemmDesc d) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 product with both operands read k-fast (A[m][k] and B[k][n] contiguous in
+// k), plain or with B one permuted block (CMB = 4) or a combination of three
+// permuted blocks (CMB = 2): the loading scheme of the segmented kernel above
+// (buffer resources over the batch entry's operands, 32-bit offsets, elements
+// outside the product read as zero beyond the resource, the three-product
+// planes formed at the LDS store).  A thread loads the four A rows and the
+// BN/16 B columns of one k per step; a 64-wide tile has four waves of 32 x 32,
+// a 16-wide one four waves of 16 x 16 stacked along M.
+// ---------------------------------------------------------------------------
+// Three workgroups per CU (168 registers a wave); two for the combined operand,
+// whose three loaded blocks per element need more.
+template <bool ATOMIC, int BN, int CMB>
+__global__ __launch_bounds__(NT, CMB == 2 ? 2 : 3) void zgemm_kb_f64_kernel(GemmDesc d, int ksplit, int kchunk) {
+  constexpr int BK = 16, NB = BN / 16;  // B columns per thread
+  constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16, IB = WM / 16, JB = WN / 16;
+  constexpr int NX = CMB == 2 ? 3 : 1;  // blocks combined into B
+  __shared__ double sA[3][BK][BM + 1];
+  __shared__ double sB[3][BK][BN + 1];
+
+  const int tilesN = (d.N + BN - 1) / BN;
+  const int kz = blockIdx.x % ksplit, tile = blockIdx.x / ksplit;
+  const int tm = tile / tilesN, tn = tile % tilesN;
+  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (b >= d.batch) return;
+  const int kbeg = kz * kchunk, kend = min(d.K, kbeg + kchunk);
+  if (kbeg >= kend) return;
+
+  const cplx *pa, *pb[NX];
+  cplx* C;
+  double wc[NX];
+  if (d.bl) {
+    const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
+    C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
+    pa = d.A + d.cA[0] * I + d.cA[1] * J + d.cA[2] * K + d.cA[3] * n;
+    if constexpr (CMB == 0) {
+      pb[0] = d.B + d.cB[0] * I + d.cB[1] * J + d.cB[2] * K + d.cB[3] * n;
+      wc[0] = 1.0;
+    } else {
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+        pb[x] = d.B + (int64_t)d.part[6 * n + d.comb_perm[x]] * d.comb_stride;
+        wc[x] = CMB == 2 ? d.comb_w[x] : 1.0;
+      }
+    }
+  } else {
+    C = d.C + b * d.sCb;
+    pa = d.A + b * d.sAb;
+    pb[0] = d.B + b * d.sBb;
+    wc[0] = 1.0;
+  }
+  // operand spans in elements (host-checked below 2^27)
+  const int spanA = (int)((d.M / d.M0 - 1) * d.sAm1 + (d.M0 - 1) * d.sAm0 + (d.K / d.K0 - 1) * d.sAk1 +
+                          (d.K0 - 1) * d.sAk0 + 1);
+  const int spanB = (int)((d.K / d.K0 - 1) * d.sBk1 + (d.K0 - 1) * d.sBk0 + (d.N / d.N0 - 1) * d.sBn1 +
+                          (d.N0 - 1) * d.sBn0 + 1);
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)pa, 0, spanA * (int)sizeof(cplx), kRsrcWord3);
+  __amdgpu_buffer_rsrc_t rb[NX];
+#pragma unroll
+  for (int x = 0; x < NX; ++x)
+    rb[x] = __builtin_amdgcn_make_buffer_rsrc((void*)pb[x], 0, spanB * (int)sizeof(cplx), kRsrcWord3);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = BN == 64 ? (wave >> 1) * WM : wave * WM, wn = BN == 64 ? (wave & 1) * WN : 0;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kt = tid & 15, rt = tid >> 4;  // the thread's k, and its first row / column
+  int aoff[4], boff[NB];
+  bool aok[4], bok[NB];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + rt + 16 * r;
+    aok[r] = m < d.M;
+    aoff[r] = aok[r] ? (int)((m / d.M0) * d.sAm1 + (m % d.M0) * d.sAm0) : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    const int nn = n0 + rt + 16 * r;
+    bok[r] = nn < d.N;
+    boff[r] = bok[r] ? (int)((nn / d.N0) * d.sBn1 + (nn % d.N0) * d.sBn0) : 0;
+  }
+  const float invK0 = 1.0f / (float)d.K0;
+
+  cplx av[4], bv[NB][NX];
+  auto load = [&](int k0) {
+    const int k = k0 + kt;
+    int q, r;
+    split_k(k, d.K0, invK0, q, r);
+    const bool kok = k < kend;
+    const int koa = (int)(q * d.sAk1 + r * d.sAk0), kob = (int)(q * d.sBk1 + r * d.sBk0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) av[t] = buf_load_cplx(ra, kok & aok[t], (aoff[t] + koa) * (int)sizeof(cplx));
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+#pragma unroll
+      for (int x = 0; x < NX; ++x)
+        bv[t][x] = buf_load_cplx(rb[x], kok & bok[t], (boff[t] + kob) * (int)sizeof(cplx));
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int m = rt + 16 * t;
+      const double re = av[t].re, im = av[t].im;
+      sA[0][kt][m] = re;
+      sA[1][kt][m] = im;
+      sA[2][kt][m] = re + im;
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      double re = bv[t][0].re, im = bv[t][0].im;
+      if constexpr (NX > 1) {
+        re = wc[0] * re;
+        im = wc[0] * im;
+#pragma unroll
+        for (int x = 1; x < NX; ++x) {
+          re += wc[x] * bv[t][x].re;
+          im += wc[x] * bv[t][x].im;
+        }
+      }
+      const int nn = rt + 16 * t;
+      sB[0][kt][nn] = re;
+      sB[1][kt][nn] = im - re;
+      sB[2][kt][nn] = re + im;
+    }
+  };
+
+  d4 c1[IB][JB], c2[IB][JB], c3[IB][JB];
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j) c1[i][j] = c2[i][j] = c3[i][j] = d4{0, 0, 0, 0};
+
+  const int nsteps = (kend - kbeg + BK - 1) / BK;
+  load(kbeg);
+  stash();
+  __syncthreads();
+  for (int it = 0; it < nsteps; ++it) {
+    load(kbeg + (it + 1) * BK);  // in flight during the MFMAs (masked after the last step)
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4), c16 = lane & 15;
+      double ar[IB], ai[IB], sa[IB], br[JB], db[JB], sb[JB];
+#pragma unroll
+      for (int i = 0; i < IB; ++i) {
+        ar[i] = sA[0][kr][wm + 16 * i + c16];
+        ai[i] = sA[1][kr][wm + 16 * i + c16];
+        sa[i] = sA[2][kr][wm + 16 * i + c16];
+      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        br[j] = sB[0][kr][wn + 16 * j + c16];
+        db[j] = sB[1][kr][wn + 16 * j + c16];
+        sb[j] = sB[2][kr][wn + 16 * j + c16];
+      }
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) c1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], br[j], c1[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) c2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], db[j], c2[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < IB; ++i)
+#pragma unroll
+        for (int j = 0; j < JB; ++j) c3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], sb[j], c3[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    stash();
+    __syncthreads();
+  }
+
+  int64_t co[JB], ro[IB][4];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) co[j] = c_off(n0 + wn + 16 * j + (lane & 15), d.N, d.N0, d.sCn1, d.sCn0);
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ro[i][r] = c_off(m0 + wm + 16 * i + Frag<double>::row(lane, r), d.M, d.M0, d.sCm1, d.sCm0);
+#pragma unroll
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double p1 = c1[i][j][r];
+        put<ATOMIC>(d, C, ro[i][r], co[j], p1 - c3[i][j][r], p1 + c2[i][j][r]);
+      }
+}
+
 __global__ void axpy_kernel(AxpyDesc d, int64_t total) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -1139,8 +1329,42 @@ void launch_gather_gemm(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit,
   }
 }
 
+// Products the k-fast FP64 kernel takes: both operands contiguous in k, no
+// gathered K, column or K segments, and operand spans within its 32-bit offsets.
+bool kb_f64_fits(const GemmDesc& d, bool kfa, bool nfb) {
+  if (!kfa || nfb || d.gk_start || d.ncs || d.nseg) return false;
+  if (!(d.comb_n == 0 || d.comb_n == 1 || (d.comb_n == 3 && d.comb_on == 1))) return false;
+  if (d.M % d.M0 || d.N % d.N0 || d.K % d.K0) return false;
+  const int64_t spanA = (d.M / d.M0 - 1) * d.sAm1 + (d.M0 - 1) * d.sAm0 + (d.K / d.K0 - 1) * d.sAk1 + (d.K0 - 1) * d.sAk0;
+  const int64_t spanB = (d.K / d.K0 - 1) * d.sBk1 + (d.K0 - 1) * d.sBk0 + (d.N / d.N0 - 1) * d.sBn1 + (d.N0 - 1) * d.sBn0;
+  // k is read up to K + 15 before it is masked: keep those offsets below 2^27 elements as well
+  const int64_t over = 16 * (d.sAk1 + d.sAk0 + d.sBk1 + d.sBk0);
+  return spanA >= 0 && spanB >= 0 && spanA + over < (1LL << 27) && spanB + over < (1LL << 27);
+}
+
 template <int MODE, bool ATOMIC>
 void launch_layout(const GemmDesc& d, dim3 grid, hipStream_t s, int ksplit, int kchunk, bool kfa, bool nfb, int bn) {
+  if constexpr (MODE == RTCC3_PREC_FP64) {
+    if (kb_f64_fits(d, kfa, nfb)) {
+      const int cmb = d.comb_n == 0 ? 0 : d.comb_n == 1 ? 4 : 2;
+      if (bn == 16) {
+        if (cmb == 0)
+          hipLaunchKernelGGL((zgemm_kb_f64_kernel<ATOMIC, 16, 0>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+        else if (cmb == 4)
+          hipLaunchKernelGGL((zgemm_kb_f64_kernel<ATOMIC, 16, 4>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+        else
+          hipLaunchKernelGGL((zgemm_kb_f64_kernel<ATOMIC, 16, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+      } else {
+        if (cmb == 0)
+          hipLaunchKernelGGL((zgemm_kb_f64_kernel<ATOMIC, 64, 0>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+        else if (cmb == 4)
+          hipLaunchKernelGGL((zgemm_kb_f64_kernel<ATOMIC, 64, 4>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+        else
+          hipLaunchKernelGGL((zgemm_kb_f64_kernel<ATOMIC, 64, 2>), grid, dim3(NT), 0, s, d, ksplit, kchunk);
+      }
+      return;
+    }
+  }
   if (d.ncs > 0) {
     if constexpr (ATOMIC && (MODE == RTCC3_PREC_FP64 || MODE == RTCC3_PREC_FP32)) {
       typedef typename std::conditional<MODE == RTCC3_PREC_FP64, double, float>::type T;
@@ -1225,6 +1449,7 @@ GemmDesc transposed(const GemmDesc& d) {
 struct Tuner {
   std::unordered_map<uint64_t, int> best;  // descriptor key -> K split
   std::unordered_map<uint64_t, int> heur;  // the heuristic's split for the same products
+  std::unordered_map<uint64_t, TuneRecord> rec;
   bool tuning = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;
 };
@@ -1278,6 +1503,14 @@ void tuner_set_tuning(Tuner* t, bool on) { t->tuning = on; }
 void tuner_clear(Tuner* t) {
   t->best.clear();
   t->heur.clear();
+}
+int tuner_records(const Tuner* t, TuneRecord* out, int cap) {
+  int n = 0;
+  for (auto& kv : t->rec) {
+    if (n < cap && out) out[n] = kv.second;
+    ++n;
+  }
+  return n;
 }
 void tuner_counts(const Tuner* t, int& sites, int& changed) {
   sites = (int)t->best.size();
@@ -1428,7 +1661,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
       for (int64_t ks = kmin; ks <= kmax && ks <= 64; ks *= 2)
         if (ks != ksplit) cand.push_back((int)ks);
       launch(ksplit);  // warm the caches
-      float best_ms = 1e30f;
+      float best_ms = 1e30f, heur_ms = 0.f;
       int best = ksplit;
       for (int ks : cand) {
         float ms = 1e30f;
@@ -1441,6 +1674,7 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
           RTCC3_HIP(hipEventElapsedTime(&t, tu->e0, tu->e1));
           ms = std::min(ms, t);
         }
+        if (ks == ksplit) heur_ms = ms;
         if (ms < 0.97f * best_ms) {  // a new choice must win by more than the noise
           best_ms = ms;
           best = ks;
@@ -1448,10 +1682,11 @@ void gemm(const GemmDesc& d0, hipStream_t s) {
       }
       tu->best[key] = best;
       tu->heur[key] = ksplit;
+      tu->rec[key] = TuneRecord{d.M, d.N, d.K, d.batch, ksplit, best, heur_ms, best_ms};
       ksplit = best;
     } else {
       auto it = tu->best.find(key);
-      if (it != tu->best.end()) ksplit = it->second;
+      if (it != tu->best.end()) ksplit = std::max<int>(it->second, (int)kmin);
     }
   }
   launch(ksplit);

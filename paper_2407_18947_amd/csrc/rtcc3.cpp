@@ -707,6 +707,19 @@ extern "C" int rtcc3_tuning_summary(rtcc3_ctx* c, int out[2]) {
   return RTCC3_OK;
 }
 
+extern "C" int rtcc3_tuning_report(rtcc3_ctx* c, double* out, int max_records) {
+  if (!c || max_records < 0 || (max_records > 0 && !out)) return RTCC3_EINVAL;
+  std::vector<TuneRecord> r((size_t)max_records);
+  const int n = tuner_records(c->tuner, r.data(), max_records);
+  for (int i = 0; i < std::min(n, max_records); ++i) {
+    const TuneRecord& t = r[i];
+    const double row[8] = {(double)t.M, (double)t.N, (double)t.K, (double)t.batch, (double)t.heuristic,
+                           (double)t.chosen, (double)t.heuristic_ms, (double)t.chosen_ms};
+    std::memcpy(out + 8 * i, row, sizeof(row));
+  }
+  return n;
+}
+
 extern "C" const char* rtcc3_last_error(const rtcc3_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 extern "C" void rtcc3_destroy(rtcc3_ctx* c) {

@@ -231,7 +231,7 @@ void Triples::set_window_blocks(Engine& e, int n) {
   RTCC3_HIP(hipStreamSynchronize(e.stream));
   RTCC3_HIP(hipStreamSynchronize(s2_));
   free_windows();
-  for (const char* b : {"tw_W", "tw_Wl", "tw_T", "tw_L", "tw_S"}) e.release(b);
+  for (const char* b : {"tw_T", "tw_L", "tw_S"}) e.release(b);
   wcap_ = n;
   build_windows();
   for (auto& w : rhs_windows_) upload(w);
@@ -286,14 +286,15 @@ void finish_window(Window& w, const std::vector<std::array<int, 3>>& blocks) {
 
 void Triples::build_windows() {
   const int o = d_.o;
-  // Four window buffers of nw blocks each (W for t3 and for lambda3, t3,
-  // lambda3); larger windows mean fewer, larger launches.  Budget: half the
-  // free device memory, at most 48 GiB (of the 288 GB of HBM); when all o^3
-  // blocks fit, one window serves both passes and nothing is built twice.
+  // Two window buffers of nw blocks each (t3 and lambda3, each built and then
+  // symmetrised in place) and S; larger windows mean fewer, larger launches.
+  // Budget: half the free device memory, at most 48 GiB (of the 288 GB of
+  // HBM); when all o^3 blocks fit, one window serves both passes and nothing
+  // is built twice.
   size_t free_b = 0, total_b = 0;
   RTCC3_HIP(hipMemGetInfo(&free_b, &total_b));
   const int64_t budget = std::max<int64_t>((int64_t)1 << 30, std::min<int64_t>((int64_t)48 << 30, (int64_t)(free_b / 2)));
-  int wmax = (int)std::max<int64_t>(6, budget / (4 * 16 * (int64_t)d_.v * d_.v * pad8(d_.v)));
+  int wmax = (int)std::max<int64_t>(6, budget / (16 * (int64_t)d_.v * d_.v * (2 * pad8(d_.v) + o)));
   if (wcap_ > 0) wmax = std::max(6, std::min(wmax, wcap_));
   // ---- RHS windows: canonical triples i <= j <= k with all their orderings
   std::vector<std::array<int, 3>> cur;
@@ -534,8 +535,8 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   const int64_t winlen = (int64_t)max_nw_ * vb;
   // The window buffers first: a buffer's first request zero-fills it on the
   // engine stream, which must come before the fork below.
-  cplx* W = e.tensor("tw_W", {(int64_t)max_nw_, v, v, vp}).p;
-  cplx* Wl = e.tensor("tw_Wl", {(int64_t)max_nw_, v, v, vp}).p;
+  // The builds write W' into T and L, which the symmetrisation then turns
+  // into t3 and lambda3 in place.
   cplx* T = e.tensor("tw_T", {(int64_t)max_nw_, v, v, vp}).p;
   cplx* L = e.tensor("tw_L", {(int64_t)max_nw_, v, v, vp}).p;
   cplx* S = e.tensor("tw_S", {(int64_t)max_nw_, v, v, o}).p;
@@ -595,7 +596,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     seg(g.seg[0], 0, v, t2, {(int64_t)o * v2, v2, 0, 0}, v, 1, gW1, {0, 0, v3, 0}, v2);
     seg(g.seg[1], up16(v), o, gW2, {(int64_t)v * o, 0, (int64_t)o * v * o, 0}, o, 1, t2, {0, (int64_t)o * v2, 0, 0},
         v2);
-    g.C = W;  // C[a][(b,c)] at a*va + b*vp + c
+    g.C = T;  // C[a][(b,c)] at a*va + b*vp + c
     g.sCm0 = va;
     g.N0 = v;
     g.sCn1 = vp;
@@ -608,7 +609,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     build_flop_ += 8.0 * nw * v * v2 * (v + o);
   }
   RTCC3_HIP(hipEventRecord(ev_t3b_, s));
-  launch_sym_cube(W, T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, nullptr, s);
+  launch_sym_cube(T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, nullptr, s);
   RTCC3_HIP(hipEventRecord(ev_t_, s));  // t3 blocks ready
 
   // Contractions run over the blocks this window is responsible for: all of
@@ -658,7 +659,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     seg(g.seg[1], k1, o, gLD, {(int64_t)v * oo, o, 0, 0}, oo, 1, l2, {0, 0, v2, 0}, ov2);
     seg(g.seg[2], k2, v, l2, {0, ov2, v2, 0}, v, 1, gLA, {v3, 0, 0, 0}, v2);
     seg(g.seg[3], k3, v, l2, {ov2, v2, 0, 0}, v, 1, gLB, {0, 0, v3, 0}, v2);
-    g.C = Wl;
+    g.C = L;
     g.sCm0 = va;
     g.N0 = v;
     g.sCn1 = vp;
@@ -679,7 +680,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
-    launch_sym_cube(Wl, L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, &le, s2);
+    launch_sym_cube(L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, &le, s2);
   }
   RTCC3_HIP(hipEventRecord(ev_l_, s2));  // lambda3 blocks ready
   launches_ += 4;

@@ -186,14 +186,21 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
 }
 
 // Tiled P_ijk^abc + denominator for one canonical triple c = (i<=j<=k) per
-// blockIdx.y, one 8x8x8 cube of (a,b,c) per blockIdx.x.  With p_s the six
-// permutations (identity, (12), (23), (13), cyclic, cyclic^2) of positions,
-//   t_c[t] = sum_s W[slot_s][t o p_s] / D(t),   T[slot_s][t o p_s] = t_c[t]
+// blockIdx.y, one 8x8x8 cube of (a,b,c) per blockIdx.x, in place.  With p_s
+// the six permutations (identity, (12), (23), (13), cyclic, cyclic^2) of
+// positions,
+//   t_c[t] = sum_s W[slot_s][t o p_s] / D(t),   W[slot_s][t o p_s] <- t_c[t]
 // where slot_s is the window slot of the ordered triple (i,j,k) o p_s, because
-// t_{sigma(ijk)}^{sigma(abc)} = t_{ijk}^{abc}.  Sources are read and
-// destinations written along their unit-stride index through LDS.  The LDS
-// cube is padded (row strides CB+1 and CB*(CB+1)+1 elements, both odd) so that
-// walking any of its three axes touches distinct banks.
+// t_{sigma(ijk)}^{sigma(abc)} = t_{ijk}^{abc}.  A workgroup reads the six
+// (slot, cube) places it writes, all of them before any write, and the places
+// of different workgroups are disjoint: for distinct i, j, k the six slots
+// differ; when two occupied indices coincide, two slots are one block and the
+// cubes related by swapping the matching virtual positions form one set of
+// places, handled by the workgroup of the cube whose coordinates are ordered
+// there (the others return at once).  Sources are read and destinations
+// written along their unit-stride index through LDS.  The LDS cube is padded
+// (row strides CB+1 and CB*(CB+1)+1 elements, both odd) so that walking any of
+// its three axes touches distinct banks.
 constexpr int CB = 8;
 constexpr int CS1 = CB + 1, CS0 = CB * CS1 + 1;
 __device__ __forceinline__ int cube_at(int t0, int t1, int t2) { return t0 * CS0 + t1 * CS1 + t2; }
@@ -207,8 +214,8 @@ __device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 
 //   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik,
 // evaluated at that source's own occupied and virtual indices.
 template <bool LAM>
-__global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ W, cplx* __restrict__ T,
-                                                         const int* __restrict__ canon, const int* __restrict__ part,
+__global__ __launch_bounds__(256) void sym_cube_kernel(cplx* __restrict__ W, const int* __restrict__ canon,
+                                                         const int* __restrict__ part,
                                                          const double* __restrict__ eps, int o, int v, int vp,
                                                          LamElem le) {
   __shared__ cplx acc[CB * CS0];
@@ -217,7 +224,9 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   const int* sl = part + 6 * n0;
   const int nc = (v + CB - 1) / CB;
   const int cube = blockIdx.x;
-  const int c0 = (cube / (nc * nc)) * CB, c1 = ((cube / nc) % nc) * CB, c2 = (cube % nc) * CB;  // cube corner
+  const int q0 = cube / (nc * nc), q1 = (cube / nc) % nc, q2 = cube % nc;
+  if ((I == J && q0 > q1) || (J == K && q1 > q2)) return;  // another workgroup owns these places
+  const int c0 = q0 * CB, c1 = q1 * CB, c2 = q2 * CB;  // cube corner
   // (selects rather than arrays indexed by the permutation, which would live in scratch memory)
   auto pick = [](int p, int a, int b, int c) { return p == 0 ? a : p == 1 ? b : c; };
   const int64_t vb = (int64_t)v * v * vp;  // block stride; element [X0][X1][X2] at (X0*v + X1)*vp + X2
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(const cplx* __restrict__ 
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
     const int x0 = pick(p0, c0, c1, c2), x1 = pick(p1, c0, c1, c2), x2 = pick(p2, c0, c1, c2);
-    cplx* dst = T + (int64_t)sl[s] * vb;
+    cplx* dst = W + (int64_t)sl[s] * vb;
     for (int e = threadIdx.x; e < CB * CB * CB; e += blockDim.x) {
       const int u0 = e / (CB * CB), u1 = (e / CB) % CB, u2 = e % CB;
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
@@ -381,16 +390,16 @@ __global__ __launch_bounds__(256) void gram_kernel(const cplx* __restrict__ A, c
 }
 }  // namespace
 
-void launch_sym_cube(const cplx* W, cplx* T, const int* canon, int ncanon, const int* part, const double* eps, int o,
-                     int v, int vp, const LamElem* le, hipStream_t s) {
+void launch_sym_cube(cplx* W, const int* canon, int ncanon, const int* part, const double* eps, int o, int v, int vp,
+                     const LamElem* le, hipStream_t s) {
   RTCC3_CHECK(vp >= v, "sym: row stride below v");
   if (ncanon <= 0) return;
   const int nc = (v + CB - 1) / CB;
   const dim3 grid((unsigned)(nc * nc * nc), (unsigned)ncanon);
   if (le) {
-    hipLaunchKernelGGL(sym_cube_kernel<true>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, vp, *le);
+    hipLaunchKernelGGL(sym_cube_kernel<true>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, *le);
   } else {
-    hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, T, canon, part, eps, o, v, vp, LamElem{});
+    hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, LamElem{});
   }
   RTCC3_HIP(hipGetLastError());
 }

@@ -33,8 +33,9 @@
  * Memory.  rtcc3_create allocates every device buffer the context will use (it
  * evaluates the right-hand side once, on the zero state, to size them); no
  * later call allocates device memory, except rtcc3_set_option with
- * RTCC3_OPT_WINDOW_BLOCKS, which replaces the window buffers.  A request that
- * would need more memory after creation fails with RTCC3_ESTATE.
+ * RTCC3_OPT_WINDOW_BLOCKS, which replaces the window buffers, and with
+ * RTCC3_OPT_TANGENT, which adds the derivative buffers.  A request that would
+ * need more memory after creation fails with RTCC3_ESTATE.
  */
 #ifndef RTCC3_H
 #define RTCC3_H
@@ -130,10 +131,50 @@ int rtcc3_propagate_batch(rtcc3_ctx *const *ctxs, int n, int steps, double dt, c
 /* Dipole of the context's current state at field E[3] (host) -> out[3] (host). */
 int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
 
+/* Derivatives along a direction (forward mode; RTCC3_OPT_TANGENT first).  The
+ * right-hand side f(y, E) is a polynomial in the amplitudes and affine in the
+ * field (eq. cc3-rt-t, eq. cc3-rt-l, with h = h0 - mu.E of Sec. 2.2.1), and so
+ * is the dipole (Sec. 2.2.3); every kernel of the evaluation has its
+ * derivative applied beside it (each product C = A B adds A' B + A B').
+ *
+ * rtcc3_rhs_tangent: dy = f(y, E) and dydot = (df/dy) ydot + (df/dE) Edot at
+ * field E[3] with field direction Edot[3] (host), state y_dev and direction
+ * ydot_dev (device, state length, caller-owned; also dy_dev, dydot_dev).
+ * mu, mudot (host [3], may be NULL): the dipole at (y, E) and its derivative
+ * along the same direction.  The context's state is not changed. */
+int rtcc3_rhs_tangent(rtcc3_ctx *ctx, const double E[3], const double Edot[3], const rtcc3_c64 *y_dev,
+                      const rtcc3_c64 *ydot_dev, rtcc3_c64 *dy_dev, rtcc3_c64 *dydot_dev, rtcc3_c64 mu[3],
+                      rtcc3_c64 mudot[3]);
+
+/* rtcc3_propagate_tangent: `steps` RK4 steps as rtcc3_propagate (same field
+ * layout; each step's kernels launched from the host, on the context's
+ * stream only), together with the derivative of the dipole series along a
+ * direction of the inputs:
+ *   field_dot   [(2*steps+1)*3] host: direction of the field samples (may be NULL: zero)
+ *   kappa_dot   direction of a scale of the dipole integrals, mu -> (1 + kappa) mu
+ *               in both the coupling -mu.E and the dipole, taken at kappa = 0
+ *   ydot0       [state length] host: direction of the initial state (may be NULL: zero)
+ *   dipole_out, dipole_dot [(steps+1)*3] host: mu(t_n) and d mu(t_n)/ds (may be NULL)
+ * The state and its derivative advance together (the derivative of each RK4
+ * stage is that of the right-hand side at the stage); rtcc3_get_state_tangent
+ * reads the derivative of the final state.  With field_dot = the field's shape
+ * at unit amplitude, dipole_dot is the derivative of the dipole series with
+ * respect to the field amplitude (at a delta kick of vanishing amplitude, the
+ * linear response whose transform gives the polarisability, Sec. 2.2.1 and 2.2.2).
+ * Returns RTCC3_EDIVERGED if the state, its derivative or a dipole becomes
+ * non-finite (nothing is restored). */
+int rtcc3_propagate_tangent(rtcc3_ctx *ctx, int steps, double dt, const double *field, const double *field_dot,
+                            double kappa_dot, const rtcc3_c64 *ydot0, rtcc3_c64 *dipole_out,
+                            rtcc3_c64 *dipole_dot);
+
+/* Derivative of the context's state after rtcc3_propagate_tangent (zero before
+ * any; layout and y_on_device as rtcc3_get_state). */
+int rtcc3_get_state_tangent(rtcc3_ctx *ctx, rtcc3_c64 *ydot, int y_on_device);
+
 /* Options: RTCC3_OPT_TRIPLES (1 = CC3, 0 = CCSD model), RTCC3_OPT_PRECISION,
  * RTCC3_OPT_WINDOW_BLOCKS: the most ordered occupied triples (i,j,k) whose t3
- * and lambda3 blocks are held at once (4 * 16 * v*v*vp bytes each, vp = v rounded up to
- * a multiple of 8); 0 (default)
+ * and lambda3 blocks are held at once (16 * v*v*(2*vp + o) bytes each, vp = v rounded
+ * up to a multiple of 8, twice that with RTCC3_OPT_TANGENT); 0 (default)
  * sizes the windows from half the free device memory, at most 48 GiB.  Values
  * below 6 count as 6 (a window holds every ordering of a triple), and the
  * windows of the density pass hold whole slabs (i,l,k) of an occupied pair
@@ -155,14 +196,20 @@ int rtcc3_dipole(rtcc3_ctx *ctx, const double E[3], rtcc3_c64 out[3]);
  * for it to matter is chosen by timing the feasible splits once, at creation
  * (on the zero state, one stream); 1 = tune again now, 0 = forget the choices
  * (the library's heuristic then).  The answer depends on it only through the
- * order of atomic additions. */
+ * order of atomic additions.
+ * RTCC3_OPT_TANGENT: 1 = allocate the derivative buffers that rtcc3_rhs_tangent
+ * and rtcc3_propagate_tangent need (a twin of every buffer of the context, so
+ * as much device memory again); these calls return RTCC3_ESTATE without it.
+ * Needs o <= 15 (EINVAL otherwise).  0 is ignored (the buffers stay until
+ * rtcc3_destroy). */
 enum {
   RTCC3_OPT_TRIPLES = 1,
   RTCC3_OPT_PRECISION = 2,
   RTCC3_OPT_WINDOW_BLOCKS = 3,
   RTCC3_OPT_SINGLE_STREAM = 4,
   RTCC3_OPT_GRAPH = 5,
-  RTCC3_OPT_AUTOTUNE = 6
+  RTCC3_OPT_AUTOTUNE = 6,
+  RTCC3_OPT_TANGENT = 7
 };
 int rtcc3_set_option(rtcc3_ctx *ctx, int option, int value);
 

@@ -92,8 +92,15 @@ class Model:
         return cls(s.o, s.v, s.eps, s.B, s.mu)
 
     def h(self, E):
-        """One-electron operator with the dipole coupling V = -mu.E (Sec. 2.2.1)."""
-        E = torch.as_tensor(np.asarray(E, dtype=np.float64))
+        """One-electron operator with the dipole coupling V = -mu.E (Sec. 2.2.1).
+
+        E may be complex (the derivatives below evaluate the equations, which are
+        polynomials in E, at complex fields)."""
+        E = np.asarray(E)
+        if np.iscomplexobj(E):
+            Ec = torch.as_tensor(E.astype(np.complex128))
+            return self.h0.to(C128) - torch.einsum("x,xpq->pq", Ec, self.mu.to(C128))
+        E = torch.as_tensor(E.astype(np.float64))
         return self.h0 - torch.einsum("x,xpq->pq", E, self.mu)
 
     def denom3(self, i, j, k):
@@ -847,3 +854,76 @@ def propagate_field_coupled(m: Model, y0, dt, field, steps=None):
         y = (y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)).detach()
     mus.append(rhs_field_coupled(m, y, field[2 * steps], with_dipole=True)[1])
     return y, torch.stack(mus).detach()
+
+
+# -----------------------------------------------------------------------------
+# Derivatives along a direction (forward mode)
+# -----------------------------------------------------------------------------
+
+def rhs_tangent(m: Model, y, E, ydot, Edot, kdot=0.0, triples="explicit", with_triples=True, npts=16):
+    """The right-hand side and the dipole at (y, E) and their derivatives along
+    the direction (ydot, Edot, kdot), kdot being that of a scale of the dipole
+    integrals, mu -> (1 + kappa) mu in the coupling -mu.E and in the dipole,
+    taken at kappa = 0.
+
+    Along s the right-hand side and the dipole,
+        g(s) = (f, mu)(y + s ydot, (1 + s kdot)(E + s Edot)) * (1, 1 + s kdot),
+    are polynomials (the amplitude equations and the density are polynomial in
+    the amplitudes, and h is linear in the field), so the first Taylor
+    coefficient g'(0) is the discrete Cauchy integral over the npts-th roots of
+    unity, g'(0) = (1/npts) sum_k g(r w^k) / (r w^k), exact (up to rounding) when
+    the degree is below npts + 1.  The radius r scales the direction to a
+    perturbation of 0.1 in its largest component.
+
+    Returns (dy, mu, dy_dot, mu_dot)."""
+    y = torch.as_tensor(np.asarray(y), dtype=C128)
+    ydot = torch.as_tensor(np.asarray(ydot), dtype=C128)
+    E = np.asarray(E, dtype=np.float64)
+    Edot = np.asarray(Edot, dtype=np.float64)
+    size = max(float(ydot.abs().max()) if ydot.numel() else 0.0, float(np.abs(Edot).max()), abs(float(kdot)))
+    if size == 0.0:
+        dy, mu = rhs(m, y, E, triples=triples, with_dipole=True, with_triples=with_triples)
+        return dy, mu, torch.zeros_like(dy), torch.zeros_like(mu)
+    r = 0.1 / size
+    acc_f, acc_mu = 0.0, 0.0
+    for k in range(npts):
+        z = r * np.exp(2j * np.pi * k / npts)
+        Ez = (1.0 + z * kdot) * (E + z * Edot)
+        f, mu = rhs(m, y + z * ydot, Ez, triples=triples, with_dipole=True, with_triples=with_triples)
+        acc_f = acc_f + f / z
+        acc_mu = acc_mu + (1.0 + z * kdot) * mu / z
+    dy, mu = rhs(m, y, E, triples=triples, with_dipole=True, with_triples=with_triples)
+    return dy, mu, acc_f / npts, acc_mu / npts
+
+
+def propagate_tangent(m: Model, y0, dt, field, field_dot=None, kdot=0.0, ydot0=None, steps=None,
+                      triples="explicit", with_triples=True, npts=16):
+    """RK4 of propagate() together with its derivative along a direction of the
+    inputs (field samples field_dot, dipole scale kdot, initial state ydot0):
+    every stage's derivative is that of the right-hand side at the stage, so
+    this is the exact derivative of the discrete propagation.
+
+    Returns (y, ydot, mu[steps+1, 3], mu_dot[steps+1, 3])."""
+    field = np.asarray(field, dtype=np.float64)
+    if steps is None:
+        steps = (field.shape[0] - 1) // 2
+    fdot = np.zeros_like(field) if field_dot is None else np.asarray(field_dot, dtype=np.float64)
+    y = torch.as_tensor(np.asarray(y0), dtype=C128).clone()
+    yd = torch.zeros_like(y) if ydot0 is None else torch.as_tensor(np.asarray(ydot0), dtype=C128).clone()
+    kw = dict(triples=triples, with_triples=with_triples, npts=npts)
+    mus, mds = [], []
+    for n in range(steps):
+        k1, mu, k1d, mud = rhs_tangent(m, y, field[2 * n], yd, fdot[2 * n], kdot, **kw)
+        mus.append(mu)
+        mds.append(mud)
+        k2, _, k2d, _ = rhs_tangent(m, y + 0.5 * dt * k1, field[2 * n + 1], yd + 0.5 * dt * k1d,
+                                    fdot[2 * n + 1], kdot, **kw)
+        k3, _, k3d, _ = rhs_tangent(m, y + 0.5 * dt * k2, field[2 * n + 1], yd + 0.5 * dt * k2d,
+                                    fdot[2 * n + 1], kdot, **kw)
+        k4, _, k4d, _ = rhs_tangent(m, y + dt * k3, field[2 * n + 2], yd + dt * k3d, fdot[2 * n + 2], kdot, **kw)
+        y = y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        yd = yd + (dt / 6.0) * (k1d + 2.0 * k2d + 2.0 * k3d + k4d)
+    _, mu, _, mud = rhs_tangent(m, y, field[2 * steps], yd, fdot[2 * steps], kdot, **kw)
+    mus.append(mu)
+    mds.append(mud)
+    return y, yd, torch.stack(mus), torch.stack(mds)

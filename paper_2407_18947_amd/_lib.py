@@ -18,13 +18,14 @@ LIBPATH = os.path.join(_HERE, "librtcc3.so")
 RTCC3_OK, RTCC3_EINVAL, RTCC3_ENOMEM, RTCC3_EDEVICE, RTCC3_ESTATE, RTCC3_EDIVERGED = 0, -1, -2, -3, -4, -5
 RTCC3_FP64, RTCC3_FP32, RTCC3_BF16X3, RTCC3_BF16X2 = 0, 1, 2, 3
 RTCC3_OPT_TRIPLES, RTCC3_OPT_PRECISION, RTCC3_OPT_WINDOW_BLOCKS, RTCC3_OPT_SINGLE_STREAM = 1, 2, 3, 4
-RTCC3_OPT_GRAPH, RTCC3_OPT_AUTOTUNE = 5, 6
+RTCC3_OPT_GRAPH, RTCC3_OPT_AUTOTUNE, RTCC3_OPT_TANGENT = 5, 6, 7
 
 EXPORTS = [
     "rtcc3_create", "rtcc3_set_state", "rtcc3_get_state", "rtcc3_rhs", "rtcc3_rhs_terms", "rtcc3_propagate",
     "rtcc3_propagate_batch",
     "rtcc3_dipole", "rtcc3_set_option", "rtcc3_last_timing", "rtcc3_zgemm_selftest",
-    "rtcc3_zgemm_selftest_noalloc", "rtcc3_tuning_summary", "rtcc3_tuning_report", "rtcc3_last_error", "rtcc3_destroy",
+    "rtcc3_zgemm_selftest_noalloc", "rtcc3_tuning_summary", "rtcc3_tuning_report", "rtcc3_rhs_tangent",
+    "rtcc3_propagate_tangent", "rtcc3_get_state_tangent", "rtcc3_last_error", "rtcc3_destroy",
 ]
 
 _lib = None
@@ -59,6 +60,9 @@ def load():
     L.rtcc3_tuning_report.argtypes = [VP, VP, I]
     L.rtcc3_zgemm_selftest.argtypes = [I, I, I, I, VP, VP, VP]
     L.rtcc3_zgemm_selftest_noalloc.argtypes = [I, I, I, I, VP, VP, VP]
+    L.rtcc3_rhs_tangent.argtypes = [VP, VP, VP, VP, VP, VP, VP, VP, VP]
+    L.rtcc3_propagate_tangent.argtypes = [VP, I, D, VP, VP, D, VP, VP, VP]
+    L.rtcc3_get_state_tangent.argtypes = [VP, VP, I]
     L.rtcc3_last_error.argtypes = [VP]
     L.rtcc3_last_error.restype = ctypes.c_char_p
     L.rtcc3_destroy.argtypes = [VP]
@@ -169,6 +173,38 @@ def rtcc3_set_option(ctx, option, value):
     _check(load().rtcc3_set_option(ctx, int(option), int(value)), ctx)
 
 
+def rtcc3_rhs_tangent(ctx, E, Edot, y_dev, ydot_dev, dy_dev, dydot_dev):
+    """Fills dy_dev and dydot_dev; returns (mu[3], mudot[3])."""
+    E, Edot = _f64(E), _f64(Edot)
+    mu = np.empty(3, dtype=np.complex128)
+    mudot = np.empty(3, dtype=np.complex128)
+    _check(load().rtcc3_rhs_tangent(ctx, _ptr(E), _ptr(Edot), _ptr(y_dev), _ptr(ydot_dev), _ptr(dy_dev),
+                                    _ptr(dydot_dev), _ptr(mu), _ptr(mudot)), ctx)
+    return mu, mudot
+
+
+def rtcc3_propagate_tangent(ctx, steps, dt, field, field_dot=None, kappa_dot=0.0, ydot0=None):
+    """Returns (mu, mudot), each [(steps+1), 3]."""
+    field = _f64(field)
+    if field.shape != (2 * steps + 1, 3):
+        raise ValueError(f"field must have shape {(2 * steps + 1, 3)}")
+    fd = None if field_dot is None else _f64(field_dot)
+    if fd is not None and fd.shape != field.shape:
+        raise ValueError("field_dot must have the field's shape")
+    yd = None if ydot0 is None else _c128(ydot0)
+    mu = np.empty((steps + 1, 3), dtype=np.complex128)
+    mudot = np.empty((steps + 1, 3), dtype=np.complex128)
+    _check(load().rtcc3_propagate_tangent(ctx, int(steps), float(dt), _ptr(field), _ptr(fd), float(kappa_dot),
+                                          _ptr(yd), _ptr(mu), _ptr(mudot)), ctx)
+    return mu, mudot
+
+
+def rtcc3_get_state_tangent(ctx, n):
+    y = np.empty(n, dtype=np.complex128)
+    _check(load().rtcc3_get_state_tangent(ctx, _ptr(y), 0), ctx)
+    return y
+
+
 def rtcc3_last_timing(ctx):
     out = np.zeros(6)
     _check(load().rtcc3_last_timing(ctx, _ptr(out)), ctx)
@@ -255,6 +291,12 @@ class Context:
 
     def dipole(self, E):
         return rtcc3_dipole(self.ctx, E)
+
+    def propagate_tangent(self, steps, dt, field, field_dot=None, kappa_dot=0.0, ydot0=None):
+        return rtcc3_propagate_tangent(self.ctx, steps, dt, field, field_dot, kappa_dot, ydot0)
+
+    def get_state_tangent(self):
+        return rtcc3_get_state_tangent(self.ctx, self.ylen)
 
     def terms_size(self):
         o, v, n = self.o, self.v, self.n

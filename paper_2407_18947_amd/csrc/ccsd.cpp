@@ -49,8 +49,8 @@ CCSDResult ccsd_forward(Engine& e, const Dims& d, const cplx* y, const View& h, 
   // amplitudes: copies of the state's t1, t2 into tracked buffers
   View t1 = e.tensor("t1", {o, v});
   View t2 = e.tensor("t2", {o, o, v, v});
-  copy(t1.p, y, ov, e.stream);
-  copy(t2.p, y + ov, oovv, e.stream);
+  e.copy(t1.p, y, ov);
+  e.copy(t2.p, y + ov, oovv);
   e.set_requires_grad(t1.buf, want_grad);
   e.set_requires_grad(t2.buf, want_grad);
   if (want_grad) e.tape_begin();
@@ -189,7 +189,7 @@ void ccsd_backward(Engine& e, const Dims& d, const cplx* y, const View& ones_o, 
   // dE/dh~_ii = dE/dF_ii = 1 (occupied i) and dE/dt2 = L.
   e.zero_grads();
   View gR1 = e.grad(r.R1), gR2 = e.grad(r.R2);
-  copy(gR1.p, y + ov + oovv, ov, e.stream);
+  e.copy(gR1.p, y + ov + oovv, ov);
   View l2 = Engine::raw(const_cast<cplx*>(y) + 2 * ov + oovv, {o, o, v, v});
   e.axpy(R(0.5), l2, gR2);
   e.axpy(ONE, ones_o, Engine::diag(blk(e.grad(r.F), 'o', 'o'), 0, 1));

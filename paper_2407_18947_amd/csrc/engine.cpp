@@ -6,11 +6,76 @@
 namespace rtcc3 {
 
 Engine::~Engine() {
-  for (auto& b : bufs_) {
-    if (b.p) (void)hipFree(b.p);
-    if (b.g) (void)hipFree(b.g);
-  }
+  for (auto& b : bufs_)
+    for (cplx* q : {b.p, b.g, b.tp, b.tg})
+      if (q) (void)hipFree(q);
   if (scratch_) (void)hipFree(scratch_);
+}
+
+cplx* Engine::alloc_twin(int64_t n) {
+  cplx* q = nullptr;
+  if (n <= 0) return q;
+  if (sealed_) throw Error(-4, "engine: twin allocated after the context was set up");
+  hipError_t e = hipMalloc(&q, sizeof(cplx) * n);
+  if (e != hipSuccess) throw Error(-2, "engine: out of device memory for a tangent twin");
+  RTCC3_HIP(hipMemsetAsync(q, 0, sizeof(cplx) * n, stream));
+  return q;
+}
+
+void Engine::enable_twins() {
+  if (twins_) return;
+  for (auto& b : bufs_) {
+    if (b.p && !b.tp) b.tp = alloc_twin(b.n);
+    if (b.g && !b.tg) b.tg = alloc_twin(b.n);
+    b.tp_nz = b.tg_nz = false;
+  }
+  twins_ = true;
+}
+
+const Engine::Range* Engine::find(const cplx* p, int64_t* off) const {
+  auto it = ranges_.upper_bound(p);
+  if (it == ranges_.begin()) return nullptr;
+  --it;
+  const int64_t d = p - it->first;
+  if (d < 0 || d >= it->second.n) return nullptr;
+  *off = d;
+  return &it->second;
+}
+
+const cplx* Engine::twin(const cplx* p) const {
+  int64_t off = 0;
+  const Range* r = find(p, &off);
+  if (!r) return nullptr;
+  const Buf& b = bufs_[r->buf];
+  if (r->kind == 0) return b.tp_nz ? b.tp + off : nullptr;
+  return b.tg_nz ? b.tg + off : nullptr;
+}
+
+cplx* Engine::twin_out(const cplx* p) {
+  int64_t off = 0;
+  const Range* r = find(p, &off);
+  RTCC3_CHECK(r != nullptr, "engine: derivative written to memory outside the engine's buffers");
+  Buf& b = bufs_[r->buf];
+  cplx* t = r->kind == 0 ? b.tp : b.tg;
+  RTCC3_CHECK(t != nullptr, "engine: buffer '" + b.name + "' has no tangent twin");
+  (r->kind == 0 ? b.tp_nz : b.tg_nz) = true;
+  return t + off;
+}
+
+void Engine::copy(cplx* dst, const cplx* src, int64_t n) {
+  rtcc3::copy(dst, src, n, stream);
+  if (!tangent_) return;
+  const cplx* st = twin(src);
+  if (st) {
+    rtcc3::copy(twin_out(dst), st, n, stream);
+    return;
+  }
+  int64_t off = 0;
+  const Range* r = find(dst, &off);
+  RTCC3_CHECK(r != nullptr, "engine: copy into memory outside the engine's buffers");
+  Buf& b = bufs_[r->buf];
+  const bool nz = r->kind == 0 ? b.tp_nz : b.tg_nz;
+  if (nz) fill((r->kind == 0 ? b.tp : b.tg) + off, n, cplx{0, 0}, stream);
 }
 
 int Engine::buffer(const std::string& name, int64_t n) {
@@ -27,10 +92,13 @@ int Engine::buffer(const std::string& name, int64_t n) {
     hipError_t e = hipMalloc(&b.p, sizeof(cplx) * n);
     if (e != hipSuccess) throw Error(-2, "engine: out of device memory for '" + name + "'");
     RTCC3_HIP(hipMemsetAsync(b.p, 0, sizeof(cplx) * n, stream));
+    if (twins_) b.tp = alloc_twin(n);
   }
   bufs_.push_back(b);
-  names_[name] = (int)bufs_.size() - 1;
-  return (int)bufs_.size() - 1;
+  const int id = (int)bufs_.size() - 1;
+  names_[name] = id;
+  if (b.p) ranges_[b.p] = Range{n, id, 0};
+  return id;
 }
 
 void Engine::release(const std::string& name) {
@@ -38,9 +106,12 @@ void Engine::release(const std::string& name) {
   if (it == names_.end()) return;
   RTCC3_HIP(hipStreamSynchronize(stream));
   Buf& b = bufs_[it->second];
-  if (b.p) RTCC3_HIP(hipFree(b.p));
-  if (b.g) RTCC3_HIP(hipFree(b.g));
-  b.p = b.g = nullptr;
+  if (b.p) ranges_.erase(b.p);
+  if (b.g) ranges_.erase(b.g);
+  for (cplx* q : {b.p, b.g, b.tp, b.tg})
+    if (q) RTCC3_HIP(hipFree(q));
+  b.p = b.g = b.tp = b.tg = nullptr;
+  b.tp_nz = b.tg_nz = false;
   b.n = 0;
   b.rg = false;
   names_.erase(it);
@@ -92,9 +163,23 @@ void Engine::zero(const View& v) {
   }
   RTCC3_CHECK(contiguous, "engine: zero() needs a contiguous view");
   fill(v.p, v.numel(), cplx{0, 0}, stream);
+  if (!twins_) return;
+  int64_t off = 0;
+  const Range* r = find(v.p, &off);
+  if (!r) return;
+  Buf& b = bufs_[r->buf];
+  bool& nz = r->kind == 0 ? b.tp_nz : b.tg_nz;
+  if (!nz) return;  // already zero
+  fill((r->kind == 0 ? b.tp : b.tg) + off, v.numel(), cplx{0, 0}, stream);
+  if (off == 0 && v.numel() == b.n) nz = false;
 }
 
-void Engine::zero_buffer(int buf) { fill(bufs_[buf].p, bufs_[buf].n, cplx{0, 0}, stream); }
+void Engine::zero_buffer(int buf) {
+  Buf& b = bufs_[buf];
+  fill(b.p, b.n, cplx{0, 0}, stream);
+  if (b.tp_nz) fill(b.tp, b.n, cplx{0, 0}, stream);
+  b.tp_nz = false;
+}
 
 View Engine::slice(View v, int dim, int64_t lo, int64_t hi) {
   RTCC3_CHECK(dim < v.nd && lo >= 0 && hi <= v.sh[dim] && lo <= hi, "engine: bad slice");
@@ -155,6 +240,8 @@ View Engine::grad(const View& v) {
     hipError_t e = hipMalloc(&b.g, sizeof(cplx) * b.n);
     if (e != hipSuccess) throw Error(-2, "engine: out of device memory for a gradient");
     RTCC3_HIP(hipMemsetAsync(b.g, 0, sizeof(cplx) * b.n, stream));
+    ranges_[b.g] = Range{b.n, v.buf, 1};
+    if (twins_) b.tg = alloc_twin(b.n);
   }
   View g = v;
   g.p = b.g + v.off;
@@ -169,10 +256,31 @@ void Engine::tape_begin() {
 
 void Engine::zero_grads() {
   for (auto& b : bufs_)
-    if (b.rg && b.g) fill(b.g, b.n, cplx{0, 0}, stream);
+    if (b.rg && b.g) {
+      fill(b.g, b.n, cplx{0, 0}, stream);
+      if (b.tg_nz) fill(b.tg, b.n, cplx{0, 0}, stream);
+      b.tg_nz = false;
+    }
 }
 
 void Engine::axpy(cplx alpha, const View& X, const View& Y) {
+  axpy_exec(alpha, X, Y);
+  if (tangent_) {
+    const cplx* xt = twin(X.p);
+    if (xt) {
+      View Xt = X, Yt = Y;
+      Xt.p = const_cast<cplx*>(xt);
+      Yt.p = twin_out(Y.p);
+      axpy_exec(alpha, Xt, Yt);
+    }
+  }
+  if (recording_ && requires_grad(X.buf)) {
+    if (Y.buf >= 0) bufs_[Y.buf].rg = true;
+    tape_.push_back(Op{1, "", alpha, X, View(), Y});
+  }
+}
+
+void Engine::axpy_exec(cplx alpha, const View& X, const View& Y) {
   RTCC3_CHECK(X.nd == Y.nd, "engine: axpy rank mismatch");
   AxpyDesc d;
   d.nd = X.nd;
@@ -186,14 +294,30 @@ void Engine::axpy(cplx alpha, const View& X, const View& Y) {
   d.Y = Y.p;
   d.alpha = alpha;
   axpy_strided(d, stream);
-  if (recording_ && requires_grad(X.buf)) {
-    if (Y.buf >= 0) bufs_[Y.buf].rg = true;
-    tape_.push_back(Op{1, "", alpha, X, View(), Y});
+}
+
+void Engine::einsum_dual(const std::string& spec, cplx alpha, const View& A, const View& B, const View& C) {
+  // the twins of the inputs are looked up before C's is marked written
+  const cplx* at = tangent_ ? twin(A.p) : nullptr;
+  const cplx* bt = tangent_ ? twin(B.p) : nullptr;
+  einsum_exec(spec, alpha, A, B, C);
+  if (!at && !bt) return;
+  View Ct = C;
+  Ct.p = twin_out(C.p);
+  if (at) {
+    View At = A;
+    At.p = const_cast<cplx*>(at);
+    einsum_exec(spec, alpha, At, B, Ct);
+  }
+  if (bt) {
+    View Bt = B;
+    Bt.p = const_cast<cplx*>(bt);
+    einsum_exec(spec, alpha, A, Bt, Ct);
   }
 }
 
 void Engine::einsum(const char* spec, cplx alpha, const View& A, const View& B, const View& C) {
-  einsum_exec(spec, alpha, A, B, C);
+  einsum_dual(spec, alpha, A, B, C);
   if (recording_ && (requires_grad(A.buf) || requires_grad(B.buf))) {
     if (C.buf >= 0) bufs_[C.buf].rg = true;
     tape_.push_back(Op{0, spec, alpha, A, B, C});
@@ -213,8 +337,8 @@ void Engine::backward() {
     const std::string& s = op.spec;
     const size_t c1 = s.find(','), c2 = s.find("->");
     const std::string sa = s.substr(0, c1), sb = s.substr(c1 + 1, c2 - c1 - 1), sc = s.substr(c2 + 2);
-    if (requires_grad(op.A.buf)) einsum_exec(sc + "," + sb + "->" + sa, op.alpha, gC, op.B, grad(op.A));
-    if (requires_grad(op.B.buf)) einsum_exec(sa + "," + sc + "->" + sb, op.alpha, op.A, gC, grad(op.B));
+    if (requires_grad(op.A.buf)) einsum_dual(sc + "," + sb + "->" + sa, op.alpha, gC, op.B, grad(op.A));
+    if (requires_grad(op.B.buf)) einsum_dual(sa + "," + sc + "->" + sb, op.alpha, op.A, gC, grad(op.B));
   }
 }
 

@@ -76,6 +76,29 @@ class Engine {
   void zero_grads();
   void backward();
 
+  // Tangent (forward) mode.  Once twins are enabled every buffer and every
+  // gradient has a twin of its size, meant to hold its derivative along one
+  // direction.  While tangent mode is on, each operation also applies its
+  // derivative: einsum C += a A.B adds a (A'.B + A.B') to C', axpy Y += a X
+  // adds a X' to Y', zero() clears the twin, copy() copies it, and the reverse
+  // sweep differentiates its own operations the same way, so the twins of the
+  // gradients become the derivatives of the gradients.  A twin is looked up
+  // by address (any pointer into a buffer or gradient).  A twin never written
+  // since it was last cleared is known to be zero (constants) and skipped.
+  void enable_twins();
+  bool twins() const { return twins_; }
+  void set_tangent(bool on) { tangent_ = on && twins_; }
+  bool tangent() const { return tangent_; }
+  // Twin of the element at p for reading: nullptr when it is zero (or p lies
+  // outside every buffer).
+  const cplx* twin(const cplx* p) const;
+  // Twin of the element at p for writing (from then on it is not known to be
+  // zero); p must lie in a buffer or gradient.
+  cplx* twin_out(const cplx* p);
+  // dst[0..n) = src[0..n), with the twins when tangent mode is on (a zero twin
+  // of src clears that of dst).
+  void copy(cplx* dst, const cplx* src, int64_t n);
+
  private:
   struct Buf {
     std::string name;
@@ -83,7 +106,22 @@ class Engine {
     cplx* g = nullptr;
     int64_t n = 0;
     bool rg = false;
+    cplx* tp = nullptr;  // twin of p
+    cplx* tg = nullptr;  // twin of g
+    bool tp_nz = false, tg_nz = false;  // twin written since it was last cleared
   };
+  // address range of a buffer (kind 0) or gradient (kind 1)
+  struct Range {
+    int64_t n;
+    int buf;
+    int kind;
+  };
+  std::map<const cplx*, Range> ranges_;
+  bool twins_ = false, tangent_ = false;
+  const Range* find(const cplx* p, int64_t* off) const;
+  cplx* alloc_twin(int64_t n);
+  void einsum_dual(const std::string& spec, cplx alpha, const View& A, const View& B, const View& C);
+  void axpy_exec(cplx alpha, const View& X, const View& Y);
   struct Op {
     int kind;  // 0 einsum, 1 axpy
     std::string spec;

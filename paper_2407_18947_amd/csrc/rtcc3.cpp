@@ -44,6 +44,10 @@ struct rtcc3_ctx {
   hipStream_t side_stream = nullptr;
   int single_stream = 0;
   hipEvent_t ev_side1 = nullptr;
+  // derivative buffers (RTCC3_OPT_TANGENT): the engine's twins, and
+  int tangent_ready = 0;
+  cplx* zero_nn = nullptr;      // a zero n x n matrix (h0 of the field derivative of h)
+  cplx* mu_dot_out = nullptr;   // derivative of the dipole, device [3]
 };
 
 namespace {
@@ -81,11 +85,13 @@ View sub(cplx* p, int64_t off, std::vector<int64_t> shape) { return Engine::raw(
 struct FieldRef {
   const double* host = nullptr;
   const double* dev = nullptr;
+  const double* dot = nullptr;  // host direction of the field (tangent mode)
 };
 
 struct TermsOut {
   cplx* terms = nullptr;    // optional rtcc3_rhs_terms layout
   cplx* mu = nullptr;       // optional dipole (device, 3)
+  cplx* mu_dot = nullptr;   // optional derivative of the dipole (device, 3; tangent mode)
   bool mu_at_step = false;  // dipole into the propagation's series at the device step counter
 };
 
@@ -98,6 +104,10 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
   TunerScope tuned(c->tuner);
   // h = h0 - sum_x E_x mu^x
   build_h(c->h.p, c->h0.p, c->mu.p, n * n, E.dev, E.host, c->stream);
+  if (e.tangent()) {  // h' = -sum_x Edot_x mu^x
+    RTCC3_CHECK(E.dot != nullptr, "tangent: field direction missing");
+    build_h(e.twin_out(c->h.p), c->zero_nn, c->mu.p, n * n, nullptr, E.dot, c->stream);
+  }
   CCSDResult r = ccsd_forward(e, d, y, c->h, c->B, c->I, c->ones_o);
   ccsd_residual(e, d, r);
   const bool want_density = t.terms || t.mu || t.mu_at_step;
@@ -125,7 +135,7 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
   }
 
   if (dy) {
-    fill(dy, c->ylen, cplx{0, 0}, c->stream);
+    e.zero(Engine::raw(dy, {c->ylen}));
     View dt1 = sub(dy, 0, {o, v}), dt2 = sub(dy, ov, {o, o, v, v});
     View dl1 = sub(dy, ov + oovv, {o, v}), dl2 = sub(dy, 2 * ov + oovv, {o, o, v, v});
     e.axpy(C(0, -1), r.R1, dt1);
@@ -162,6 +172,13 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
     e.zero(m3);
     e.einsum("pq,xpq->x", ONE, D, mut, m3);
     if (t.mu) copy(t.mu, m3.p, 3, c->stream);
+    if (t.mu_dot) {
+      const cplx* m3t = e.twin(m3.p);
+      if (m3t)
+        copy(t.mu_dot, m3t, 3, c->stream);
+      else
+        fill(t.mu_dot, 3, cplx{0, 0}, c->stream);
+    }
     if (t.mu_at_step) store_dipole(c->mus, m3.p, c->pst, c->stream);
     if (t.terms) {
       cplx* p = t.terms;
@@ -379,6 +396,23 @@ struct Runner {
     for (auto& z : mh)
       if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(c, RTCC3_EDIVERGED, "dipole became non-finite");
     return RTCC3_OK;
+  }
+};
+
+// Tangent mode for one call: every kernel on the context's stream (the
+// derivative launches follow their products in order), restored afterwards.
+struct TangentScope {
+  rtcc3_ctx* c;
+  int single;
+  explicit TangentScope(rtcc3_ctx* cc) : c(cc), single(cc->single_stream) {
+    c->single_stream = 1;
+    c->tri->set_single_stream(true);
+    c->e->set_tangent(true);
+  }
+  ~TangentScope() {
+    c->e->set_tangent(false);
+    c->single_stream = single;
+    c->tri->set_single_stream(single != 0);
   }
 };
 
@@ -636,6 +670,137 @@ extern "C" int rtcc3_propagate_batch(rtcc3_ctx* const* ctxs, int n, int steps, d
   return rc;
 }
 
+extern "C" int rtcc3_rhs_tangent(rtcc3_ctx* c, const double E[3], const double Edot[3], const rtcc3_c64* y_dev,
+                                 const rtcc3_c64* ydot_dev, rtcc3_c64* dy_dev, rtcc3_c64* dydot_dev, rtcc3_c64 mu[3],
+                                 rtcc3_c64 mudot[3]) {
+  if (!c) return RTCC3_EINVAL;
+  if (!c->tangent_ready) return fail(c, RTCC3_ESTATE, "derivative buffers not allocated (RTCC3_OPT_TANGENT)");
+  if (!field_ok(E) || !field_ok(Edot)) return fail(c, RTCC3_EINVAL, "field and its direction must be 3 finite numbers");
+  if (!y_dev || !ydot_dev || !dy_dev || !dydot_dev) return fail(c, RTCC3_EINVAL, "NULL state pointer");
+  return guarded(c, [&]() -> int {
+    Engine& e = *c->e;
+    const int64_t L = c->ylen;
+    TangentScope ts(c);
+    // the state and its direction into the context's stage buffer and its twin
+    RTCC3_HIP(hipMemcpyAsync(c->ytmp, y_dev, sizeof(cplx) * L, hipMemcpyDeviceToDevice, c->stream));
+    RTCC3_HIP(hipMemcpyAsync(e.twin_out(c->ytmp), ydot_dev, sizeof(cplx) * L, hipMemcpyDeviceToDevice, c->stream));
+    TermsOut t;
+    t.mu = c->mu_out;
+    t.mu_dot = c->mu_dot_out;
+    rhs_impl(c, FieldRef{E, nullptr, Edot}, c->ytmp, c->k, t, c->with_triples != 0);
+    RTCC3_HIP(hipMemcpyAsync(dy_dev, c->k, sizeof(cplx) * L, hipMemcpyDeviceToDevice, c->stream));
+    const cplx* kt = e.twin(c->k);
+    if (kt)
+      RTCC3_HIP(hipMemcpyAsync(dydot_dev, kt, sizeof(cplx) * L, hipMemcpyDeviceToDevice, c->stream));
+    else
+      RTCC3_HIP(hipMemsetAsync(dydot_dev, 0, sizeof(cplx) * L, c->stream));
+    if (mu) RTCC3_HIP(hipMemcpyAsync(mu, c->mu_out, sizeof(cplx) * 3, hipMemcpyDeviceToHost, c->stream));
+    if (mudot) RTCC3_HIP(hipMemcpyAsync(mudot, c->mu_dot_out, sizeof(cplx) * 3, hipMemcpyDeviceToHost, c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    c->tri->fold_timing();
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_propagate_tangent(rtcc3_ctx* c, int steps, double dt, const double* field,
+                                       const double* field_dot, double kappa_dot, const rtcc3_c64* ydot0,
+                                       rtcc3_c64* dipole_out, rtcc3_c64* dipole_dot) {
+  if (!c) return RTCC3_EINVAL;
+  if (!c->tangent_ready) return fail(c, RTCC3_ESTATE, "derivative buffers not allocated (RTCC3_OPT_TANGENT)");
+  if (int rc = check_propagate_args(c, steps, dt, field)) return rc;
+  const int64_t nf = (int64_t)(2 * steps + 1) * 3;
+  if (field_dot && !finite(field_dot, nf)) return fail(c, RTCC3_EINVAL, "non-finite field direction");
+  if (!std::isfinite(kappa_dot)) return fail(c, RTCC3_EINVAL, "non-finite kappa_dot");
+  if (ydot0 && !finite((const double*)ydot0, 2 * c->ylen)) return fail(c, RTCC3_EINVAL, "non-finite state direction");
+  return guarded(c, [&]() -> int {
+    Engine& e = *c->e;
+    const int64_t L = c->ylen;
+    const bool tri = c->with_triples != 0;
+    TangentScope ts(c);
+    cplx* yt = e.twin_out(c->y);
+    if (ydot0)
+      RTCC3_HIP(hipMemcpyAsync(yt, ydot0, sizeof(cplx) * L, hipMemcpyHostToDevice, c->stream));
+    else
+      fill(yt, L, cplx{0, 0}, c->stream);
+    // the direction of the field that h sees: d/ds of (1 + kappa) E at kappa = 0
+    std::vector<double> fd((size_t)nf);
+    for (int64_t q = 0; q < nf; ++q) fd[q] = (field_dot ? field_dot[q] : 0.0) + kappa_dot * field[q];
+    std::vector<cplx> mh((size_t)(steps + 1) * 3), mdh((size_t)(steps + 1) * 3);
+    View YT = Engine::raw(c->ytmp, {L}), K = Engine::raw(c->k, {L}), A = Engine::raw(c->acc, {L}),
+         Y = Engine::raw(c->y, {L});
+    auto sample = [&](int k) { return FieldRef{field + 3 * (size_t)k, nullptr, fd.data() + 3 * (size_t)k}; };
+    auto dipoles = [&](int step) {
+      RTCC3_HIP(hipMemcpyAsync(mh.data() + 3 * (size_t)step, c->mu_out, sizeof(cplx) * 3, hipMemcpyDeviceToHost,
+                               c->stream));
+      RTCC3_HIP(hipMemcpyAsync(mdh.data() + 3 * (size_t)step, c->mu_dot_out, sizeof(cplx) * 3,
+                               hipMemcpyDeviceToHost, c->stream));
+    };
+    TermsOut t;
+    t.mu = c->mu_out;
+    t.mu_dot = c->mu_dot_out;
+    RTCC3_HIP(hipEventRecord(c->ev0, c->stream));
+    for (int n = 0; n < steps; ++n) {
+      rhs_impl(c, sample(2 * n), c->y, c->k, t, tri);  // k1 (and mu(t_n))
+      dipoles(n);
+      e.copy(c->acc, c->k, L);
+      e.copy(c->ytmp, c->y, L);
+      e.axpy(C(0.5 * dt), K, YT);
+      rhs_impl(c, sample(2 * n + 1), c->ytmp, c->k, TermsOut{}, tri);  // k2
+      e.axpy(C(2.0), K, A);
+      e.copy(c->ytmp, c->y, L);
+      e.axpy(C(0.5 * dt), K, YT);
+      rhs_impl(c, sample(2 * n + 1), c->ytmp, c->k, TermsOut{}, tri);  // k3
+      e.axpy(C(2.0), K, A);
+      e.copy(c->ytmp, c->y, L);
+      e.axpy(C(dt), K, YT);
+      rhs_impl(c, sample(2 * n + 2), c->ytmp, c->k, TermsOut{}, tri);  // k4
+      e.axpy(ONE, K, A);
+      e.axpy(C(dt / 6.0), A, Y);
+    }
+    rhs_impl(c, sample(2 * steps), c->y, nullptr, t, tri);
+    dipoles(steps);
+    RTCC3_HIP(hipEventRecord(c->ev1, c->stream));
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    RTCC3_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms[0] = ms;
+    c->tri->fold_timing();
+    c->tri->timing(c->last_ms[1], c->last_ms[2]);
+    c->tri->build_timing(c->last_ms[3], c->last_ms[4], c->last_ms[5]);
+    // the dipole operator itself scales with 1 + kappa
+    for (size_t q = 0; q < mh.size(); ++q) {
+      mdh[q].re += kappa_dot * mh[q].re;
+      mdh[q].im += kappa_dot * mh[q].im;
+    }
+    if (dipole_out) std::memcpy(dipole_out, mh.data(), sizeof(cplx) * mh.size());
+    if (dipole_dot) std::memcpy(dipole_dot, mdh.data(), sizeof(cplx) * mdh.size());
+    for (size_t q = 0; q < mh.size(); ++q)
+      if (!std::isfinite(mh[q].re) || !std::isfinite(mh[q].im) || !std::isfinite(mdh[q].re) ||
+          !std::isfinite(mdh[q].im))
+        return fail(c, RTCC3_EDIVERGED, "dipole or its derivative became non-finite");
+    return RTCC3_OK;
+  });
+}
+
+extern "C" int rtcc3_get_state_tangent(rtcc3_ctx* c, rtcc3_c64* ydot, int y_on_device) {
+  if (!c) return RTCC3_EINVAL;
+  if (!ydot) return fail(c, RTCC3_EINVAL, "ydot is NULL");
+  if (!c->tangent_ready) return fail(c, RTCC3_ESTATE, "derivative buffers not allocated (RTCC3_OPT_TANGENT)");
+  return guarded(c, [&]() -> int {
+    const cplx* yt = c->e->twin(c->y);
+    const hipMemcpyKind kind = y_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (yt) {
+      RTCC3_HIP(hipMemcpyAsync(ydot, yt, sizeof(cplx) * c->ylen, kind, c->stream));
+    } else if (y_on_device) {
+      RTCC3_HIP(hipMemsetAsync(ydot, 0, sizeof(cplx) * c->ylen, c->stream));
+    } else {
+      std::memset(ydot, 0, sizeof(cplx) * c->ylen);
+    }
+    RTCC3_HIP(hipStreamSynchronize(c->stream));
+    return RTCC3_OK;
+  });
+}
+
 extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
   if (!c) return RTCC3_EINVAL;
   if (option == RTCC3_OPT_TRIPLES) {
@@ -673,6 +838,40 @@ extern "C" int rtcc3_set_option(rtcc3_ctx* c, int option, int value) {
       RTCC3_HIP(hipStreamSynchronize(c->side_stream));
       c->single_stream = value ? 1 : 0;
       c->tri->set_single_stream(value != 0);
+      return RTCC3_OK;
+    });
+  }
+  if (option == RTCC3_OPT_TANGENT) {
+    if (!value || c->tangent_ready) return RTCC3_OK;
+    if (c->d.o > 15) return fail(c, RTCC3_EINVAL, "derivatives need o <= 15");
+    return guarded(c, [&]() -> int {
+      RTCC3_HIP(hipStreamSynchronize(c->side_stream));
+      drop_graph(c);
+      Engine& e = *c->e;
+      e.seal(false);
+      const int64_t n = c->d.n;
+      c->zero_nn = e.tensor("zero_nn", {n, n}).p;
+      c->mu_dot_out = e.tensor("mu_dot_out", {3}).p;
+      e.enable_twins();
+      // one derivative evaluation of each kind on the zero state and direction,
+      // so that nothing is allocated later
+      static const double E0[3] = {0.0, 0.0, 0.0};
+      std::vector<cplx> keep((size_t)c->ylen);
+      RTCC3_HIP(hipMemcpy(keep.data(), c->y, sizeof(cplx) * keep.size(), hipMemcpyDeviceToHost));
+      fill(c->y, c->ylen, cplx{0, 0}, c->stream);
+      {
+        TangentScope ts(c);
+        TermsOut t;
+        t.mu = c->mu_out;
+        t.mu_dot = c->mu_dot_out;
+        rhs_impl(c, FieldRef{E0, nullptr, E0}, c->y, c->k, t, true);
+        rhs_impl(c, FieldRef{E0, nullptr, E0}, c->y, c->k, TermsOut{}, true);
+      }
+      RTCC3_HIP(hipStreamSynchronize(c->stream));
+      RTCC3_HIP(hipMemcpy(c->y, keep.data(), sizeof(cplx) * keep.size(), hipMemcpyHostToDevice));
+      c->tri->reset_timing();
+      e.seal(true);
+      c->tangent_ready = 1;
       return RTCC3_OK;
     });
   }

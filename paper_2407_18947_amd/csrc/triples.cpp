@@ -164,6 +164,161 @@ void checked_colseg_gemm(const GemmDesc& g, const int* bl_host, int64_t lenA, co
   gemm(g, s);
 }
 
+// ---------------------------------------------------------------------------
+// Derivatives of the products (tangent mode of the engine): a product
+// C (+)= alpha A B adds alpha (A' B + A B') to C', with the twins of the
+// operands and of C from the engine.  An operand whose twin is zero adds no
+// launch.  A store-mode product stores its first derivative launch and
+// accumulates the others; if every twin is zero it clears C' instead.
+// ---------------------------------------------------------------------------
+
+void tangent_gemm(Engine& e, const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC,
+                  hipStream_t s) {
+  const cplx* at = e.twin(g.A);
+  const cplx* bt = e.twin(g.B);
+  RTCC3_CHECK(!g.store, "triples: derivative of a plain store-mode product");
+  if (!at && !bt) return;
+  cplx* ct = e.twin_out(g.C);
+  for (int q = 0; q < 2; ++q) {
+    const cplx* x = q == 0 ? at : bt;
+    if (!x) continue;
+    GemmDesc h = g;
+    (q == 0 ? h.A : h.B) = x;
+    h.C = ct;
+    checked_gemm(h, bl_host, lenA, lenB, lenC, s);
+  }
+}
+
+void tangent_gather(Engine& e, const GemmDesc& g, const Groups& gr, int64_t lenA, int64_t lenB, int64_t lenC,
+                    hipStream_t s) {
+  const cplx* at = e.twin(g.A);
+  const cplx* bt = e.twin(g.B);
+  if (!at && !bt) return;
+  cplx* ct = e.twin_out(g.C);
+  for (int q = 0; q < 2; ++q) {
+    const cplx* x = q == 0 ? at : bt;
+    if (!x) continue;
+    GemmDesc h = g;
+    (q == 0 ? h.A : h.B) = x;
+    h.C = ct;
+    checked_gather_gemm(h, gr, lenA, lenB, lenC, s);
+  }
+}
+
+void tangent_seg(Engine& e, const GemmDesc& g, const int* bl_host, const int64_t* lenA, const int64_t* lenB,
+                 int64_t lenC, hipStream_t s) {
+  struct Term {
+    GemmDesc::Seg sg;
+    int64_t la, lb;
+  };
+  std::vector<Term> terms;
+  for (int t = 0; t < g.nseg; ++t) {
+    const cplx* at = e.twin(g.seg[t].A);
+    const cplx* bt = e.twin(g.seg[t].B);
+    if (at) {
+      terms.push_back(Term{g.seg[t], lenA[t], lenB[t]});
+      terms.back().sg.A = at;
+    }
+    if (bt) {
+      terms.push_back(Term{g.seg[t], lenA[t], lenB[t]});
+      terms.back().sg.B = bt;
+    }
+  }
+  cplx* ct = e.twin_out(g.C);
+  if (terms.empty()) {
+    if (g.store) fill(ct, lenC, cplx{0, 0}, s);
+    return;
+  }
+  for (size_t p0 = 0; p0 < terms.size(); p0 += 4) {
+    GemmDesc h = g;
+    h.C = ct;
+    h.nseg = (int)std::min<size_t>(4, terms.size() - p0);
+    int64_t la[4], lb[4];
+    int k0 = 0;
+    for (int q = 0; q < h.nseg; ++q) {
+      h.seg[q] = terms[p0 + q].sg;
+      h.seg[q].k0 = k0;  // segments start at multiples of 16
+      la[q] = terms[p0 + q].la;
+      lb[q] = terms[p0 + q].lb;
+      if (q + 1 < h.nseg) k0 += (h.seg[q].len + 15) / 16 * 16;
+    }
+    h.K = h.K0 = k0 + h.seg[h.nseg - 1].len;
+    if (p0 > 0 || !g.store) {
+      h.store = 0;
+      h.atomic = 1;
+    }
+    checked_seg_gemm(h, bl_host, la, lb, lenC, s);
+  }
+}
+
+void tangent_colseg(Engine& e, const GemmDesc& g, const int* bl_host, int64_t lenA, const int64_t* lenB,
+                    const int64_t* lenC, hipStream_t s) {
+  const cplx* at = e.twin(g.A);
+  if (at) {  // A' with every segment's B (and tail)
+    GemmDesc h = g;
+    h.A = at;
+    for (int t = 0; t < g.ncs; ++t) {
+      h.cs[t].C = e.twin_out(g.cs[t].C);
+      if (g.cs[t].tB) h.cs[t].tC = e.twin_out(g.cs[t].tC);
+    }
+    checked_colseg_gemm(h, bl_host, lenA, lenB, lenC, s);
+  }
+  // A with the segments' B' (and tails'); a segment whose B' is zero but whose
+  // tail's is not runs with a zero scale
+  GemmDesc h = g;
+  int64_t lb[8] = {0}, lc[8] = {0};
+  int ns = 0;
+  for (int t = 0; t < g.ncs; ++t) {
+    const GemmDesc::ColSeg& c = g.cs[t];
+    const cplx* bt = e.twin(c.B);
+    const cplx* tbt = c.tB ? e.twin(c.tB) : nullptr;
+    if (!bt && !tbt) continue;
+    GemmDesc::ColSeg q = c;
+    if (bt)
+      q.B = bt;
+    else
+      q.alpha = cplx{0, 0};
+    q.C = e.twin_out(c.C);
+    if (c.tB) {
+      if (tbt)
+        q.tB = tbt;
+      else
+        q.talpha = cplx{0, 0};
+      q.tC = e.twin_out(c.tC);
+    }
+    h.cs[ns] = q;
+    lb[ns] = lenB[t];
+    lc[ns] = lenC[t];
+    lb[4 + ns] = lenB[4 + t];
+    lc[4 + ns] = lenC[4 + t];
+    ++ns;
+  }
+  if (ns == 0) return;
+  h.ncs = ns;
+  h.N = h.N0 = 16 * ns;
+  checked_colseg_gemm(h, bl_host, lenA, lb, lc, s);
+}
+
+// The products with their derivatives in tangent mode.
+void prod(Engine& e, const GemmDesc& g, const int* bl_host, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
+  checked_gemm(g, bl_host, lenA, lenB, lenC, s);
+  if (e.tangent()) tangent_gemm(e, g, bl_host, lenA, lenB, lenC, s);
+}
+void prod_gather(Engine& e, GemmDesc& g, const Groups& gr, int64_t lenA, int64_t lenB, int64_t lenC, hipStream_t s) {
+  checked_gather_gemm(g, gr, lenA, lenB, lenC, s);
+  if (e.tangent()) tangent_gather(e, g, gr, lenA, lenB, lenC, s);
+}
+void prod_seg(Engine& e, const GemmDesc& g, const int* bl_host, const int64_t* lenA, const int64_t* lenB,
+              int64_t lenC, hipStream_t s) {
+  checked_seg_gemm(g, bl_host, lenA, lenB, lenC, s);
+  if (e.tangent()) tangent_seg(e, g, bl_host, lenA, lenB, lenC, s);
+}
+void prod_colseg(Engine& e, const GemmDesc& g, const int* bl_host, int64_t lenA, const int64_t* lenB,
+                 const int64_t* lenC, hipStream_t s) {
+  checked_colseg_gemm(g, bl_host, lenA, lenB, lenC, s);
+  if (e.tangent()) tangent_colseg(e, g, bl_host, lenA, lenB, lenC, s);
+}
+
 // The innermost index of a window block padded to a multiple of 8.
 int pad8(int v) { return (v + 7) / 8 * 8; }
 
@@ -604,12 +759,14 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, vb);
     const int64_t lA[2] = {lT2, lOOOV}, lB[2] = {lOVVV_, lT2};
     build_event(s);
-    checked_seg_gemm(g, blh, lA, lB, winlen, s);
+    prod_seg(e, g, blh, lA, lB, winlen, s);
     build_event(s);
     build_flop_ += 8.0 * nw * v * v2 * (v + o);
   }
   RTCC3_HIP(hipEventRecord(ev_t3b_, s));
-  launch_sym_cube(T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, nullptr, s);
+  launch_sym_cube(T, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, nullptr, nullptr, s);
+  if (e.tangent())  // the symmetrisation and the denominator are linear in W'
+    launch_sym_cube(e.twin_out(T), w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, nullptr, nullptr, s);
   RTCC3_HIP(hipEventRecord(ev_t_, s));  // t3 blocks ready
 
   // Contractions run over the blocks this window is responsible for: all of
@@ -639,7 +796,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
       const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
       build_event(s2);  // same kernel as the builds: timed with them
-      checked_seg_gemm(g, cblh, lA, lB, lS, s2);
+      prod_seg(e, g, cblh, lA, lB, lS, s2);
       build_event(s2);
       build_flop_ += 8.0 * cn * v * (o * v) * (2 * v);
     }
@@ -669,7 +826,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
     RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));  // after the t3 build (a no-op when S went first)
     build_event(s2);
-    checked_seg_gemm(g, blh, lA, lB, winlen, s2);
+    prod_seg(e, g, blh, lA, lB, winlen, s2);
     build_event(s2);
     build_flop_ += 8.0 * nw * v * v2 * (2 * o + 2 * v);
     RTCC3_HIP(hipEventRecord(ev_l3b_, s2));
@@ -680,7 +837,15 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   }
   {  // P_ijk^abc and the denominator; the terms without a summation index are added per source
     LamElem le{Lov, F, l1, l2};
-    launch_sym_cube(L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, &le, s2);
+    launch_sym_cube(L, w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, &le, nullptr, s2);
+    if (e.tangent()) {
+      // the bracket terms' derivative: L l1' + f~' l2 + f~ l2' (L is invariant
+      // under the T1 transformation: its twin is zero)
+      RTCC3_CHECK(!e.twin(Lov), "triples: L_iajb has a derivative");
+      LamElem d0{Lov, e.twin(F), e.twin(l1), l2}, d1{nullptr, F, nullptr, e.twin(l2)};
+      launch_sym_cube(e.twin_out(L), w.d_canon, (int)w.canon.size() / 4, w.d_part, eps_, o, v, vp, &d0,
+                      d1.l2 ? &d1 : nullptr, s2);
+    }
   }
   RTCC3_HIP(hipEventRecord(ev_l_, s2));  // lambda3 blocks ready
   launches_ += 4;
@@ -703,7 +868,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     // along with products that read the block anyway (tail columns of the Y1
     // product below; the f~ term inside tb_X2c); else one sweep per block
     const bool tails = o <= 15;
-    if (!tails) launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, vp, 3, s);
+    if (!tails) {
+      RTCC3_CHECK(!e.tangent(), "triples: derivatives need o <= 15");
+      launch_small_t3(T, cbl, cn, Lov, F, l2, X1, X2p, Z34, o, v, vp, 3, s);
+    }
     // the t3 side's products are bound by the matrix cores like the lambda3
     // build: they start once it is done
     RTCC3_HIP(hipStreamWaitEvent(s, ev_l3b_, 0));
@@ -744,7 +912,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
-      checked_gemm(g, oblh, lOVVV, winlen, oovv, s);
+      prod(e, g, oblh, lOVVV, winlen, oovv, s);
     }
     // X2 -= sum_c Zh[(a,b)][c] G[K][I][c][x] into X2p[x][J], G[k][m][c][x] = (kx|mc)~.
     // The contraction set holds every ordering of its triples, so each term of
@@ -772,7 +940,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       std::memcpy(g.cC, cc, sizeof(g.cC));
-      checked_gather_gemm(g, gr, winlen, lOOOV, oovv, s);
+      prod_gather(e, g, gr, winlen, lOOOV, oovv, s);
     };
     {
       // (G[K][I] - 2 G[I][K]) is tb_X2c at [K][I]; G[I][J] is tb_X2b at [I][J]
@@ -805,7 +973,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = v;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)o * v2, v2, 0, 0);
-      checked_gemm(g, cblh, lOVVV, winlen, oovv, s2);
+      prod(e, g, cblh, lOVVV, winlen, oovv, s2);
     }
     {  // Y2: -sum_d lambda[(a,b)][d] (xI|dK)~ into Y2p[x][J], summed over the blocks of each J
       GemmDesc g = base((int)v2, o, v * w.gJ.max, 0, nullptr, pr);
@@ -826,7 +994,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = 1;
       g.sCn0 = (int64_t)o * v2;
       set4(g.cC, 0, v2, 0, 0);
-      checked_gather_gemm(g, w.gJ, winlen, lOOOV, oovv, s2);
+      prod_gather(e, g, w.gJ, winlen, lOOOV, oovv, s2);
     }
     // Products that read one block of the window as A[m][(k,l)] (M = v,
     // K = v^2, unit stride along (k,l)) and differ in B and C run as column
@@ -870,7 +1038,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
           lenB[4 + t] = q.tlenB;
           lenC[4 + t] = q.tlenC;
         }
-        checked_colseg_gemm(g, cblh, winlen, lenB, lenC, st);
+        prod_colseg(e, g, cblh, winlen, lenB, lenC, st);
       }
     };
     auto cseg = [&](const cplx* Bp, std::initializer_list<int64_t> cb, int64_t sbk, int64_t sbn, cplx* Cp,
@@ -958,7 +1126,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCn1 = v;
       g.sCn0 = 1;
       set4(g.cC, 0, v3, 0, 0);
-      checked_gather_gemm(g, w.gJ, t2len, winlen, lOVVV, s2);
+      prod_gather(e, g, w.gJ, t2len, winlen, lOVVV, s2);
     }
     launches_ += tails ? 9 : 10;
   }
@@ -988,11 +1156,14 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.C = Dab;
       g.sCm0 = v;
       g.sCn0 = 1;
-      checked_gemm(g, w.owned.data(), winlen, winlen, v2, s);
+      prod(e, g, w.owned.data(), winlen, winlen, v2, s);
     }
     // D_ia first term: sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]; it equals the
     // Y1 intermediate Z34 when the same pass also evaluates the right-hand side
-    if (!rhs_terms) launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, vp, 2, s);
+    if (!rhs_terms) {
+      RTCC3_CHECK(!e.tangent(), "triples: derivatives of the density need the right-hand side pass");
+      launch_small_t3(T, w.d_owned, no, Lov, F, l2, nullptr, nullptr, Z34, o, v, vp, 2, s);
+    }
     {  // D_ia second term: Rd[J][I][b][x] += sum_cd lambda[b][(c,d)] t2[x][K][(c,d)]
       GemmDesc g = base(v, o, (int)v2, no, w.d_owned, pr);
       g.atomic = 1;
@@ -1011,7 +1182,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.sCm0 = o;
       g.sCn0 = 1;
       set4(g.cC, (int64_t)v * o, (int64_t)o * v * o, 0, 0);
-      checked_gemm(g, w.owned.data(), winlen, t2len, (int64_t)o * o * v * o, s);
+      prod(e, g, w.owned.data(), winlen, t2len, (int64_t)o * o * v * o, s);
     }
   }
   if (density_terms && !w.slabs.empty()) {
@@ -1026,6 +1197,14 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
                     "triples: slab out of bounds");
       // whole padded blocks: the padding is zero and adds nothing
       launch_gram(T, L, w.d_slabs, nslab, o, vb, R(-0.5), Dij, s2);
+      if (e.tangent()) {
+        const cplx *Tt = e.twin(T), *Lt = e.twin(L);
+        if (Tt || Lt) {
+          cplx* Dt = e.twin_out(Dij);
+          if (Tt) launch_gram(Tt, L, w.d_slabs, nslab, o, vb, R(-0.5), Dt, s2);
+          if (Lt) launch_gram(T, Lt, w.d_slabs, nslab, o, vb, R(-0.5), Dt, s2);
+        }
+      }
     } else {
       GemmDesc g = base(o, o, (int)vb, nslab, w.d_slabs, pr);  // whole padded blocks (zero padding)
       g.atomic = 1;
@@ -1041,7 +1220,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       g.C = Dij;
       g.sCm0 = o;
       g.sCn0 = 1;
-      checked_gemm(g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s2);
+      prod(e, g, w.slabs.data(), winlen, winlen, (int64_t)o * o, s2);
     }
   }
   // the next window reuses every window buffer: join the lambda3 side

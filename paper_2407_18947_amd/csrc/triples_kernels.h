@@ -18,10 +18,11 @@ struct LamElem {
 // (canon: 4 ints per entry, I <= J <= K and the slot of that ordering): every
 // ordering's block of W is replaced by the symmetrised, divided result.
 // le (may be null): add the lambda3 bracket terms without a summation index to
-// every source element first.  Blocks are [v][v][vp]: vp >= v is the row
-// stride of the innermost index.
+// every source element first; le2 (may be null): add them for a second set of
+// inputs too.  A null input of a set reads as zero.  Blocks are [v][v][vp]:
+// vp >= v is the row stride of the innermost index.
 void launch_sym_cube(cplx* W, const int* canon, int ncanon, const int* part, const double* eps, int o, int v, int vp,
-                     const LamElem* le, hipStream_t s);
+                     const LamElem* le, const LamElem* le2, hipStream_t s);
 // D[i][j] += alpha * sum_s sum_k A[(slot_s + i)*K + k] B[(slot_s + j)*K + k] for
 // i, j < o <= 16, slot_s = slabs[4 s + 3] (the slab's o blocks are consecutive
 // slots of K elements each).  D is [o][o], accumulated with atomics.

@@ -209,15 +209,20 @@ __device__ __forceinline__ int cube_at(int t0, int t1, int t2) { return t0 * CS0
 __device__ __forceinline__ int cstride(int p) { return p == 0 ? CS0 : p == 1 ? CS1 : 1; }
 __device__ __constant__ int kPerm[6][3] = {{0, 1, 2}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}};
 
-// With LAM, each source element first receives the terms of the lambda3 bracket
-// that carry no summation index,
+// With NL > 0, each source element first receives the terms of the lambda3
+// bracket that carry no summation index,
 //   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik,
-// evaluated at that source's own occupied and virtual indices.
-template <bool LAM>
+// evaluated at that source's own occupied and virtual indices, from NL sets of
+// inputs (a null input of a set reads as zero; the derivative of the terms
+// takes two sets, e.g. (L, f~', l1', l2) and (f~, l2')).
+struct LamPair {
+  LamElem e[2];
+};
+template <int NL>
 __global__ __launch_bounds__(256) void sym_cube_kernel(cplx* __restrict__ W, const int* __restrict__ canon,
                                                          const int* __restrict__ part,
                                                          const double* __restrict__ eps, int o, int v, int vp,
-                                                         LamElem le) {
+                                                         LamPair le) {
   __shared__ cplx acc[CB * CS0];
   const int q = blockIdx.y;
   const int I = canon[4 * q], J = canon[4 * q + 1], K = canon[4 * q + 2], n0 = canon[4 * q + 3];
@@ -233,37 +238,40 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(cplx* __restrict__ W, con
   for (int e = threadIdx.x; e < CB * CS0; e += blockDim.x) acc[e] = cplx{0, 0};
   __syncthreads();
   const int nn = o + v;
-  // With LAM, a source's terms without a summation index need, per cube, only
-  // 8x8 slices of L and l2 and 8-vectors of l1 and f~: staged in LDS first.
-  __shared__ cplx lt[LAM ? 4 : 1][CB][CB];  // L[si,X0,sj,X1], L[si,X0,sj,X2], l2[sj,sk,X1,X2], l2[si,sk,X1,X2]
-  __shared__ cplx lv[LAM ? 4 : 1][CB];      // l1[sk,X2], l1[sk,X1], f~[si,X0], f~[sj,X0]
+  // With NL > 0, a source's terms without a summation index need, per cube and
+  // set, only 8x8 slices of L and l2 and 8-vectors of l1 and f~: staged in LDS first.
+  constexpr int NS = NL > 0 ? NL : 1;
+  __shared__ cplx lt[NS][4][CB][CB];  // L[si,X0,sj,X1], L[si,X0,sj,X2], l2[sj,sk,X1,X2], l2[si,sk,X1,X2]
+  __shared__ cplx lv[NS][4][CB];      // l1[sk,X2], l1[sk,X1], f~[si,X0], f~[sj,X0]
   for (int s = 0; s < 6; ++s) {
     const int p0 = kPerm[s][0], p1 = kPerm[s][1], p2 = kPerm[s][2];
     const int x0 = pick(p0, c0, c1, c2), x1 = pick(p1, c0, c1, c2), x2 = pick(p2, c0, c1, c2);
     const cplx* src = W + (int64_t)sl[s] * vb;
     const int si = pick(p0, I, J, K), sj = pick(p1, I, J, K), sk = pick(p2, I, J, K);  // the source's occupied triple
-    if (LAM) {
+    if (NL > 0) {
       static_assert(CB == 8, "the staging below maps 256 threads onto four 8x8 tables");
-      const int q = threadIdx.x >> 6, i = (threadIdx.x >> 3) & 7, j = threadIdx.x & 7;
-      // table q, row i, column j: one pointer and one range test per thread
-      const int ri = q < 2 ? x0 : x1, cj = q == 0 ? x1 : x2;  // virtual offsets of the row and column
-      const cplx* tb = q < 2    ? le.Lov + ((int64_t)si * v * o + sj) * v         // L[si, ., sj, .]
-                       : q == 2 ? le.l2 + ((int64_t)sj * o + sk) * v * v         // l2[sj, sk, ., .]
-                                : le.l2 + ((int64_t)si * o + sk) * v * v;        // l2[si, sk, ., .]
-      const int64_t rs = q < 2 ? (int64_t)o * v : v;  // row stride
-      const bool okt = ri + i < v && cj + j < v;  // a masked element reads the table's first one
-      const cplx xt = tb[okt ? (int64_t)(ri + i) * rs + cj + j : 0];
-      lt[q][i][j] = okt ? xt : cplx{0, 0};
-      if (threadIdx.x < 4 * CB) {
-        const int r = threadIdx.x >> 3;
-        const int off = r == 0 ? x2 : r == 1 ? x1 : x0;
-        const cplx* vp = r == 0 ? le.l1 + (int64_t)sk * v + x2
-                         : r == 1 ? le.l1 + (int64_t)sk * v + x1
-                         : r == 2 ? le.F + (int64_t)si * nn + o + x0
-                                  : le.F + (int64_t)sj * nn + o + x0;
-        const bool okv = off + j < v;
-        const cplx xv = vp[okv ? j : 0];
-        lv[r][j] = okv ? xv : cplx{0, 0};
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const LamElem& ler = le.e[r];
+        const int tq = threadIdx.x >> 6, i = (threadIdx.x >> 3) & 7, j = threadIdx.x & 7;
+        // table tq, row i, column j: one pointer and one range test per thread
+        const int ri = tq < 2 ? x0 : x1, cj = tq == 0 ? x1 : x2;  // virtual offsets of the row and column
+        const cplx* tb = tq < 2    ? (ler.Lov ? ler.Lov + ((int64_t)si * v * o + sj) * v : nullptr)  // L[si, ., sj, .]
+                         : tq == 2 ? (ler.l2 ? ler.l2 + ((int64_t)sj * o + sk) * v * v : nullptr)    // l2[sj, sk, ., .]
+                                   : (ler.l2 ? ler.l2 + ((int64_t)si * o + sk) * v * v : nullptr);   // l2[si, sk, ., .]
+        const int64_t rs = tq < 2 ? (int64_t)o * v : v;  // row stride
+        const bool okt = tb && ri + i < v && cj + j < v;
+        lt[r][tq][i][j] = okt ? tb[(int64_t)(ri + i) * rs + cj + j] : cplx{0, 0};
+        if (threadIdx.x < 4 * CB) {
+          const int rr = threadIdx.x >> 3;
+          const int off = rr == 0 ? x2 : rr == 1 ? x1 : x0;
+          const cplx* vq = rr == 0   ? (ler.l1 ? ler.l1 + (int64_t)sk * v + x2 : nullptr)
+                           : rr == 1 ? (ler.l1 ? ler.l1 + (int64_t)sk * v + x1 : nullptr)
+                           : rr == 2 ? (ler.F ? ler.F + (int64_t)si * nn + o + x0 : nullptr)
+                                     : (ler.F ? ler.F + (int64_t)sj * nn + o + x0 : nullptr);
+          const bool okv = vq && off + j < v;
+          lv[r][rr][j] = okv ? vq[j] : cplx{0, 0};
+        }
       }
       __syncthreads();
     }
@@ -272,12 +280,13 @@ __global__ __launch_bounds__(256) void sym_cube_kernel(cplx* __restrict__ W, con
       const int X0 = x0 + u0, X1 = x1 + u1, X2 = x2 + u2;
       if (X0 < v && X1 < v && X2 < v) {
         cplx w = src[((int64_t)X0 * v + X1) * vp + X2];
-        if (LAM) {
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
           //   L_ijab l_c^k - L_ijac l_b^k + f~_ia l_bc^jk - f~_ja l_bc^ik at the source's indices
-          w = cadd(w, cmul(lt[0][u0][u1], lv[0][u2]));
-          w = csub(w, cmul(lt[1][u0][u2], lv[1][u1]));
-          w = cadd(w, cmul(lv[2][u0], lt[2][u1][u2]));
-          w = csub(w, cmul(lv[3][u0], lt[3][u1][u2]));
+          w = cadd(w, cmul(lt[r][0][u0][u1], lv[r][0][u2]));
+          w = csub(w, cmul(lt[r][1][u0][u2], lv[r][1][u1]));
+          w = cadd(w, cmul(lv[r][2][u0], lt[r][2][u1][u2]));
+          w = csub(w, cmul(lv[r][3][u0], lt[r][3][u1][u2]));
         }
         cplx& r = acc[u0 * cstride(p0) + u1 * cstride(p1) + u2 * cstride(p2)];
         r.re += w.re;
@@ -391,16 +400,21 @@ __global__ __launch_bounds__(256) void gram_kernel(const cplx* __restrict__ A, c
 }  // namespace
 
 void launch_sym_cube(cplx* W, const int* canon, int ncanon, const int* part, const double* eps, int o, int v, int vp,
-                     const LamElem* le, hipStream_t s) {
+                     const LamElem* le, const LamElem* le2, hipStream_t s) {
   RTCC3_CHECK(vp >= v, "sym: row stride below v");
+  RTCC3_CHECK(le || !le2, "sym: a second set of bracket inputs needs a first");
   if (ncanon <= 0) return;
   const int nc = (v + CB - 1) / CB;
   const dim3 grid((unsigned)(nc * nc * nc), (unsigned)ncanon);
-  if (le) {
-    hipLaunchKernelGGL(sym_cube_kernel<true>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, *le);
-  } else {
-    hipLaunchKernelGGL(sym_cube_kernel<false>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, LamElem{});
-  }
+  LamPair lp;
+  if (le) lp.e[0] = *le;
+  if (le2) lp.e[1] = *le2;
+  if (le2)
+    hipLaunchKernelGGL(sym_cube_kernel<2>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, lp);
+  else if (le)
+    hipLaunchKernelGGL(sym_cube_kernel<1>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, lp);
+  else
+    hipLaunchKernelGGL(sym_cube_kernel<0>, grid, dim3(256), 0, s, W, canon, part, eps, o, v, vp, lp);
   RTCC3_HIP(hipGetLastError());
 }
 

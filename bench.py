@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 import torch  # noqa: E402  (device memory and streams of the binding)
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 METRIC = "RK4 steps/sec (T+Λ RT-CC3) at o=15,v=57; FP32-split vs FP64 at dipole err"
 SIZE_NAMES = {(5, 19): "water-monomer", (10, 38): "water-dimer", (15, 57): "water-trimer",
               (25, 95): "water-pentamer"}
@@ -136,6 +141,70 @@ def alpha_proxy(make_ctx, y0, steps, dt, amp, codes, precisions):
     finally:
         ctx.close()
     return out
+
+
+def derivatives(codes, split, steps, dt=0.025, amp=0.001, h=1e-5, o=10, v=38, seed=2):
+    """Derivative of the dipole series with respect to the kick amplitude and a
+    scale of the dipole integrals at the water-dimer size (forward mode: the
+    state and its derivative propagated together, rtcc3_propagate_tangent), its
+    cost against the plain propagation, central differences (h) of plain
+    propagations as the check, and the split precision's derivative against
+    FP64's.  Context creation is outside the timed calls."""
+    import dataclasses
+
+    import numpy as np
+
+    from paper_2407_18947_amd import _lib
+    from paper_2407_18947_amd.inputs import field_delta_kick, initial_state, make_system
+
+    s = make_system(o, v, seed=seed)
+    y0 = initial_state(s)
+    shape = field_delta_kick(steps, dt, 1.0, "z")
+
+    def plain(A=amp, scale=1.0):
+        sys_ = s if scale == 1.0 else dataclasses.replace(s, mu=s.mu * scale)
+        ctx = _lib.Context(sys_, codes["fp64"])
+        ctx.set_state(y0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu = ctx.propagate(steps, dt, A * shape)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ctx.close()
+        progress(f"derivatives: plain propagation A={A} scale={scale}: {t:.2f} s")
+        return mu[:, 2], t
+
+    def tangent(prec):
+        ctx = _lib.Context(s, codes[prec])
+        ctx.set_option(_lib.RTCC3_OPT_TANGENT, 1)
+        out = {}
+        for name, fdot, kdot in (("A", shape, 0.0), ("kappa", None, 1.0)):
+            ctx.set_state(y0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, d = ctx.propagate_tangent(steps, dt, amp * shape, fdot, kdot)
+            torch.cuda.synchronize()
+            out[name] = (d[:, 2], time.perf_counter() - t0)
+            progress(f"derivatives: {prec} d/d{name}: {out[name][1]:.2f} s")
+        ctx.close()
+        return out
+
+    mu, t_plain = plain()
+    fd = {"A": (plain(amp + h)[0] - plain(amp - h)[0]) / (2 * h),
+          "kappa": (plain(amp, 1 + h)[0] - plain(amp, 1 - h)[0]) / (2 * h)}
+    t64 = tangent("fp64")
+    tsp = tangent(split)
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+    return {
+        "workload": (f"o={o}, v={v}, naux={s.naux}, seed {seed}, delta kick {amp} a.u. along z, "
+                     f"{steps} RK4 steps of dt={dt}; d mu_z(t_n)/dA and d mu_z(t_n)/dkappa"),
+        "plain_ms_per_step": 1e3 * t_plain / steps,
+        "fp64": {p: {"ms_per_step": 1e3 * t64[p][1] / steps, "cost_vs_plain": t64[p][1] / t_plain,
+                     "rel_err_vs_central_difference": rel(t64[p][0], fd[p])} for p in ("A", "kappa")},
+        split: {p: {"ms_per_step": 1e3 * tsp[p][1] / steps, "cost_vs_plain": tsp[p][1] / t_plain,
+                    "rel_err_vs_fp64": rel(tsp[p][0], t64[p][0])} for p in ("A", "kappa")},
+        "central_difference_h": h,
+    }
 
 
 MIXED_BATCH = [(5, 19, 30), (5, 36, 31), (10, 38, 32), (10, 72, 33), (5, 19, 34), (5, 36, 35), (10, 38, 36),
@@ -270,6 +339,8 @@ def main():
                     help="steps of the mixed-size batch and of the graph comparison (0: skip both)")
     ap.add_argument("--batch-trimer", type=int, default=0,
                     help="steps of the twelve-member finite-field batch at the trimer size (0: skip)")
+    ap.add_argument("--tangent-steps", type=int, default=100,
+                    help="RK4 steps of the derivative propagations at the water-dimer size (0: skip)")
     ap.add_argument("--alpha-steps", type=int, default=10,
                     help="RK4 steps of each of the eight finite-field propagations of the polarisability proxy "
                          "(0: skip)")
@@ -323,6 +394,7 @@ def main():
         del src, dst
 
     secs, mu_main, timing = run(args.precision)
+    progress(f"main {args.precision}: {K} steps in {secs:.2f} s")
     steps_per_s = K / secs
     tri_ms_per_step = timing[1] / K
     alg = triples_flops_per_step(o, v)
@@ -390,6 +462,7 @@ def main():
     }
     if not args.no_split and args.split != args.precision:
         secs_s, mu_s, timing_s = run(args.split)
+        progress(f"split {args.split}: {K} steps in {secs_s:.2f} s")
         tri_s = timing_s[1] / K
         out["split"] = {
             "precision": args.split,
@@ -404,6 +477,7 @@ def main():
         if args.alpha_steps > 0:
             mu1 = alpha_proxy(lambda: _lib.Context(s, codes[args.precision]), y0, args.alpha_steps, dt, 0.001, codes,
                               [args.precision, args.split])
+            progress("polarisability proxy done")
             ref = mu1[args.precision]
             out["split"]["alpha_proxy"] = {
                 "definition": "max_t |mu1_split - mu1_main| / max_t |mu1_main|, mu1 = four-point finite-field "
@@ -415,10 +489,14 @@ def main():
     if args.batch_steps > 0:
         out["batched"] = {"mixed": batched_mixed(codes, args.split, args.batch_steps, dt, amp),
                           "graph": graph_gain(codes, args.batch_steps, dt, amp)}
+        progress("batched and graph runs done")
+    if args.tangent_steps > 0:
+        out["derivatives"] = derivatives(codes, args.split, args.tangent_steps)
     if args.batch_trimer > 0:
         out.setdefault("batched", {})["finite_field_trimer"] = batched_finite_field_trimer(
             codes, args.split, args.batch_trimer, dt, 1200, s, y0)
     if not args.no_cpu_baseline:
+        progress("oracle sample on the host cores")
         cb = cpu_baseline(s, y0, field[0], args.cpu_blocks)
         cb["cpu_model"] = cpu_model()
         cb["nproc"] = os.cpu_count()

@@ -185,6 +185,64 @@ def test_split_precision_tangent_within_its_precision():
     _close("bf16x3 d mu/dA", out[_lib.RTCC3_BF16X3], out[_lib.RTCC3_FP64], 1e-6)
 
 
+def test_autograd_function_backward_and_forward_mode():
+    """L = sum_n w_n . Re mu(t_n) through DipoleSeries: its gradient with
+    respect to the amplitude and the dipole scale equals central differences of
+    L (h = 1e-5, the dipole scale through contexts of scaled integrals), and
+    forward-mode autograd gives the derivative series along (dA, dkappa)."""
+    import torch.autograd.forward_ad as fwAD
+
+    from paper_2407_18947_amd.sensitivity import dipole_series
+
+    o, v, steps, dt, A, h = 3, 6, 6, 0.05, 0.002, 1e-5
+    s = make_system(o, v, seed=55)
+    y0 = initial_state(s)
+    shape = field_delta_kick(steps, dt, 1.0, "z")
+    w = torch.tensor(np.random.default_rng(3).normal(size=(steps + 1, 3)))
+    ctx = _lib.Context(s)
+    a = torch.tensor(A, dtype=torch.float64, requires_grad=True)
+    k = torch.tensor(0.0, dtype=torch.float64, requires_grad=True)
+    loss = (w * dipole_series(a, k, ctx, y0, shape, dt)).sum()
+    loss.backward()
+
+    def L(Aval, scale=1.0):
+        return float((w.numpy() * _kick_mu(s, y0, steps, dt, Aval, scale).real).sum())
+
+    fdA = (L(A + h) - L(A - h)) / (2 * h)
+    fdk = (L(A, 1 + h) - L(A, 1 - h)) / (2 * h)
+    assert abs(a.grad.item() - fdA) < 1e-7 * abs(fdA), (a.grad.item(), fdA)
+    assert abs(k.grad.item() - fdk) < 1e-7 * abs(fdk), (k.grad.item(), fdk)
+    with fwAD.dual_level():
+        ad = fwAD.make_dual(torch.tensor(A, dtype=torch.float64), torch.tensor(1.0, dtype=torch.float64))
+        kd = fwAD.make_dual(torch.tensor(0.0, dtype=torch.float64), torch.tensor(0.5, dtype=torch.float64))
+        tangent = fwAD.unpack_dual(dipole_series(ad, kd, ctx, y0, shape, dt)).tangent.numpy()
+    ctx.set_state(y0)
+    _, want = ctx.propagate_tangent(steps, dt, A * shape, shape, 0.5)
+    ctx.close()
+    _close("forward mode", tangent, want.real, 1e-13)
+
+
+def test_polarizability_from_the_linear_response_matches_finite_field():
+    """alpha_zz(w) from one derivative propagation at zero field equals the one
+    from the four-point finite-field mu^(1) of four propagations (A = 0.001)."""
+    from paper_2407_18947_amd.properties import absorption_spectrum
+    from paper_2407_18947_amd.sensitivity import polarizability
+
+    o, v, steps, dt, A = 3, 6, 200, 0.05, 0.001
+    s = make_system(o, v, seed=56)
+    y0 = initial_state(s)
+    shape = field_delta_kick(steps, dt, 1.0, "z")
+    w = np.linspace(0.2, 1.5, 27)
+    ctx = _lib.Context(s)
+    S, alpha = polarizability(ctx, y0, shape, dt, w, damping=0.02)
+    ctx.close()
+    runs = {q: _kick_mu(s, y0, steps, dt, q * A) for q in (1, -1, 2, -2)}
+    mu1 = finite_field_mu1(runs[1], runs[-1], runs[2], runs[-2], A)
+    S_ff, alpha_ff = absorption_spectrum(mu1, shape[::2], dt, w, damping=0.02)
+    _close("alpha_zz", alpha[2], alpha_ff[2], 1e-8)
+    _close("S", S, S_ff, 1e-8)
+
+
 def test_tangent_calls_need_the_option():
     s = make_system(2, 3, seed=54)
     ctx = _lib.Context(s)

@@ -303,18 +303,29 @@ def batched_finite_field_trimer(codes, precision, steps, dt, window_blocks, s, y
         for c in ctxs:
             c.set_state(y0)
         fields = [field_delta_kick(steps, dt, a, d) for d, a in members]
+        progress(f"finite-field batch: {len(ctxs)} contexts created")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mus = _lib.rtcc3_propagate_batch([c.ctx for c in ctxs], steps, dt, fields)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
+        progress(f"finite-field batch: {steps} steps of {len(ctxs)} members in {t:.2f} s")
+        # one member alone with the same window, for the lockstep's gain
+        ctxs[0].set_state(y0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctxs[0].propagate(steps, dt, fields[0])
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
     finally:
         for c in ctxs:
             c.close()
     z = {a: mus[i][:, 2] for i, (d, a) in enumerate(members) if d == "z"}
     mu1 = P.finite_field_mu1(z[0.001], z[-0.001], z[0.002], z[-0.002], 0.001)
     return {"members": len(members), "precision": precision, "steps": steps, "window_blocks": window_blocks,
-            "aggregate_steps_per_s": len(members) * steps / t, "mu1_z_last": complex(mu1[-1]).real}
+            "aggregate_steps_per_s": len(members) * steps / t, "one_member_alone_steps_per_s": steps / t_one,
+            "speedup_vs_one_after_another": (len(members) * steps / t) / (steps / t_one),
+            "mu1_z_last": complex(mu1[-1]).real}
 
 
 def main():
@@ -417,8 +428,8 @@ def main():
         "vs_baseline": None,
         "context_paper_p100_gpu_dp_ratio": steps_per_s / PAPER_GPU_DP_TRIMER_STEPS_PER_S,
         "dtype": {"fp64": "f64", "fp32": "f32 triples GEMMs, f64 elsewhere",
-                  "bf16x3": "bf16x3-split triples build GEMMs, f32 other triples GEMMs, f64 elsewhere",
-                  "bf16x2": "bf16x2-split triples build GEMMs, f32 other triples GEMMs, f64 elsewhere"}[args.precision],
+                  "bf16x3": "bf16x3-split triples build GEMMs, f32 or f64 other triples GEMMs, f64 elsewhere",
+                  "bf16x2": "bf16x2-split triples build GEMMs, f32 or f64 other triples GEMMs, f64 elsewhere"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"RT-CC3 T+Lambda, o={o}, v={v}, naux={s.naux}, seeded synthetic "

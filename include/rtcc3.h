@@ -70,7 +70,8 @@ enum {
  *   RTCC3_BF16X2  two bf16 slices (16 bits), three slice products
  * The bf16 splits apply to the segmented products (the builds of t3 and
  * lambda3 and the S intermediate of Y1); the other triples products of such a
- * run use FP32. */
+ * run use FP32, except the X2 product with an operand combined from three
+ * blocks and the 16-wide gathered products, which use FP64 (faster there). */
 enum { RTCC3_FP64 = 0, RTCC3_FP32 = 1, RTCC3_BF16X3 = 2, RTCC3_BF16X2 = 3 };
 
 /* Create a context.

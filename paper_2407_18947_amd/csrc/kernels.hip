@@ -1523,7 +1523,18 @@ void tuner_counts(const Tuner* t, int& sites, int& changed) {
 TunerScope::TunerScope(Tuner* t) : prev(g_tuner) { g_tuner = t; }
 TunerScope::~TunerScope() { g_tuner = prev; }
 
-void gemm(const GemmDesc& d0, hipStream_t s) {
+void gemm(const GemmDesc& d_in, hipStream_t s) {
+  // A bf16-split run takes the split kernel for its segmented products only.
+  // Its other products run in FP32, except two forms whose FP64 kernels are
+  // faster than the FP32 ones on gfx950 (alone at o=15, v=57: the operand
+  // combined from three blocks 6.9 against 7.8 ms, the 16-wide gathered
+  // products 1.95 against 2.51 ms); those run in FP64, which is also more
+  // accurate.
+  GemmDesc dsel = d_in;
+  if ((dsel.prec == RTCC3_PREC_BF16X3 || dsel.prec == RTCC3_PREC_BF16X2) &&
+      !((dsel.nseg > 0 || dsel.force_prec) && !dsel.comb_n && !dsel.gk_start && !dsel.ncs))
+    dsel.prec = (dsel.comb_n == 3 || (dsel.gk_start && dsel.N <= 16)) ? RTCC3_PREC_FP64 : RTCC3_PREC_FP32;
+  const GemmDesc& d0 = dsel;
   if (d0.M <= 0 || d0.N <= 0 || d0.batch <= 0) return;
   if (d0.K <= 0) return;
   RTCC3_CHECK(d0.M0 >= 1 && d0.N0 >= 1 && d0.K0 >= 1, "gemm: inner extents must be >= 1");

@@ -23,8 +23,8 @@ __device__ __forceinline__ void catomic(cplx* p, cplx x) {
 //   flags&1: X1[I][a]     += sum_bc (t[a,b,c] - t[c,b,a]) L[J,b,K,c]
 //            X2p[I,J][a,b]+= sum_c  (t[a,b,c] - t[c,b,a]) f~[K, c]
 //   flags&2: Z[I][a]      += sum_bc (t[a,b,c] - t[b,a,c]) l2[J,K,b,c]
-// One (block, a) per workgroup; used when v > 64 (the wave kernel below maps
-// the unit-stride index onto the 64 lanes of a wave).
+// One (block, a) per workgroup; used when v > 128 (the wave kernel below maps
+// the unit-stride index onto the 64 lanes of a wave, in up to two chunks).
 __global__ void small_t3_simple_kernel(const cplx* __restrict__ T, const int* __restrict__ bl, const cplx* __restrict__ Lov,
                                 const cplx* __restrict__ F, const cplx* __restrict__ l2, cplx* __restrict__ X1,
                                 cplx* __restrict__ X2p, cplx* __restrict__ Z, int o, int v, int vp, int flags) {
@@ -92,21 +92,25 @@ __device__ __forceinline__ void wave_sum8(cplx* v, int lane) {
 }
 
 // One workgroup of SW_NW waves per block and chunk of SW_NW rows y
-// (blockIdx.y); wave w owns the row y = SW_NW*chunk + w, lane = z (unit
-// stride, v <= 64), and the wave walks x four at a time (fewer live registers,
-// so the kernel shares the chip with the products that run beside it).  Sums
-// over z use wave_sum8 on the terms of four x at once; sums over x stay in
-// registers, so X2b and Zb are complete per workgroup; X1a, Za, X1b (sums
-// over y) go through LDS and are added per chunk.
+// (blockIdx.y); wave w owns the row y = SW_NW*chunk + w, lane = z within each
+// of NZC 64-wide chunks of the unit-stride index (v <= 64 NZC), and the wave
+// walks x four at a time (fewer live registers, so the kernel shares the chip
+// with the products that run beside it).  Every element of a block is read
+// once, as part of a coalesced row.  Sums over z use wave_sum8 on the terms of
+// four x at once (after adding the z chunks); sums over x stay in registers,
+// per z chunk, so X2b and Zb are complete per workgroup; X1a, Za, X1b (sums
+// over y) go through LDS and are added per chunk of rows.
 constexpr int SW_NW = 8;
 
+template <int NZC>
 __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* __restrict__ T, const int* __restrict__ bl,
                                                               const cplx* __restrict__ Lov, const cplx* __restrict__ F,
                                                               const cplx* __restrict__ l2, cplx* __restrict__ X1,
                                                               cplx* __restrict__ X2p, cplx* __restrict__ Z, int o,
                                                               int v, int vp, int flags) {
-  __shared__ cplx sP[2][SW_NW][64];  // per-wave X1a[x], Za[x]
-  __shared__ cplx sz[SW_NW][64];     // per-wave X1b[z]
+  constexpr int VZ = 64 * NZC;
+  __shared__ cplx sP[2][SW_NW][VZ];  // per-wave X1a[x], Za[x]
+  __shared__ cplx sz[SW_NW][VZ];     // per-wave X1b[z]
   const int q = blockIdx.x;
   const int I = bl[4 * q], J = bl[4 * q + 1], K = bl[4 * q + 2], n = bl[4 * q + 3];
   const int64_t v2 = (int64_t)v * v, va = (int64_t)v * vp;  // t[x][y][z] at x*va + y*vp + z
@@ -116,30 +120,45 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
   const cplx* l2JK = l2 + ((int64_t)J * o + K) * v2;
   const int64_t Ly = (int64_t)o * v;
   const bool doX = flags & 1, doZ = flags & 2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, z = lane;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int y = blockIdx.y * SW_NW + w;
-  const bool yin = y < v, zin = z < v, ok = yin && zin;
+  const bool yin = y < v;
   const cplx* LJy = Lov + (int64_t)J * v * o * v + (int64_t)K * v + (yin ? y * Ly : 0);  // L[J,y,K,.]
-  const cplx Lyz = ok ? LJy[z] : cplx{0, 0};
-  const cplx lyz = ok ? l2JK[(int64_t)y * v + z] : cplx{0, 0};
-  const cplx fz = zin ? fK[z] : cplx{0, 0};
-  cplx a3{0, 0}, a4{0, 0}, a5{0, 0};
+  bool zin[NZC];
+  cplx Lyz[NZC], lyz[NZC], fz[NZC], a3[NZC], a4[NZC];
+#pragma unroll
+  for (int c = 0; c < NZC; ++c) {
+    const int z = 64 * c + lane;
+    zin[c] = z < v;
+    const bool ok = yin && zin[c];
+    Lyz[c] = ok ? LJy[z] : cplx{0, 0};
+    lyz[c] = ok ? l2JK[(int64_t)y * v + z] : cplx{0, 0};
+    fz[c] = zin[c] ? fK[z] : cplx{0, 0};
+    a3[c] = a4[c] = cplx{0, 0};
+  }
+  cplx a5{0, 0};
   for (int xg = 0; xg < v; xg += 4) {
     // four x at a time: u = (X2a terms, X1a terms), zq = (Za terms, unused)
     cplx u[8], zq[8];
 #pragma unroll
+    for (int e = 0; e < 8; ++e) u[e] = zq[e] = cplx{0, 0};
+#pragma unroll
     for (int xl = 0; xl < 4; ++xl) {
       const int x = xg + xl;
       const bool xin = x < v;
-      const cplx tv = ok && xin ? t[(int64_t)x * va + (int64_t)y * vp + z] : cplx{0, 0};
-      u[xl] = cmul(tv, fz);
-      u[4 + xl] = cmul(tv, Lyz);
-      zq[xl] = cmul(tv, lyz);
-      zq[4 + xl] = cplx{0, 0};
-      if (xin) {
-        a3 = cadd(a3, cmul(tv, fK[x]));
-        a4 = cadd(a4, cmul(tv, yin ? LJy[x] : cplx{0, 0}));
-        a5 = cadd(a5, cmul(tv, zin ? l2JK[(int64_t)x * v + z] : cplx{0, 0}));
+      const cplx fx = xin ? fK[x] : cplx{0, 0};
+      const cplx Lx = xin && yin ? LJy[x] : cplx{0, 0};
+#pragma unroll
+      for (int c = 0; c < NZC; ++c) {
+        const int z = 64 * c + lane;
+        const bool ok = yin && zin[c] && xin;
+        const cplx tv = ok ? t[(int64_t)x * va + (int64_t)y * vp + z] : cplx{0, 0};
+        u[xl] = cadd(u[xl], cmul(tv, fz[c]));
+        u[4 + xl] = cadd(u[4 + xl], cmul(tv, Lyz[c]));
+        zq[xl] = cadd(zq[xl], cmul(tv, lyz[c]));
+        a3[c] = cadd(a3[c], cmul(tv, fx));
+        a4[c] = cadd(a4[c], cmul(tv, Lx));
+        a5 = cadd(a5, cmul(tv, zin[c] && xin ? l2JK[(int64_t)x * v + z] : cplx{0, 0}));
       }
     }
     const int qi = lane >> 3;                   // the entry a lane's reduced value belongs to
@@ -160,19 +179,22 @@ __global__ __launch_bounds__(64 * SW_NW) void small_t3_wave_kernel(const cplx* _
       if ((lane & 7) == 0 && qi < 4 && xs < v) sP[1][w][xs] = zq[0];
     }
   }
-  // X2b[z][y] = sum_x t[x,y,z] f[x] (subtracted); Zb[y] = sum_xz t l2[x][z] (subtracted)
-  if (doX && ok) catomic(&X2p[(((int64_t)I * o + J) * v + z) * v + y], cplx{-a3.re, -a3.im});
-  if (doZ) {
+#pragma unroll
+  for (int c = 0; c < NZC; ++c) {
+    const int z = 64 * c + lane;
+    // X2b[z][y] = sum_x t[x,y,z] f[x] (subtracted)
+    if (doX && yin && zin[c]) catomic(&X2p[(((int64_t)I * o + J) * v + z) * v + y], cplx{-a3[c].re, -a3[c].im});
+    sz[w][z] = a4[c];
+  }
+  if (doZ) {  // Zb[y] = sum_xz t l2[x][z] (subtracted)
     for (int off = 32; off > 0; off >>= 1) {
       a5.re += __shfl_xor(a5.re, off);
       a5.im += __shfl_xor(a5.im, off);
     }
     if (lane == 0 && yin) catomic(&Z[(int64_t)I * v + y], cplx{-a5.re, -a5.im});
   }
-  sz[w][z] = a4;
   __syncthreads();
-  if (threadIdx.x < v) {
-    const int a = threadIdx.x;
+  for (int a = threadIdx.x; a < v; a += blockDim.x) {
     const int nw = min(SW_NW, v - (int)blockIdx.y * SW_NW);  // waves with a row
     cplx s1{0, 0}, s2{0, 0}, s4{0, 0};
     for (int ww = 0; ww < nw; ++ww) {
@@ -435,10 +457,13 @@ void launch_small_t3(const cplx* T, const int* bl, int nb, const cplx* Lov, cons
                      cplx* X2p, cplx* Z, int o, int v, int vp, int flags, hipStream_t s) {
   RTCC3_CHECK(vp >= v, "small_t3: row stride below v");
   if (nb <= 0) return;
+  const unsigned nyc = (unsigned)((v + SW_NW - 1) / SW_NW);
   if (v <= 64) {
-    const unsigned nyc = (unsigned)((v + SW_NW - 1) / SW_NW);
-    hipLaunchKernelGGL(small_t3_wave_kernel, dim3((unsigned)nb, nyc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1, X2p,
-                       Z, o, v, vp, flags);
+    hipLaunchKernelGGL(small_t3_wave_kernel<1>, dim3((unsigned)nb, nyc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1,
+                       X2p, Z, o, v, vp, flags);
+  } else if (v <= 128) {
+    hipLaunchKernelGGL(small_t3_wave_kernel<2>, dim3((unsigned)nb, nyc), dim3(64 * SW_NW), 0, s, T, bl, Lov, F, l2, X1,
+                       X2p, Z, o, v, vp, flags);
   } else {
     hipLaunchKernelGGL(small_t3_simple_kernel, dim3((unsigned)v, (unsigned)nb), dim3(64), 0, s, T, bl, Lov, F, l2, X1,
                        X2p, Z, o, v, vp, flags);

@@ -5,7 +5,7 @@ Calls only the oracle (oracle/rtcc3.py) and the seeded input generators
 than a minute are stored here instead of being recomputed by each test run.
 
 Run: python tests/golden/make_golden.py [case ...]
-cases: monomer, dimer, trimer_terms, o17v24_terms, pentamer_sampled (default: all)
+cases: monomer, dimer, trimer_terms, o17v24_terms, o16v66_terms, pentamer_sampled (default: all)
 """
 import os
 import sys
@@ -27,6 +27,8 @@ TERMS_FIELD = np.array([0.001, -0.002, 0.002])
 TERMS_CASES = {
     "trimer_terms": dict(o=15, v=57, seed=3, state_seed=8, scale=0.02),
     "o17v24_terms": dict(o=17, v=24, seed=12, state_seed=4, scale=0.1),
+    # o > 15 with v > 64: the separate sweep over blocks wider than one wave
+    "o16v66_terms": dict(o=16, v=66, seed=13, state_seed=5, scale=0.05),
 }
 PENTAMER = dict(o=25, v=95, seed=5, state_seed=9, scale=0.02)
 # doubles rows (i, j) stored for the trimer: X2[i,j,:,:] and Y2[i,j,:,:]
@@ -112,6 +114,7 @@ CASES = {
     "dimer": dimer,
     "trimer_terms": lambda: terms("trimer_terms"),
     "o17v24_terms": lambda: terms("o17v24_terms"),
+    "o16v66_terms": lambda: terms("o16v66_terms"),
     "pentamer_sampled": pentamer_sampled,
 }
 

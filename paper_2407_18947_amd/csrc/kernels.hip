@@ -1586,7 +1586,10 @@ void gemm(const GemmDesc& d_in, hipStream_t s) {
   const bool tr = d0.M <= 16 && d0.N > 16 && d0.nseg == 0 && !d0.gk_start && d0.ncs == 0;
   GemmDesc d = tr ? transposed(d0) : d0;
   if (d.ncs > 0) d.N = d.N0 = 64;  // one 64-wide tile of four 16-column segments
-  const int bn = d.N <= 16 && d.nseg == 0 ? 16 : 64;  // the segmented kernel has 64-wide tiles
+  // The segmented kernel has 64-wide tiles.  A gathered product up to 32 wide
+  // (an occupied index of 17 to 32) takes two 16-wide tiles rather than one
+  // 64-wide tile that would be mostly padding.
+  const int bn = (d.N <= 16 || (d.gk_start && d.N <= 32)) && d.nseg == 0 ? 16 : 64;
   const int64_t tiles = (int64_t)((d.M + BM - 1) / BM) * ((d.N + bn - 1) / bn);
   // Split K across workgroups when the grid is too small to fill the chip and
   // K is long; the partial products are then added with atomics.

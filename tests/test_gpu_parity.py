@@ -314,6 +314,14 @@ def test_o17_v24_all_terms():
     _compare_terms_golden("o17v24_terms", 17, 24, 12, 4, 0.1)
 
 
+def test_o16_v66_all_terms():
+    """o = 16 > 15 with v = 66 > 64: the separate sweep for X1, the f~ term of X2 and
+    Z34 over blocks wider than one wave (two 64-wide chunks of the unit-stride
+    index), two row tiles in the products, padded rows of 72."""
+    _say("terms o=16 v=66")
+    _compare_terms_golden("o16v66_terms", 16, 66, 13, 5, 0.05)
+
+
 def test_pentamer_size_sampled_elements():
     """o=25, v=95 (naux 360; v > 64 and o > 16: two row tiles, padded rows of 96,
     the separate X1 sweep with more than 64 virtuals, windows of whole canonical

@@ -801,6 +801,19 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(GemmDesc d, int ksplit,
         put<ATOMIC>(d, C, ro[i][r], co[j], (double)crr[i][j][r] - (double)cii[i][j][r], (double)cim[i][j][r]);
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (consecutive linear ids
+// land on different XCDs, each with an L2 of its own).  xcd_contiguous() maps
+// a workgroup's linear id p < total to a logical id such that each XCD takes
+// a contiguous range of logical ids (XCD x gets the x-th eighth): work items
+// that share operands then run on one XCD and can share its L2.  A bijection
+// of [0, total).
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t p, int64_t total) {
+  constexpr int NXCD = 8;
+  const int64_t q = total / NXCD, r = total % NXCD;
+  const int64_t x = p % NXCD, slot = p / NXCD;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 K-segmented product (the builds of t3 and lambda3 and the S product):
 // one 64 x 64 tile of C per workgroup, four waves of 32 x 32, complex products
@@ -837,8 +850,14 @@ __global__ __launch_bounds__(NT, 3) void zgemm_seg_f64_kernel(GemmDesc d) {
   __shared__ double sB[3][BK][BN + 1];  // Br, Bi - Br, Br + Bi   [plane][k][n]
 
   const int tilesN = (d.N + BN - 1) / BN;
-  const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
-  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  // each XCD takes a contiguous range of (block, tile) pairs: the tiles of a
+  // block share its A rows, and neighbouring blocks share B slices
+  const int64_t by = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  const int64_t lg = xcd_contiguous((int64_t)blockIdx.x + (int64_t)gridDim.x * by,
+                                    (int64_t)gridDim.x * gridDim.y * gridDim.z);
+  const int tx = (int)(lg % gridDim.x);
+  const int64_t b = lg / gridDim.x;
+  const int tm = tx / tilesN, tn = tx % tilesN;
   if (b >= d.batch) return;
   const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
   cplx* C = d.C + d.cC[0] * I + d.cC[1] * J + d.cC[2] * K + d.cC[3] * n;
@@ -992,19 +1011,6 @@ __global__ __launch_bounds__(NT, 3) void zgemm_seg_f64_kernel(GemmDesc d) {
 // ---------------------------------------------------------------------------
 // Three workgroups per CU (168 registers a wave); two for the combined operand,
 // whose three loaded blocks per element need more.
-// Workgroups are dispatched to the eight XCDs in turn (consecutive linear ids
-// land on different XCDs, each with an L2 of its own).  xcd_contiguous() maps
-// a workgroup's linear id p < total to a logical id such that each XCD takes
-// a contiguous range of logical ids (XCD x gets the x-th eighth): work items
-// that share operands then run on one XCD and can share its L2.  A bijection
-// of [0, total).
-__device__ __forceinline__ int64_t xcd_contiguous(int64_t p, int64_t total) {
-  constexpr int NXCD = 8;
-  const int64_t q = total / NXCD, r = total % NXCD;
-  const int64_t x = p % NXCD, slot = p / NXCD;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
-}
-
 template <bool ATOMIC, int BN, int CMB>
 __global__ __launch_bounds__(NT, CMB == 2 ? 2 : 3) void zgemm_kb_f64_kernel(GemmDesc d, int ksplit, int kchunk) {
   constexpr int BK = 16, NB = BN / 16;  // B columns per thread

@@ -342,6 +342,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-blocks", type=int, default=60, help="oracle blocks timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--window-blocks", type=int, default=0,
+                    help="cap the triples windows of the main run at this many ordered blocks (0: one window "
+                         "from free memory)")
     ap.add_argument("--single-stream", action="store_true",
                     help="every kernel on one stream, one after another (times each kernel alone; not the metric)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -383,6 +386,8 @@ def main():
         tune_rows.append(_lib.rtcc3_tuning_report(ctx.ctx))
         if args.single_stream:
             ctx.set_option(_lib.RTCC3_OPT_SINGLE_STREAM, 1)
+        if args.window_blocks > 0:
+            ctx.set_option(_lib.RTCC3_OPT_WINDOW_BLOCKS, args.window_blocks)
         ctx.set_state(y0)
         mu_w = ctx.propagate(W, dt, field[: 2 * W + 1]) if W > 0 else None
         torch.cuda.synchronize()
@@ -437,6 +442,10 @@ def main():
                          f"delta kick {amp} a.u. along z, dt={dt}"),
             "o": o, "v": v, "naux": s.naux, "precision": args.precision,
             **({"single_stream": True} if args.single_stream else {}),
+            # capped triples windows: blocks held at once and their device memory
+            **({"window_blocks": args.window_blocks,
+                "window_bytes": args.window_blocks * 16 * v * v * (2 * (-(-v // 8) * 8) + o)}
+               if args.window_blocks > 0 else {}),
         },
         # Dominant kernel: the segmented store-mode product, launched for a
         # window's t3 blocks, its lambda3 blocks (before symmetrisation) and

@@ -344,8 +344,12 @@ __global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_ke
                                                                                   int kchunk) {
   typedef typename Frag<T>::acc acc_t;
   constexpr int BK = 16;
-  constexpr int WM = BN == 64 ? 32 : 16, WN = BN == 64 ? 32 : 16;  // wave sub-tile
-  constexpr int IB = WM / 16, JB = WN / 16;                         // MFMA blocks per wave
+  // Wave sub-tile: 32x32 (2x2 MFMA blocks) in a 64x64 tile, 16x16 in a 64x16
+  // tile; with column segments each wave takes 16 rows and all 64 columns, so
+  // that a launch with fewer than four segments skips the MFMAs of the unused
+  // 16-column blocks in every wave alike.
+  constexpr int WM = CMB == 5 ? 16 : BN == 64 ? 32 : 16, WN = CMB == 5 ? BN : BN == 64 ? 32 : 16;
+  constexpr int IB = WM / 16, JB = WN / 16;  // MFMA blocks per wave
   typedef TileLoader<KFA, NFB, BN, BK, SEG, CMB> Loader;
   // Segmented products keep one LDS buffer (two barriers per K step) so that
   // three workgroups fit on a CU; the others double-buffer.
@@ -415,6 +419,9 @@ __global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_ke
     }
 
   const int nsteps = (kend - kbeg + BK - 1) / BK;
+  // the wave's 16-column blocks that carry a column segment (all of them otherwise)
+  const int jlive = CMB == 5 ? min(JB, d.ncs - (wn >> 4)) : JB;
+  auto live = [&](int j) { return CMB != 5 || j < jlive; };
   ld.load(d, kbeg);
   stash(0);
   __syncthreads();
@@ -450,33 +457,40 @@ __global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_ke
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(sa[i], br[j], cre[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) cre[i][j] = Frag<T>::mfma(sa[i], br[j], cre[i][j]);
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ar[i], db[j], cim[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) cim[i][j] = Frag<T>::mfma(ar[i], db[j], cim[i][j]);
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) c3[i][j] = Frag<T>::mfma(ai[i], sb[j], c3[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) c3[i][j] = Frag<T>::mfma(ai[i], sb[j], c3[i][j]);
       } else {
         // four independent MFMAs between two that update the same accumulator
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) cre[i][j] = Frag<T>::mfma(ar[i], br[j], cre[i][j]);
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) cim[i][j] = Frag<T>::mfma(ar[i], bi[j], cim[i][j]);
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) cre[i][j] = Frag<T>::mfma(nai[i], bi[j], cre[i][j]);
 #pragma unroll
         for (int i = 0; i < IB; ++i)
 #pragma unroll
-          for (int j = 0; j < JB; ++j) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
+          for (int j = 0; j < JB; ++j)
+            if (live(j)) cim[i][j] = Frag<T>::mfma(ai[i], br[j], cim[i][j]);
       }
     }
     if (NBUF == 1) __syncthreads();  // every wave is done with the buffer
@@ -499,33 +513,29 @@ __global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_ke
     const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
-      const bool lo = wn == 0;
-      const GemmDesc::ColSeg& g0 = d.cs[j];
-      const GemmDesc::ColSeg& g1 = d.cs[2 + j];
       const int sg = (wn >> 4) + j;
-      const int ns = lo ? g0.n : g1.n;
+      if (sg >= d.ncs) continue;
+      const GemmDesc::ColSeg& g = d.cs[sg];
       const int c = lane & 15;
-      const bool tail = c == 15 && (lo ? g0.tB : g1.tB) != nullptr;
-      if (sg >= d.ncs || (c >= ns && !tail)) continue;
+      const bool tail = c == 15 && g.tB != nullptr;
+      if (c >= g.n && !tail) continue;
       cplx* Cs;
       int64_t base, sCm, sCn;
       double alr, ali;
       if (tail) {
-        Cs = lo ? g0.tC : g1.tC;
-        base = lo ? g0.tcC[0] * I + g0.tcC[1] * J + g0.tcC[2] * K + g0.tcC[3] * n
-                  : g1.tcC[0] * I + g1.tcC[1] * J + g1.tcC[2] * K + g1.tcC[3] * n;
-        sCm = lo ? g0.tsCm : g1.tsCm;
+        Cs = g.tC;
+        base = g.tcC[0] * I + g.tcC[1] * J + g.tcC[2] * K + g.tcC[3] * n;
+        sCm = g.tsCm;
         sCn = 0;
-        alr = lo ? g0.talpha.re : g1.talpha.re;
-        ali = lo ? g0.talpha.im : g1.talpha.im;
+        alr = g.talpha.re;
+        ali = g.talpha.im;
       } else {
-        Cs = lo ? g0.C : g1.C;
-        base = lo ? g0.cC[0] * I + g0.cC[1] * J + g0.cC[2] * K + g0.cC[3] * n
-                  : g1.cC[0] * I + g1.cC[1] * J + g1.cC[2] * K + g1.cC[3] * n;
-        sCm = lo ? g0.sCm : g1.sCm;
-        sCn = lo ? g0.sCn : g1.sCn;
-        alr = lo ? g0.alpha.re : g1.alpha.re;
-        ali = lo ? g0.alpha.im : g1.alpha.im;
+        Cs = g.C;
+        base = g.cC[0] * I + g.cC[1] * J + g.cC[2] * K + g.cC[3] * n;
+        sCm = g.sCm;
+        sCn = g.sCn;
+        alr = g.alpha.re;
+        ali = g.alpha.im;
       }
 #pragma unroll
       for (int i = 0; i < IB; ++i)

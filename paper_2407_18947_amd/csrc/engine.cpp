@@ -9,7 +9,8 @@ Engine::~Engine() {
   for (auto& b : bufs_)
     for (cplx* q : {b.p, b.g, b.tp, b.tg})
       if (q) (void)hipFree(q);
-  if (scratch_) (void)hipFree(scratch_);
+  for (auto& sc : scratch_)
+    if (sc.p) (void)hipFree(sc.p);
 }
 
 cplx* Engine::alloc_twin(int64_t n) {
@@ -217,17 +218,25 @@ View Engine::diag(View v, int d0, int d1) {
 }
 
 cplx* Engine::scratch(int64_t n) {
-  if (n > scratch_n_) {
+  Scratch* sc = nullptr;
+  for (auto& x : scratch_)
+    if (x.stream == stream) sc = &x;
+  if (!sc) {
+    if (sealed_) throw Error(-4, "engine: scratch for a new stream after the context was set up");
+    scratch_.push_back(Scratch{stream, nullptr, 0});
+    sc = &scratch_.back();
+  }
+  if (n > sc->n) {
     if (sealed_) throw Error(-4, "engine: scratch grown after the context was set up");
     // work on any stream may still read the old scratch
     RTCC3_HIP(hipDeviceSynchronize());
-    if (scratch_) RTCC3_HIP(hipFree(scratch_));
-    scratch_ = nullptr;
-    hipError_t e = hipMalloc(&scratch_, sizeof(cplx) * n);
+    if (sc->p) RTCC3_HIP(hipFree(sc->p));
+    sc->p = nullptr;
+    hipError_t e = hipMalloc(&sc->p, sizeof(cplx) * n);
     if (e != hipSuccess) throw Error(-2, "engine: out of device memory for scratch");
-    scratch_n_ = n;
+    sc->n = n;
   }
-  return scratch_;
+  return sc->p;
 }
 
 void Engine::set_requires_grad(int buf, bool on) { bufs_[buf].rg = on; }

@@ -133,8 +133,14 @@ class Engine {
   std::vector<Op> tape_;
   bool recording_ = false;
   bool sealed_ = false;
-  cplx* scratch_ = nullptr;
-  int64_t scratch_n_ = 0;
+  // Relayout scratch, one region per stream that einsums run on, so that
+  // einsums on different streams may run at the same time.
+  struct Scratch {
+    hipStream_t stream;
+    cplx* p;
+    int64_t n;
+  };
+  std::vector<Scratch> scratch_;
 
   cplx* scratch(int64_t n);
   void einsum_exec(const std::string& spec, cplx alpha, const View& A, const View& B, const View& C);

@@ -43,7 +43,7 @@ struct rtcc3_ctx {
   // (on stream itself with single_stream)
   hipStream_t side_stream = nullptr;
   int single_stream = 0;
-  hipEvent_t ev_side1 = nullptr;
+  hipEvent_t ev_side0 = nullptr, ev_side1 = nullptr;
   // derivative buffers (RTCC3_OPT_TANGENT): the engine's twins, and
   int tangent_ready = 0;
   cplx* zero_nn = nullptr;      // a zero n x n matrix (h0 of the field derivative of h)
@@ -109,7 +109,24 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
     build_h(e.twin_out(c->h.p), c->zero_nn, c->mu.p, n * n, nullptr, E.dot, c->stream);
   }
   CCSDResult r = ccsd_forward(e, d, y, c->h, c->B, c->I, c->ones_o);
-  ccsd_residual(e, d, r);
+  // The triples read only the dressed integrals and Fock matrix of the forward
+  // part: with more than one stream the residual runs on the side stream,
+  // beside the triples' integral blocks (einsums on the two streams use
+  // separate scratch), and the reverse sweep follows it there.
+  if (with_triples && !c->single_stream) {
+    RTCC3_HIP(hipEventRecord(c->ev_side0, c->stream));
+    RTCC3_HIP(hipStreamWaitEvent(c->side_stream, c->ev_side0, 0));
+    e.stream = c->side_stream;
+    try {
+      ccsd_residual(e, d, r);
+    } catch (...) {
+      e.stream = c->stream;
+      throw;
+    }
+    e.stream = c->stream;
+  } else {
+    ccsd_residual(e, d, r);
+  }
   const bool want_density = t.terms || t.mu || t.mu_at_step;
 
   TriplesOut to;
@@ -476,6 +493,7 @@ extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const do
     RTCC3_HIP(hipEventCreate(&c->ev0));
     RTCC3_HIP(hipEventCreate(&c->ev1));
     RTCC3_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+    RTCC3_HIP(hipEventCreateWithFlags(&c->ev_side0, hipEventDisableTiming));
     RTCC3_HIP(hipEventCreateWithFlags(&c->ev_side1, hipEventDisableTiming));
     c->e.reset(new Engine(c->stream));
     Engine& e = *c->e;
@@ -931,6 +949,7 @@ extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
+  if (c->ev_side0) (void)hipEventDestroy(c->ev_side0);
   if (c->ev_side1) (void)hipEventDestroy(c->ev_side1);
   if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);

@@ -43,7 +43,7 @@ struct rtcc3_ctx {
   // (on stream itself with single_stream)
   hipStream_t side_stream = nullptr;
   int single_stream = 0;
-  hipEvent_t ev_side0 = nullptr, ev_side1 = nullptr;
+  hipEvent_t ev_side0 = nullptr, ev_res = nullptr, ev_side1 = nullptr;
   // derivative buffers (RTCC3_OPT_TANGENT): the engine's twins, and
   int tangent_ready = 0;
   cplx* zero_nn = nullptr;      // a zero n x n matrix (h0 of the field derivative of h)
@@ -113,6 +113,7 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
   // part: with more than one stream the residual runs on the side stream,
   // beside the triples' integral blocks (einsums on the two streams use
   // separate scratch), and the reverse sweep follows it there.
+  hipEvent_t residual_done = nullptr;
   if (with_triples && !c->single_stream) {
     RTCC3_HIP(hipEventRecord(c->ev_side0, c->stream));
     RTCC3_HIP(hipStreamWaitEvent(c->side_stream, c->ev_side0, 0));
@@ -124,6 +125,8 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
       throw;
     }
     e.stream = c->stream;
+    RTCC3_HIP(hipEventRecord(c->ev_res, c->side_stream));
+    residual_done = c->ev_res;
   } else {
     ccsd_residual(e, d, r);
   }
@@ -146,7 +149,9 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
       e.stream = c->stream;
       RTCC3_HIP(hipEventRecord(c->ev_side1, c->side_stream));
       return c->ev_side1;
-    });
+    }, residual_done);
+    // the reverse sweep's gradients are read below
+    if (hipEvent_t sd = c->tri->side_done()) RTCC3_HIP(hipStreamWaitEvent(c->stream, sd, 0));
   } else {
     ccsd_backward(e, d, y, c->ones_o, r);
   }
@@ -494,6 +499,7 @@ extern "C" int rtcc3_create(int o, int v, const double* fock, int naux, const do
     RTCC3_HIP(hipEventCreate(&c->ev1));
     RTCC3_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
     RTCC3_HIP(hipEventCreateWithFlags(&c->ev_side0, hipEventDisableTiming));
+    RTCC3_HIP(hipEventCreateWithFlags(&c->ev_res, hipEventDisableTiming));
     RTCC3_HIP(hipEventCreateWithFlags(&c->ev_side1, hipEventDisableTiming));
     c->e.reset(new Engine(c->stream));
     Engine& e = *c->e;
@@ -950,6 +956,7 @@ extern "C" void rtcc3_destroy(rtcc3_ctx* c) {
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
   if (c->ev_side0) (void)hipEventDestroy(c->ev_side0);
+  if (c->ev_res) (void)hipEventDestroy(c->ev_res);
   if (c->ev_side1) (void)hipEventDestroy(c->ev_side1);
   if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);

@@ -1236,7 +1236,7 @@ void Triples::build_event(hipStream_t s) {
 }
 
 TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density,
-                        const Beside& beside) {
+                        const Beside& beside, hipEvent_t ready) {
   const int64_t o = d.o, v = d.v;
   const int64_t ov = o * v, oovv = o * o * v * v;
   hipStream_t s = e.stream;
@@ -1270,7 +1270,9 @@ TriplesOut Triples::run(Engine& e, const Dims& d, const CCSDResult& r, const cpl
     side_done_ = (*beside_)(ev_l3b_);
     beside_ = nullptr;
   }
-  if (side_done_) RTCC3_HIP(hipStreamWaitEvent(s, side_done_, 0));
+  // the final contractions read blocks of the CCSD residual (and use this
+  // stream's own scratch): they need not wait for the work beside
+  if (ready) RTCC3_HIP(hipStreamWaitEvent(s, ready, 0));
   // ---- final contractions of the Y1 intermediates
   View Y1 = e.tensor("tr_Y1", {o, v});
   View l2 = Engine::raw(const_cast<cplx*>(y) + 2 * ov + oovv, {o, o, v, v});

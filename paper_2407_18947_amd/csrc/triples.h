@@ -63,11 +63,13 @@ class Triples {
   // has been enqueued, with an event recorded after that build: it may enqueue
   // independent work on another stream that waits for the event (so the work
   // runs beside the contractions rather than the builds) and returns an event
-  // recorded after it; the final contractions, which use the engine's scratch
-  // memory, wait for that event.
+  // recorded after it, which side_done() returns until the next run; run()
+  // does not wait for it.  ready (optional): an event after which the integral
+  // blocks of the CCSD residual that the final contractions read are complete.
   typedef std::function<hipEvent_t(hipEvent_t)> Beside;
   TriplesOut run(Engine& e, const Dims& d, const CCSDResult& r, const cplx* y, bool want_density,
-                 const Beside& beside = nullptr);
+                 const Beside& beside = nullptr, hipEvent_t ready = nullptr);
+  hipEvent_t side_done() const { return side_done_; }
   void set_precision(int p) { prec_ = p; }
   // All work on the caller's stream, one kernel after another (for timing
   // kernels alone); the default runs the lambda3 side on a second stream.

@@ -86,6 +86,11 @@ struct GemmDesc {
   // A bf16-split precision runs unsegmented products in FP32 unless
   // force_prec is set (self-tests of the split kernel).
   int force_prec;
+  // grp > 1 (segmented store products): workgroups walk groups of grp
+  // consecutive batch entries column tile by column tile, so the entries of a
+  // group (which share their large operand blocks) read each 64-column slice
+  // of those blocks one after another, from one XCD's L2.
+  int grp;
   // Combined operand (comb_n = 3, block table required, A read k-fast and B
   // k-fast): operand A (comb_on = 0) or B (comb_on = 1) of batch entry b is
   //   sum_s comb_w[s] * X[part[6*n + comb_perm[s]]*comb_stride + offset],  n = bl[4*b + 3],

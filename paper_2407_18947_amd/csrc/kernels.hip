@@ -309,7 +309,10 @@ __device__ __forceinline__ void put(const GemmDesc& d, cplx* C, int64_t ro, int6
   if (ATOMIC) {
     atomic_add_cplx(p, vr, vi);
   } else if (d.store) {
-    *p = cplx{vr, vi};
+    // store mode writes each element once and nothing in the same product reads
+    // it: a streaming store leaves the cache lines to the operands
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(d2v{vr, vi}, reinterpret_cast<d2v*>(p));
   } else {
     cplx c = *p;
     c.re += vr;
@@ -565,6 +568,36 @@ __global__ __launch_bounds__(NT, (zgemm_waves<T, BN, SEG, CMB>())) void zgemm_ke
       for (int r = 0; r < 4; ++r) put<ATOMIC>(d, C, ro[i][r], co[j], (double)cre[i][j][r], (double)cim[i][j][r]);
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (consecutive linear ids
+// land on different XCDs, each with an L2 of its own).  xcd_contiguous() maps
+// a workgroup's linear id p < total to a logical id such that each XCD takes
+// a contiguous range of logical ids (XCD x gets the x-th eighth): work items
+// that share operands then run on one XCD and can share its L2.  A bijection
+// of [0, total).
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t p, int64_t total) {
+  constexpr int NXCD = 8;
+  const int64_t q = total / NXCD, r = total % NXCD;
+  const int64_t x = p % NXCD, slot = p / NXCD;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
+// Logical id lg < T * nent (T column tiles per batch entry, nent entries) to
+// (tile, entry): entry-major, or with grp > 1 group-major over groups of grp
+// consecutive entries, tile by tile within a group (the last group may be
+// short).  A bijection.
+__device__ __forceinline__ void tile_entry(int64_t lg, int64_t T, int64_t nent, int grp, int& tile, int64_t& entry) {
+  if (grp > 1) {
+    const int64_t g0 = lg / ((int64_t)grp * T) * grp;  // the group's first entry
+    const int64_t gl = min((int64_t)grp, nent - g0);
+    const int64_t r = lg - g0 * T;
+    tile = (int)(r / gl);
+    entry = g0 + r % gl;
+  } else {
+    tile = (int)(lg % T);
+    entry = lg / T;
+  }
+}
+
 // Split bf16 operands: x = s_0 + s_1 + ... + s_{NSL-1} + O(2^-8NSL |x|) with
 // each s_p the bf16 rounding of what the earlier slices leave (every
 // remainder is exact in FP32).
@@ -675,10 +708,16 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(GemmDesc d, int ksplit,
   __shared__ __attribute__((aligned(16))) bf16x8 sB[2][NSL][BN][BK / 8];  // [re, im][slice][n][k chunk]
 
   const int tilesN = (d.N + BN - 1) / BN;
-  const int kz = blockIdx.x % ksplit;
-  const int tile = blockIdx.x / ksplit;
+  int bx = blockIdx.x;
+  int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
+  if (d.grp > 1 && ksplit == 1) {  // grouped entries, each XCD a contiguous range
+    const int64_t nent = (int64_t)gridDim.y * gridDim.z;
+    tile_entry(xcd_contiguous((int64_t)blockIdx.x + (int64_t)gridDim.x * b, (int64_t)gridDim.x * nent), gridDim.x,
+               nent, d.grp, bx, b);
+  }
+  const int kz = bx % ksplit;
+  const int tile = bx / ksplit;
   const int tm = tile / tilesN, tn = tile % tilesN;
-  const int64_t b = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
   if (b >= d.batch) return;
   const int kbeg = kz * kchunk;
   const int kend = min(d.K, kbeg + kchunk);
@@ -811,19 +850,6 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(GemmDesc d, int ksplit,
         put<ATOMIC>(d, C, ro[i][r], co[j], (double)crr[i][j][r] - (double)cii[i][j][r], (double)cim[i][j][r]);
 }
 
-// Workgroups are dispatched to the eight XCDs in turn (consecutive linear ids
-// land on different XCDs, each with an L2 of its own).  xcd_contiguous() maps
-// a workgroup's linear id p < total to a logical id such that each XCD takes
-// a contiguous range of logical ids (XCD x gets the x-th eighth): work items
-// that share operands then run on one XCD and can share its L2.  A bijection
-// of [0, total).
-__device__ __forceinline__ int64_t xcd_contiguous(int64_t p, int64_t total) {
-  constexpr int NXCD = 8;
-  const int64_t q = total / NXCD, r = total % NXCD;
-  const int64_t x = p % NXCD, slot = p / NXCD;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
-}
-
 // ---------------------------------------------------------------------------
 // FP64 K-segmented product (the builds of t3 and lambda3 and the S product):
 // one 64 x 64 tile of C per workgroup, four waves of 32 x 32, complex products
@@ -863,10 +889,11 @@ __global__ __launch_bounds__(NT, 3) void zgemm_seg_f64_kernel(GemmDesc d) {
   // each XCD takes a contiguous range of (block, tile) pairs: the tiles of a
   // block share its A rows, and neighbouring blocks share B slices
   const int64_t by = (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y;
-  const int64_t lg = xcd_contiguous((int64_t)blockIdx.x + (int64_t)gridDim.x * by,
-                                    (int64_t)gridDim.x * gridDim.y * gridDim.z);
-  const int tx = (int)(lg % gridDim.x);
-  const int64_t b = lg / gridDim.x;
+  const int64_t nent = (int64_t)gridDim.y * gridDim.z;
+  const int64_t lg = xcd_contiguous((int64_t)blockIdx.x + (int64_t)gridDim.x * by, (int64_t)gridDim.x * nent);
+  int tx;
+  int64_t b;
+  tile_entry(lg, gridDim.x, nent, d.grp, tx, b);
   const int tm = tx / tilesN, tn = tx % tilesN;
   if (b >= d.batch) return;
   const int I = d.bl[4 * b], J = d.bl[4 * b + 1], K = d.bl[4 * b + 2], n = d.bl[4 * b + 3];

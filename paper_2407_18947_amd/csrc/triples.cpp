@@ -371,7 +371,8 @@ void Triples::fold_timing() {
 void Triples::free_windows() {
   for (auto* ws : {&rhs_windows_, &den_windows_}) {
     for (auto& w : *ws) {
-      for (int* p : {w.d_bl, w.d_part, w.d_owned, w.d_canon, w.d_slabs, w.d_orb, w.d_orb_owned})
+      for (int* p : {w.d_bl, w.d_part, w.d_owned, w.d_canon, w.d_slabs, w.d_orb, w.d_orb_owned, w.d_bk_t3,
+                     w.d_bk_l3, w.d_bk_own})
         if (p) (void)hipFree(p);
       for (Groups* gr : {&w.gJ, &w.gK})
         for (int* p : {gr->d_key, gr->d_start, gr->d_bl})
@@ -590,6 +591,28 @@ void Triples::upload(Window& w) {
     w.orb_owned = orbits(w.owned);
     put(&w.d_orb_owned, w.orb_owned);
   }
+  // The block tables of the build products, sorted so that neighbouring
+  // entries share the operand blocks of K and of J (t3) or I (lambda3, S):
+  // those 0.8-3 MB blocks then stay in an XCD's L2 cache for the hundreds of
+  // entries that read them instead of being fetched again for each entry.
+  auto sorted = [](const std::vector<int>& t, int p0, int p1, int p2) {
+    std::vector<std::array<int, 4>> x;
+    for (size_t e = 0; e < t.size(); e += 4) x.push_back({t[e], t[e + 1], t[e + 2], t[e + 3]});
+    std::stable_sort(x.begin(), x.end(), [&](const std::array<int, 4>& a, const std::array<int, 4>& b) {
+      return std::make_tuple(a[p0], a[p1], a[p2]) < std::make_tuple(b[p0], b[p1], b[p2]);
+    });
+    std::vector<int> out;
+    for (auto& q : x) out.insert(out.end(), q.begin(), q.end());
+    return out;
+  };
+  w.bk_t3 = sorted(w.bl, 2, 1, 0);
+  w.bk_l3 = sorted(w.bl, 2, 0, 1);
+  put(&w.d_bk_t3, w.bk_t3);
+  put(&w.d_bk_l3, w.bk_l3);
+  if (!w.owned.empty()) {
+    w.bk_own = sorted(w.owned, 2, 0, 1);
+    put(&w.d_bk_own, w.bk_own);
+  }
   RTCC3_HIP(hipMalloc(&w.d_bl, sizeof(int) * w.bl.size()));
   RTCC3_HIP(hipMemcpy(w.d_bl, w.bl.data(), sizeof(int) * w.bl.size(), hipMemcpyHostToDevice));
   RTCC3_HIP(hipMalloc(&w.d_part, sizeof(int) * w.part.size()));
@@ -745,7 +768,8 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
   // ---------------- t3 blocks
   {  // W[n][a][(b,c)] = sum_e t2[I][J][a][e] (ck|be)~[K][e][(b,c)]
      //              + sum_m -(mk|ai)~[K][I][a][m] t2[J][m][(b,c)]   (term 2 relabelled)
-    GemmDesc g = base(v, (int)v2, up16(v) + o, nw, bl, pr);
+    GemmDesc g = base(v, (int)v2, up16(v) + o, nw, w.d_bk_t3, pr);
+    g.grp = o;  // runs of o entries share K and J
     g.store = 1;
     g.nseg = 2;
     seg(g.seg[0], 0, v, t2, {(int64_t)o * v2, v2, 0, 0}, v, 1, gW1, {0, 0, v3, 0}, v2);
@@ -759,7 +783,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     set4(g.cC, 0, 0, 0, vb);
     const int64_t lA[2] = {lT2, lOOOV}, lB[2] = {lOVVV_, lT2};
     build_event(s);
-    prod_seg(e, g, blh, lA, lB, winlen, s);
+    prod_seg(e, g, w.bk_t3.data(), lA, lB, winlen, s);
     build_event(s);
     build_flop_ += 8.0 * nw * v * v2 * (v + o);
   }
@@ -783,7 +807,10 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));
     {  // terms 9, 10: S[n][c][(d,x)] = sum_b t2[J][K][c][b] (xI|db)~[I][b][(d,x)]
        //                          + sum_b t2[J][I][c][b] (dK|xb)~[K][b][(d,x)]   (one store-mode product)
-      GemmDesc g = base(v, (int)(o * v), up16(v) + v, cn, cbl, pr);
+      const int* sbl = pairwin ? w.d_bk_own : w.d_bk_l3;  // cbl sorted by (K, I, J)
+      const int* sblh = pairwin ? w.bk_own.data() : w.bk_l3.data();
+      GemmDesc g = base(v, (int)(o * v), up16(v) + v, cn, sbl, pr);
+      g.grp = o;  // runs of o entries share K and I
       g.store = 1;
       g.nseg = 2;
       const int64_t ov2 = (int64_t)o * v2, v2o = v2 * o;
@@ -796,7 +823,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
       const int64_t lS = (int64_t)max_nw_ * v2 * o;
       const int64_t lA[2] = {t2len, t2len}, lB[2] = {lOOVV, lOOVV};
       build_event(s2);  // same kernel as the builds: timed with them
-      prod_seg(e, g, cblh, lA, lB, lS, s2);
+      prod_seg(e, g, sblh, lA, lB, lS, s2);
       build_event(s2);
       build_flop_ += 8.0 * cn * v * (o * v) * (2 * v);
     }
@@ -808,7 +835,8 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
      //              + sum_d l2[J][K][a][d] -(ib|dc)~[I][d][(b,c)]                (relabelled)
      //              + sum_d l2[I][J][a][d] (2(db|kc) - (dc|kb))~[K][d][(b,c)]    (relabelled)
     const int k1 = up16(o), k2 = 2 * up16(o), k3 = 2 * up16(o) + up16(v);
-    GemmDesc g = base(v, (int)v2, k3 + v, nw, bl, pr);
+    GemmDesc g = base(v, (int)v2, k3 + v, nw, w.d_bk_l3, pr);
+    g.grp = o;  // runs of o entries share K and I
     g.store = 1;
     g.nseg = 4;
     const int64_t oo = (int64_t)o * o, ov2 = (int64_t)o * v2;
@@ -826,7 +854,7 @@ void Triples::window_pass(Engine& e, const Window& w, const cplx* y, bool rhs_te
     const int64_t lA[4] = {lLC, lLC, l2len, l2len}, lB[4] = {l2len, l2len, lOVVV_, lOVVV_};
     RTCC3_HIP(hipStreamWaitEvent(s2, ev_t3b_, 0));  // after the t3 build (a no-op when S went first)
     build_event(s2);
-    prod_seg(e, g, blh, lA, lB, winlen, s2);
+    prod_seg(e, g, w.bk_l3.data(), lA, lB, winlen, s2);
     build_event(s2);
     build_flop_ += 8.0 * nw * v * v2 * (2 * o + 2 * v);
     RTCC3_HIP(hipEventRecord(ev_l3b_, s2));

@@ -41,6 +41,10 @@ struct Window {
   Groups gJ, gK;              // contraction blocks grouped by J and by K
   std::vector<int> orb;       // bl, and owned, with the orderings of each occupied triple consecutive
   std::vector<int> orb_owned;
+  // bl sorted by (K, J, I) and by (K, I, J), and owned by (K, I, J), for the
+  // build products: neighbouring entries then share their largest operand
+  // blocks, which stay in the L2 cache for them
+  std::vector<int> bk_t3, bk_l3, bk_own;
   int* d_bl = nullptr;
   int* d_part = nullptr;
   int* d_owned = nullptr;
@@ -48,6 +52,9 @@ struct Window {
   int* d_slabs = nullptr;
   int* d_orb = nullptr;
   int* d_orb_owned = nullptr;
+  int* d_bk_t3 = nullptr;
+  int* d_bk_l3 = nullptr;
+  int* d_bk_own = nullptr;
 };
 
 class Triples {

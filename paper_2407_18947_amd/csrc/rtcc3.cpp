@@ -135,10 +135,14 @@ void rhs_impl(rtcc3_ctx* c, FieldRef E, const cplx* y, cplx* dy, const TermsOut&
   TriplesOut to;
   if (with_triples) {
     // the reverse sweep needs only the CCSD forward part and residual: it runs
-    // on the side stream beside the triples contractions (after the first
-    // lambda3 build, which itself follows them)
+    // on the side stream after the residual, beside the triples work
     to = c->tri->run(e, d, r, y, want_density, [&](hipEvent_t after) -> hipEvent_t {
-      RTCC3_HIP(hipStreamWaitEvent(c->side_stream, after, 0));
+      // With bf16 slices the builds are not bound by the matrix cores and the
+      // sweep starts as soon as the residual is done, beside them; with FP64
+      // or FP32 products it waits for the lambda3 build, so that the builds
+      // share the chip only with the memory-bound symmetrisation.
+      const bool early = !c->single_stream && (c->precision == RTCC3_BF16X3 || c->precision == RTCC3_BF16X2);
+      if (!early) RTCC3_HIP(hipStreamWaitEvent(c->side_stream, after, 0));
       e.stream = c->single_stream ? c->stream : c->side_stream;
       try {
         ccsd_backward(e, d, y, c->ones_o, r);

@@ -9,7 +9,7 @@ workload; the amplitudes live in HBM before the timed region starts.
 
   python bench.py [--steps K] [--warmup W] [--precision fp64|fp32] [--gpus 1]
 
-Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
 
 
 def _traffic(o: int, v: int, precision: str):
-    """The measured traffic if it applies to this build and workload, else None."""
+    """The measured traffic if it applies to these sources and this workload, else None."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2407_18947_amd", "csrc")
     for name, want in MEASURED_TRAFFIC["fingerprint"].items():
@@ -360,7 +360,7 @@ def main():
                          "(0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np

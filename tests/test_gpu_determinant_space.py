@@ -1,0 +1,87 @@
+"""The HIP path against the determinant-space construction directly.
+
+The GPU's CCSD part follows the same sequence of intermediates as the oracle,
+so parity with the oracle alone would not catch a mistake the two share.  Here
+the GPU's residuals and triples terms are compared, through the C ABI, with the
+second-quantized construction of tests/fci_harness.py, which shares no code with
+either:
+
+* Omega_mu = <mu| exp(-T) H(E) exp(T) |0> for singles and doubles
+  (the CCSD residual with the field coupling, Sec. 2.1 and 2.2.1);
+* T3|0> = -P3 [H~, T2]|0> / eps (the closed-form t3 of eq. cc3-t3-no-pert with
+  the T1-dressed, field-included Hamiltonian) and
+  X_mu = <mu| [H~, T3] |0> (eq. cc3-x1-exp and cc3-x2-exp).
+"""
+import numpy as np
+import pytest
+import torch
+
+from fci_harness import FockSpace, dress_integrals
+from oracle import rtcc3 as orc
+from paper_2407_18947_amd import _lib
+from paper_2407_18947_amd.inputs import make_system
+
+pytestmark = pytest.mark.gpu
+FIELD = np.array([0.01, -0.02, 0.03])
+
+
+def _state(o, v, seed, scale=0.1):
+    rng = np.random.default_rng(seed)
+
+    def rc(*sh):
+        return scale * (rng.normal(size=sh) + 1j * rng.normal(size=sh))
+
+    t1, l1 = rc(o, v), rc(o, v)
+    t2, l2 = rc(o, o, v, v), rc(o, o, v, v)
+    t2 = 0.5 * (t2 + t2.transpose(1, 0, 3, 2))
+    l2 = 0.5 * (l2 + l2.transpose(1, 0, 3, 2))
+    return t1, t2, l1, l2
+
+
+def _gpu_terms(s, y):
+    ctx = _lib.Context(s, _lib.RTCC3_FP64)
+    yd = torch.tensor(y, dtype=torch.complex128, device="cuda")
+    td = torch.zeros(ctx.terms_size(), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    _lib.rtcc3_rhs_terms(ctx.ctx, FIELD, yd, td, 1)
+    out = ctx.split_terms(td.cpu().numpy())
+    ctx.close()
+    return out
+
+
+def _close(name, a, b, tol=1e-11):
+    err = np.abs(np.asarray(a) - np.asarray(b)).max()
+    scale = np.abs(b).max()
+    assert err <= tol * scale + 1e-15, f"{name}: max|diff| = {err:.3e} (largest element {scale:.3e})"
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (3, 3)])
+def test_gpu_residual_and_triples_equal_determinant_space(o, v):
+    print(f"determinant space o={o} v={v}", flush=True)
+    s = make_system(o, v, seed=11)
+    m = orc.Model.from_system(s)
+    t1, t2, l1, l2 = _state(o, v, 3)
+    y = orc.pack(*[torch.tensor(x) for x in (t1, t2, l1, l2)]).numpy()
+    g = _gpu_terms(s, y)
+
+    fs = FockSpace(o, v)
+    h = m.h(FIELD).numpy().astype(complex)  # h0 - mu.E (its sign and h0 are pinned on the CPU)
+    gbare = np.einsum("Ppq,Prs->pqrs", s.B, s.B).astype(complex)
+    H = fs.hamiltonian(h, gbare)
+    T = fs.T1(t1) + fs.T2(t2)
+    hbar = fs.expm_apply(T, H @ fs.expm_apply(T, fs.ref), sign=-1.0)
+    w1, w2 = fs.coefficients(hbar)
+    _close("R1", g["R1"], w1)
+    _close("R2", g["R2"], w2)
+
+    ht, gt = dress_integrals(o, v, t1, h, s.B)
+    Hd = fs.hamiltonian(ht, gt)
+    T2 = fs.T2(t2)
+    comm = Hd @ (T2 @ fs.ref) - T2 @ (Hd @ fs.ref)
+    den = fs.energy_denominators(s.eps)
+    mask = fs.rank == 3
+    t3s = np.zeros(fs.dim, complex)
+    t3s[mask] = -comm[mask] / den[mask]
+    x1, x2 = fs.coefficients(Hd @ t3s)
+    _close("X1", g["X1"], x1)
+    _close("X2", g["X2"], x2)

@@ -10,8 +10,18 @@ either:
   (the CCSD residual with the field coupling, Sec. 2.1 and 2.2.1);
 * T3|0> = -P3 [H~, T2]|0> / eps (the closed-form t3 of eq. cc3-t3-no-pert with
   the T1-dressed, field-included Hamiltonian) and
-  X_mu = <mu| [H~, T3] |0> (eq. cc3-x1-exp and cc3-x2-exp).
+  X_mu = <mu| [H~, T3] |0> (eq. cc3-x1-exp and cc3-x2-exp);
+* the Lambda residuals as derivatives of the CCSD Lagrangian
+  L = <0|(1 + Lambda) exp(-T) H exp(T)|0> with respect to the amplitudes,
+  dL/dt_mu = <0|(1 + Lambda) exp(-T) [H, tau_mu] exp(T)|0> (the doubles divided
+  by the weight 1/2 of l2 in the Lagrangian);
+* the dipole from the densities (Sec. 2.2.3): the CCSD part as the bra-ket
+  density <0|(1 + Lambda) exp(-T) E_pq exp(T)|0> with the bare dipole
+  integrals, the triples part (eq. cc3-dij and the two after it, with lambda3
+  from stationarity, eq. cc3-l3) with the T1-transformed ones.
 """
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -23,6 +33,7 @@ from paper_2407_18947_amd.inputs import make_system
 
 pytestmark = pytest.mark.gpu
 FIELD = np.array([0.01, -0.02, 0.03])
+C2 = 0.5  # weight of l2 in the Lagrangian and in the bra <0|(1 + Lambda)
 
 
 def _state(o, v, seed, scale=0.1):
@@ -61,7 +72,7 @@ def test_gpu_residual_and_triples_equal_determinant_space(o, v):
     s = make_system(o, v, seed=11)
     m = orc.Model.from_system(s)
     t1, t2, l1, l2 = _state(o, v, 3)
-    y = orc.pack(*[torch.tensor(x) for x in (t1, t2, l1, l2)]).numpy()
+    y = np.concatenate([x.ravel() for x in (t1, t2, l1, l2)])  # the state layout of the C ABI
     g = _gpu_terms(s, y)
 
     fs = FockSpace(o, v)
@@ -85,3 +96,48 @@ def test_gpu_residual_and_triples_equal_determinant_space(o, v):
     x1, x2 = fs.coefficients(Hd @ t3s)
     _close("X1", g["X1"], x1)
     _close("X2", g["X2"], x2)
+
+    # Lambda residuals: derivatives of the CCSD Lagrangian
+    psi = fs.expm_apply(T, fs.ref)
+    left = fs.expm_apply(T.T.tocsr(), fs.ref + fs.bra_from_lambda(l1, l2, C2), sign=-1.0)
+    hpsi = H @ psi
+
+    def dl(tau):
+        return left @ (H @ (tau @ psi)) - left @ (tau @ hpsi)
+
+    G1 = np.zeros((o, v), complex)
+    for i, a in itertools.product(range(o), range(v)):
+        e = np.zeros((o, v), complex)
+        e[i, a] = 1.0
+        G1[i, a] = dl(fs.T1(e))
+    G2 = np.zeros((o, o, v, v), complex)
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        e = np.zeros((o, o, v, v), complex)
+        e[i, j, a, b] = 1.0
+        G2[i, j, a, b] = dl(fs.T2(e)) / C2
+    _close("G1", g["G1"], G1)
+    _close("G2", g["G2"], G2)
+
+    # dipole: CCSD bra-ket density (bare integrals) + triples density (T1-transformed integrals)
+    nn = o + v
+    Db = np.array([[left @ (fs.E(p, q) @ psi) for q in range(nn)] for p in range(nn)])
+    bH = Hd.T @ fs.bra_from_lambda(l1, l2, C2)
+    l3b = np.zeros(fs.dim, complex)
+    l3b[mask] = -bH[mask] / den[mask]
+    b2 = fs.bra_from_lambda(0 * l1, l2, C2)
+    c3 = l3b @ t3s
+    DT = np.zeros((nn, nn), complex)
+    for p in range(nn):
+        for q in range(nn):
+            Ep = fs.E(p, q)
+            val = b2 @ (Ep @ t3s) + l3b @ (Ep @ t3s)
+            if p == q and p < o:
+                val -= 2.0 * c3
+            x = T2 @ (T2 @ (Ep @ fs.ref)) - 2 * (T2 @ (Ep @ (T2 @ fs.ref))) + Ep @ (T2 @ (T2 @ fs.ref))
+            DT[p, q] = val + 0.5 * (l3b @ x)
+    tm = np.zeros((nn, nn), complex)
+    tm[o:, :o] = t1.T
+    Xf, Yf = np.eye(nn) - tm, np.eye(nn) + tm  # h~ = X h Y
+    mus = s.mu.astype(complex)
+    mu = np.array([np.sum(Db * mus[x]) + np.sum(DT * (Xf @ mus[x] @ Yf)) for x in range(3)])
+    _close("mu", g["mu"], mu)

@@ -18,7 +18,10 @@ either:
 * the dipole from the densities (Sec. 2.2.3): the CCSD part as the bra-ket
   density <0|(1 + Lambda) exp(-T) E_pq exp(T)|0> with the bare dipole
   integrals, the triples part (eq. cc3-dij and the two after it, with lambda3
-  from stationarity, eq. cc3-l3) with the T1-transformed ones.
+  from stationarity, eq. cc3-l3) with the T1-transformed ones;
+* Y1 and Y2 (eq. cc3-y1-exp and cc3-y2-exp) as the amplitude derivatives of the
+  triples part of the Lagrangian, <0|(Lambda1 + Lambda2) H~ T3|0> with T3 at its
+  closed form, by four-point differences of the determinant-space construction.
 """
 import itertools
 
@@ -141,3 +144,47 @@ def test_gpu_residual_and_triples_equal_determinant_space(o, v):
     mus = s.mu.astype(complex)
     mu = np.array([np.sum(Db * mus[x]) + np.sum(DT * (Xf @ mus[x] @ Yf)) for x in range(3)])
     _close("mu", g["mu"], mu)
+
+
+def test_gpu_triples_lambda_terms_equal_determinant_space_derivatives():
+    o, v = 2, 3
+    print(f"determinant space Y1, Y2 o={o} v={v}", flush=True)
+    s = make_system(o, v, seed=11)
+    m = orc.Model.from_system(s)
+    t1, t2, l1, l2 = _state(o, v, 3)
+    y = np.concatenate([x.ravel() for x in (t1, t2, l1, l2)])
+    g = _gpu_terms(s, y)
+
+    fs = FockSpace(o, v)
+    h = m.h(FIELD).numpy().astype(complex)
+    den = fs.energy_denominators(s.eps)
+    mask = fs.rank == 3
+    bra = fs.bra_from_lambda(l1, l2, C2)
+
+    def l3(t1x, t2x):  # <0|(Lambda1 + Lambda2) H~ T3|0>, T3|0> = -P3 [H~, T2]|0> / eps
+        ht, gt = dress_integrals(o, v, t1x, h, s.B)
+        Hd = fs.hamiltonian(ht, gt)
+        T2 = fs.T2(t2x)
+        comm = Hd @ (T2 @ fs.ref) - T2 @ (Hd @ fs.ref)
+        t3s = np.zeros(fs.dim, complex)
+        t3s[mask] = -comm[mask] / den[mask]
+        return bra @ (Hd @ t3s)
+
+    hh = 1e-3  # four-point differences: error O(hh^4) of the smooth, holomorphic l3
+
+    def d4(f, x, e):
+        return (8 * (f(x + hh * e) - f(x - hh * e)) - (f(x + 2 * hh * e) - f(x - 2 * hh * e))) / (12 * hh)
+
+    Y1 = np.zeros((o, v), complex)
+    for i, a in itertools.product(range(o), range(v)):
+        e = np.zeros((o, v))
+        e[i, a] = 1.0
+        Y1[i, a] = d4(lambda x: l3(x, t2), t1, e)
+    Y2 = np.zeros((o, o, v, v), complex)
+    for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
+        e = np.zeros((o, o, v, v))
+        e[i, j, a, b] = 1.0
+        Y2[i, j, a, b] = d4(lambda x: l3(t1, x), t2, e)
+    Y2 = 0.5 * (Y2 + Y2.transpose(1, 0, 3, 2)) / C2
+    _close("Y1", g["Y1"], Y1, 1e-9)
+    _close("Y2", g["Y2"], Y2, 1e-9)
